@@ -1,0 +1,134 @@
+"""The synthetic workloads (geometry, wavenumber, incident fields), seeded.
+
+Every workload here is built from closed-form generating curves and seeded
+numpy PCG64 streams; nothing is read from disk.  The paper's own experiments
+(Sec. 6) do not publish their random placements, so these stand in for them
+with the same kinds of bodies (spheres, prolate spheroids, bowl cavities),
+sizes in wavelengths and separations.
+"""
+from __future__ import annotations
+
+import dataclasses
+import itertools
+import math
+
+import numpy as np
+
+from . import geometry as geo
+
+
+@dataclasses.dataclass
+class BodySpec:
+    contour: geo.Contour
+    centre: np.ndarray   # (3,)
+    rot: np.ndarray      # (3, 3)
+    M: int               # Fourier cutoff; N_F = 2M + 1
+
+    @property
+    def n_nodes(self) -> int:
+        return self.contour.NG * (2 * self.M + 1)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    kappa: float
+    eta: float
+    bodies: list
+    dirs: np.ndarray     # (nrhs, 3) plane-wave directions
+    note: str = ""
+
+    @property
+    def N(self) -> int:
+        return sum(b.n_nodes for b in self.bodies)
+
+    @property
+    def pairs(self) -> int:
+        """Inter-body (target, source) pairs of one operator application."""
+        n = np.array([b.n_nodes for b in self.bodies], dtype=np.int64)
+        return int(n.sum() ** 2 - (n * n).sum())
+
+
+def two_spheres(n_panels=10, p=10, M=20, kappa=math.pi) -> Workload:
+    """Two unit spheres at (+-1.5, 0, 0), kappa = pi, eta = kappa, d = +z."""
+    c = geo.sphere(1.0, n_panels, p)
+    bodies = [BodySpec(c, np.array([s * 1.5, 0.0, 0.0]), np.eye(3), M) for s in (-1.0, 1.0)]
+    return Workload("two_spheres_k1pi", kappa, kappa, bodies, np.array([[0.0, 0.0, 1.0]]),
+                    "2 unit spheres, 10x10 Gauss nodes, |m|<=20, N=8200")
+
+
+def sphere_lattice(n_panels=20, p=10, M=40, kappa=4 * math.pi, spacing=3.0, per_side=3) -> Workload:
+    """27 unit spheres on a 3x3x3 lattice (spacing 3), kappa = 4 pi, d = (1,1,1)/sqrt3."""
+    c = geo.sphere(1.0, n_panels, p)
+    offs = (np.arange(per_side) - 0.5 * (per_side - 1)) * spacing
+    bodies = [BodySpec(c, np.array(xyz, dtype=np.float64), np.eye(3), M)
+              for xyz in itertools.product(offs, offs, offs)]
+    d = np.ones((1, 3)) / math.sqrt(3.0)
+    return Workload("sphere_lattice_27_k4pi", kappa, kappa, bodies, d,
+                    "27 unit spheres 3x3x3 spacing 3, 20x10 Gauss nodes, |m|<=40, N=437400")
+
+
+def mixed_bodies(seed=3, kappa=2 * math.pi, n_dirs=64, disc_kappa=None) -> Workload:
+    """8 bodies in a 12^3 box, min gap 1: 3 spheres, 3 prolate 1x1x2, 2 bowls.
+
+    ``disc_kappa`` sets the discretisation wavenumber (panels at 10 nodes per
+    wavelength and the mode cutoff); it defaults to ``kappa``.
+    """
+    rng = np.random.default_rng(seed)
+    kd = kappa if disc_kappa is None else disc_kappa
+    shapes = ([geo.sphere_at_wavelength(kd)] * 3 + [geo.prolate_at_wavelength(kd)] * 3
+              + [geo.bowl_at_wavelength(kd)] * 2)
+    centres = geo.place_bodies([s.bound_radius for s in shapes], 12.0, 1.0, rng)
+    bodies = []
+    for s, c in zip(shapes, centres):
+        rot = np.eye(3) if s.kind == "sphere" else geo.random_rotation(rng)
+        bodies.append(BodySpec(s, c, rot, geo.modes_for(kd, s.r_max)))
+    return Workload(f"mixed8_seed{seed}", kappa, kappa, bodies, geo.fibonacci_directions(n_dirs),
+                    "3 spheres, 3 prolate 1x1x2, 2 bowls in 12^3, gap 1")
+
+
+def mixed_many(seed=5, kappa=4 * math.pi, n_bodies=64, box=24.0, gap=0.5, n_dirs=16,
+               p=10) -> Workload:
+    """64 mixed bodies (spheres, prolate aspect 1-3, bowls) in a 24^3 box."""
+    rng = np.random.default_rng(seed)
+    shapes = []
+    sph = geo.sphere(1.0, 20, p)
+    bowl = geo.bowl_at_wavelength(kappa)
+    for b in range(n_bodies):
+        kind = b % 3
+        if kind == 0:
+            shapes.append(sph)
+        elif kind == 1:
+            c = float(rng.uniform(1.0, 3.0))
+            npan = max(20, geo.panels_for_wavelength(geo._prolate_length(1.0, c), kappa))
+            shapes.append(geo.prolate(1.0, c, npan, p))
+        else:
+            shapes.append(bowl)
+    centres = geo.place_bodies([s.bound_radius for s in shapes], box, gap, rng)
+    bodies = []
+    for s, c in zip(shapes, centres):
+        rot = np.eye(3) if s.kind == "sphere" else geo.random_rotation(rng)
+        bodies.append(BodySpec(s, c, rot, geo.modes_for(kappa, s.r_max)))
+    return Workload(f"mixed{n_bodies}_seed{seed}", kappa, kappa, bodies,
+                    geo.fibonacci_directions(n_dirs), "64 mixed bodies in 24^3, gap 0.5")
+
+
+def single_sphere(a=1.0, n_panels=10, p=10, M=20, kappa=math.pi) -> Workload:
+    c = geo.sphere(a, n_panels, p)
+    return Workload("single_sphere", kappa, kappa, [BodySpec(c, np.zeros(3), np.eye(3), M)],
+                    np.array([[0.0, 0.0, 1.0]]))
+
+
+def point_sources(wl: Workload, seed: int = 11):
+    """One seeded point source strictly inside each body (global frame)."""
+    rng = np.random.default_rng(seed)
+    return np.array([b.centre + b.rot @ geo.interior_point(b.contour, rng) for b in wl.bodies])
+
+
+def exterior_targets(wl: Workload, n: int = 10, seed: int = 12) -> np.ndarray:
+    """n seeded targets on a sphere three wavelengths outside all bodies."""
+    rng = np.random.default_rng(seed)
+    cen = np.mean([b.centre for b in wl.bodies], axis=0)
+    rad = max(np.linalg.norm(b.centre - cen) + b.contour.bound_radius for b in wl.bodies)
+    lam = 2 * math.pi / wl.kappa if wl.kappa > 0 else 1.0
+    return geo.sphere_targets(n, rad + 3 * lam, cen, rng)
