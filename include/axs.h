@@ -1,0 +1,188 @@
+/*
+ * axs.h -- C ABI of the multibody acoustic scattering solver for bodies of
+ * revolution (Hao, Martinsson, Young, arXiv 1406.0236), built for AMD MI355X.
+ *
+ * Problem (Sec. 2, eq. "basic"): sound-soft exterior Helmholtz problem
+ *     -Lap u - kappa^2 u = 0 outside Gamma,  u = -v on Gamma,  radiating,
+ * written as the combined-field BIE (eq. "intHelm2")
+ *     1/2 sigma(x) + int_Gamma G(x, x') sigma(x') dA(x') = -v(x),
+ *     G = d phi / d n(x') + i eta phi,   phi = exp(i kappa R) / (4 pi R)
+ * (the paper fixes eta = kappa; eta is a parameter here).
+ * Discretisation (Sec. 3): per body, a composite Gauss-Legendre rule on the
+ * generating curve times the trapezoidal rule in the azimuth; Nystrom
+ * matrix A = D + B with D = blockdiag(F* A~ F) (modal matrices, eq. "FAF")
+ * and B the naive-rule inter-body blocks (Sec. 3.3).
+ * Solver (Sec. 4, eq. "precond"): GMRES on  sigma + D^{-1} B sigma = -D^{-1} v.
+ *
+ * Global conventions
+ *  - Node order: body (in build order), contour node i (panel-major), azimuth
+ *    l (theta_l = 2 pi l / N_F, N_F = 2M + 1).  N = sum of N_G N_F over bodies.
+ *  - Device vectors are complex128 interleaved (re, im), laid out [nrhs][N]
+ *    row-major, in memory the caller owns (e.g. torch tensors).  The library
+ *    never frees, retains or resizes caller memory.
+ *  - Host arrays are copied during the call; the caller keeps ownership.
+ *  - All device work is ordered on the stream given to axs_create; calls
+ *    return once the work is enqueued unless stated otherwise.  axs_solve and
+ *    axs_precompute_scattering synchronise that stream.
+ *  - Every entry point returns an axs_status; a failed call leaves a message
+ *    readable through axs_last_error.  Nothing crosses the ABI as an
+ *    exception.  A context is not thread-safe; distinct contexts are
+ *    independent.
+ */
+#ifndef AXS_H
+#define AXS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct axs_ctx axs_ctx;
+typedef int32_t axs_status;
+
+enum {
+    AXS_OK = 0,
+    AXS_NOT_CONVERGED = 1,   /* soft: solve stopped at max_iters above tol */
+    AXS_EINVAL = -1,         /* invalid argument (message says which) */
+    AXS_EHIP = -2,           /* a HIP runtime call failed */
+    AXS_ENOMEM = -3,         /* device allocation failed */
+    AXS_ESTATE = -4,         /* call out of order (e.g. matvec before precompute) */
+    AXS_ENONFINITE = -5      /* NaN/Inf in an input or in a residual */
+};
+
+enum {
+    AXS_FP64 = 0,            /* every step of the operator in FP64 */
+    AXS_FP32 = 1             /* inter-body sum, DFTs and modal applies in FP32,
+                                input/output vectors still complex128 */
+};
+
+/* Optional device allocator supplied by the caller (e.g. a framework's
+ * caching allocator).  alloc returns NULL on failure.  If both are NULL the
+ * library uses hipMalloc/hipFree. */
+typedef void *(*axs_alloc_fn)(size_t bytes, void *user);
+typedef void (*axs_free_fn)(void *ptr, void *user);
+
+/* Create a context on HIP device `device`, ordering all work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). */
+axs_status axs_create(axs_ctx **out, int device, void *hip_stream, axs_alloc_fn alloc,
+                      axs_free_fn free_fn, void *user);
+/* Release every device buffer the context owns, then the context. */
+axs_status axs_destroy(axs_ctx *ctx);
+/* Message of the last failed call on ctx ("" if none); valid until the next call. */
+const char *axs_last_error(const axs_ctx *ctx);
+
+/* Add one body of revolution (Sec. 3.2 discretisation).
+ *  rz[2*NG], drz[2*NG] : (r, z) and d(r, z)/ds at the NG = n_panels * p contour
+ *      nodes, panel-major; s in [-1, 1] is the panel parameter and the nodes
+ *      sit at the p-point Gauss-Legendre nodes of each panel.  The curve runs
+ *      from an axis point at the top to one at the bottom, so the outward
+ *      normal is (-z', r') / |gamma'|.  r must be > 0 at every node.
+ *  gw[NG] : the Gauss-Legendre weight of each node on [-1, 1]; checked against
+ *      the library's own p-point rule (AXS_EINVAL if they differ).
+ *  kappa >= 0, eta : wavenumber and coupling; all bodies of a context must
+ *      share them (AXS_EINVAL otherwise).
+ *  M >= 0 : Fourier cutoff; the body has N_F = 2M + 1 azimuthal nodes.
+ *  centre[3], rot[9] (row-major, orthonormal) : x = centre + rot (r cos th, r sin th, z).
+ *  Bodies with identical (rz, drz, gw, p, M) share their scattering matrices.
+ *  Bodies whose bounding balls (about `centre`) overlap are rejected
+ *  (AXS_EINVAL): Sec. 3.3 leaves touching or overlapping scatterers out.
+ *  On success *body_id is the body's index (build order). */
+axs_status axs_build_body(axs_ctx *ctx, const double *rz, const double *drz, const double *gw,
+                          int n_panels, int p, double kappa, double eta, int M,
+                          const double centre[3], const double rot[9], int *body_id);
+
+/* Build the modal matrices A~_m (m = 0..M) of every distinct shape on the
+ * device in FP64 -- modal kernels, near-panel product integration, 1/2 I --
+ * and store S_m = A~_m^{-1} (Sec. 3.2, eqs. "FAF", "singleinverse";
+ * A~_{-m} = A~_m).  Also lays out the global node arrays.  Synchronous.
+ * After it, axs_build_body returns AXS_ESTATE. */
+axs_status axs_precompute_scattering(axs_ctx *ctx);
+
+/* Number of unknowns N (valid after the first axs_build_body). */
+axs_status axs_num_unknowns(const axs_ctx *ctx, int64_t *N);
+
+/* Host copy of the node geometry, [N][7] = (x, y, z, nx, ny, nz, w) with w the
+ * surface quadrature weight (2 pi / N_F) r |gamma'| w_gauss.  After precompute. */
+axs_status axs_node_geometry(axs_ctx *ctx, double *xyz_n_w);
+
+/* Device copy of the modal matrices of body `body_id`'s shape, complex128
+ * [M+1][NG][NG] row-major: which = 0 gives A~_m, which = 1 gives S_m. */
+axs_status axs_modal_matrices(axs_ctx *ctx, int body_id, int which, void *out);
+
+/* y = sigma + D^{-1} B sigma  (eq. "precond") for nrhs vectors.
+ * sigma, y : device complex128 [nrhs][N]; they must not overlap.
+ * precision : AXS_FP64 or AXS_FP32 (see above). */
+axs_status axs_apply_matvec(axs_ctx *ctx, const void *sigma, void *y, int nrhs, int precision);
+
+/* Building blocks of the operator, same layouts as axs_apply_matvec:
+ *   axs_apply_interbody : y = B sigma        (inter-body sum alone)
+ *   axs_apply_precond   : y = D^{-1} x       (per-body DFT, S_m applies, inverse DFT) */
+axs_status axs_apply_interbody(axs_ctx *ctx, const void *sigma, void *y, int nrhs, int precision);
+axs_status axs_apply_precond(axs_ctx *ctx, const void *x, void *y, int nrhs, int precision);
+
+typedef struct {
+    int32_t iterations;       /* outer iterations (FP64 operator applications) */
+    int32_t inner_iterations; /* inner (FP32 operator) iterations, mixed mode */
+    double rel_residual;      /* final FP64 || b - (I + D^-1 B) sigma || / || b ||, b = -D^-1 v */
+    double seconds;           /* wall time of the solve on the host clock */
+    int32_t used_warm_start;  /* 1 if sigma0 was kept as the initial guess */
+    int32_t converged;
+} axs_solve_info;
+
+enum {
+    AXS_SOLVE_FP64 = 0,       /* GMRES, FP64 operator */
+    AXS_SOLVE_MIXED = 1       /* flexible GMRES with FP64 operator and residual, whose
+                                 preconditioner is an inner GMRES on the FP32 operator */
+};
+
+/* Solve (eq. "precond")  sigma + D^{-1} B sigma = -D^{-1} v  for nrhs incident fields.
+ *  incident : device complex128 [nrhs][N], v at the nodes.
+ *  sigma0   : device complex128 [nrhs][N] initial guess, or NULL for zero.  A guess
+ *             whose FP64 residual is not below || b || is replaced by zero.
+ *  sigma    : device complex128 [nrhs][N], the result.
+ *  mode     : AXS_SOLVE_FP64 or AXS_SOLVE_MIXED.
+ *  tol      : stop when every right-hand side has relative FP64 residual <= tol.
+ *  max_iters: cap on outer iterations (Krylov dimension; no restart).
+ *  info     : host array [nrhs].  Returns AXS_NOT_CONVERGED if any rhs missed tol. */
+axs_status axs_solve(axs_ctx *ctx, const void *incident, const void *sigma0, void *sigma,
+                     int nrhs, int mode, double tol, int max_iters, axs_solve_info *info);
+
+/* v[c][i] = exp(i kappa d_c . x_i) for nrhs unit directions dirs[nrhs][3] (host). */
+axs_status axs_incident_plane_waves(axs_ctx *ctx, const double *dirs, int nrhs, void *v);
+
+/* v[i] = sum_s amp_s exp(i kappa |x_i - y_s|) / (4 pi |x_i - y_s|): the field of
+ * ns point sources y_s (host [ns][3]) with complex amplitudes amp (host [ns][2]);
+ * one right-hand side. */
+axs_status axs_incident_point_sources(axs_ctx *ctx, const double *src, const double *amp,
+                                      int ns, void *v);
+
+/* u[c][t] = sum_j G(x_t, x_j) w_j sigma[c][j] at nt targets tgt (host [nt][3]),
+ * every body included (eq. "intHelm1" with the surface rule); FP64.
+ * sigma : device [nrhs][N]; u : device complex128 [nrhs][nt]. */
+axs_status axs_eval_field(axs_ctx *ctx, const void *sigma, int nrhs, const double *tgt, int nt,
+                          void *u);
+
+/* Far-field pattern u_inf(xh) with u ~ e^{i kappa |x|}/|x| u_inf:
+ * u_inf = (1/4pi) sum_j (-i kappa xh.n_j + i eta) e^{-i kappa xh.x_j} w_j sigma_j.
+ * xhat host [nd][3]; out device complex128 [nrhs][nd]. */
+axs_status axs_far_field(axs_ctx *ctx, const void *sigma, int nrhs, const double *xhat, int nd,
+                         void *out);
+
+/* Kernel timing of the last axs_apply_* call on the context's stream (HIP events
+ * around each stage), milliseconds: [0] inter-body sum, [1] forward DFT,
+ * [2] modal applies, [3] inverse DFT (+ identity), [4] total.
+ * Only filled when timing was enabled with axs_set_timing(ctx, 1). */
+axs_status axs_set_timing(axs_ctx *ctx, int enable);
+axs_status axs_last_timing(axs_ctx *ctx, double ms[5]);
+
+/* Inter-body sum launch shape (targets per thread, threads per block, source
+ * splits); 0 = library default.  Used by the autotuner. */
+axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int targets_per_thread,
+                                    int block, int splits);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AXS_H */

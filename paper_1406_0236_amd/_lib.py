@@ -1,0 +1,259 @@
+"""ctypes binding of libaxs.so (include/axs.h).  Argument marshalling only: every
+step of the computation runs in the HIP library.  Device vectors are torch
+complex128 tensors of shape (nrhs, N); PyTorch supplies device memory (through
+its caching allocator) and the stream."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaxs.so")
+
+AXS_OK, AXS_NOT_CONVERGED = 0, 1
+FP64, FP32 = 0, 1
+SOLVE_FP64, SOLVE_MIXED = 0, 1
+_STATUS = {0: "AXS_OK", 1: "AXS_NOT_CONVERGED", -1: "AXS_EINVAL", -2: "AXS_EHIP", -3: "AXS_ENOMEM",
+           -4: "AXS_ESTATE", -5: "AXS_ENONFINITE"}
+
+_lib = None
+
+
+class AxsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("inner_iterations", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("used_warm_start", ctypes.c_int32), ("converged", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "axs_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p, ALLOC_FN,
+                                    FREE_FN, ctypes.c_void_p]),
+    "axs_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "axs_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "axs_build_body": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
+    "axs_precompute_scattering": (ctypes.c_int32, [ctypes.c_void_p]),
+    "axs_num_unknowns": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "axs_node_geometry": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "axs_modal_matrices": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "axs_apply_matvec": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                          ctypes.c_int]),
+    "axs_apply_interbody": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                             ctypes.c_int]),
+    "axs_apply_precond": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_int]),
+    "axs_solve": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.POINTER(SolveInfo)]),
+    "axs_incident_plane_waves": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "axs_incident_point_sources": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                                    ctypes.c_void_p]),
+    "axs_eval_field": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_int, ctypes.c_void_p]),
+    "axs_far_field": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_int, ctypes.c_void_p]),
+    "axs_set_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int]),
+    "axs_last_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "axs_set_interbody_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_int]),
+}
+
+
+def load():
+    """Load libaxs.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "(the HIP library is required, there is no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """One solver context on one GPU (see include/axs.h for the semantics)."""
+
+    def __init__(self, device: int = 0, use_torch_allocator: bool = True):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        self.device = device
+        self.stream = torch.cuda.current_stream(device)
+        self._cb = None
+        alloc, free = ALLOC_FN(0), FREE_FN(0)
+        if use_torch_allocator:
+            stream = self.stream
+
+            def _alloc(nbytes, _user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+                except Exception:
+                    return None
+
+            def _free(p, _user):
+                torch.cuda.caching_allocator_delete(p)
+            alloc, free = ALLOC_FN(_alloc), FREE_FN(_free)
+            self._cb = (alloc, free)
+        h = ctypes.c_void_p()
+        st = self.lib.axs_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream), alloc, free, None)
+        if st != AXS_OK:
+            raise AxsError(st, "axs_create failed")
+        self.h = h
+        self.N = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.axs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, soft_ok=False):
+        if st == AXS_OK or (soft_ok and st == AXS_NOT_CONVERGED):
+            return st
+        raise AxsError(st, self.lib.axs_last_error(self.h).decode())
+
+    def _vec(self, t, nrhs=None):
+        torch = self._torch
+        assert t.dtype == torch.complex128 and t.is_cuda and t.is_contiguous(), "complex128 contiguous cuda tensor"
+        assert t.dim() == 2 and t.shape[1] == self.N, f"expected (nrhs, {self.N})"
+        return ctypes.c_void_p(t.data_ptr()), t.shape[0]
+
+    def _empty(self, nrhs, n=None):
+        torch = self._torch
+        return torch.empty((nrhs, self.N if n is None else n), dtype=torch.complex128, device=f"cuda:{self.device}")
+
+    # -- setup ------------------------------------------------------------------
+    def build_body(self, rz, drz, gw, n_panels, p, kappa, eta, M, centre, rot) -> int:
+        rz = np.ascontiguousarray(rz, dtype=np.float64)
+        drz = np.ascontiguousarray(drz, dtype=np.float64)
+        gw = np.ascontiguousarray(gw, dtype=np.float64)
+        centre = np.ascontiguousarray(centre, dtype=np.float64)
+        rot = np.ascontiguousarray(rot, dtype=np.float64)
+        bid = ctypes.c_int()
+        self._check(self.lib.axs_build_body(self.h, _ptr(rz), _ptr(drz), _ptr(gw), int(n_panels), int(p),
+                                            float(kappa), float(eta), int(M), _ptr(centre), _ptr(rot),
+                                            ctypes.byref(bid)))
+        n = ctypes.c_int64()
+        self.lib.axs_num_unknowns(self.h, ctypes.byref(n))
+        self.N = n.value
+        return bid.value
+
+    def add_workload(self, wl):
+        for b in wl.bodies:
+            c = b.contour
+            self.build_body(c.rz, c.drz, c.gw, c.n_panels, c.p, wl.kappa, wl.eta, b.M, b.centre, b.rot)
+        return self
+
+    def precompute_scattering(self):
+        self._check(self.lib.axs_precompute_scattering(self.h))
+
+    def node_geometry(self) -> np.ndarray:
+        out = np.empty((self.N, 7))
+        self._check(self.lib.axs_node_geometry(self.h, _ptr(out)))
+        return out
+
+    def modal_matrices(self, body: int, which: int = 1, M: int = None, NG: int = None):
+        """A~_m (which=0) or S_m (which=1) of body's shape as complex128 (M+1, NG, NG)."""
+        out = self._torch.empty((M + 1, NG, NG), dtype=self._torch.complex128, device=f"cuda:{self.device}")
+        self._check(self.lib.axs_modal_matrices(self.h, int(body), int(which), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    # -- operators ----------------------------------------------------------------
+    def _apply(self, fn, x, precision, out):
+        px, nrhs = self._vec(x)
+        y = self._empty(nrhs) if out is None else out
+        py, _ = self._vec(y)
+        self._check(fn(self.h, px, py, nrhs, precision))
+        return y
+
+    def apply_matvec(self, sigma, precision=FP64, out=None):
+        return self._apply(self.lib.axs_apply_matvec, sigma, precision, out)
+
+    def apply_interbody(self, sigma, precision=FP64, out=None):
+        return self._apply(self.lib.axs_apply_interbody, sigma, precision, out)
+
+    def apply_precond(self, x, precision=FP64, out=None):
+        return self._apply(self.lib.axs_apply_precond, x, precision, out)
+
+    def solve(self, incident, sigma0=None, mode=SOLVE_FP64, tol=1e-7, max_iters=200, out=None):
+        pv, nrhs = self._vec(incident)
+        p0 = self._vec(sigma0)[0] if sigma0 is not None else None
+        sig = self._empty(nrhs) if out is None else out
+        ps, _ = self._vec(sig)
+        info = (SolveInfo * nrhs)()
+        st = self.lib.axs_solve(self.h, pv, p0, ps, nrhs, int(mode), float(tol), int(max_iters), info)
+        self._check(st, soft_ok=True)
+        return sig, [i.as_dict() for i in info]
+
+    # -- fields ---------------------------------------------------------------------
+    def incident_plane_waves(self, dirs):
+        d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        v = self._empty(d.shape[0])
+        self._check(self.lib.axs_incident_plane_waves(self.h, _ptr(d), d.shape[0], ctypes.c_void_p(v.data_ptr())))
+        return v
+
+    def incident_point_sources(self, src, amp):
+        s = np.ascontiguousarray(np.atleast_2d(src), dtype=np.float64)
+        a = np.asarray(amp, dtype=np.complex128).reshape(-1)
+        ab = np.ascontiguousarray(np.stack([a.real, a.imag], axis=1))
+        v = self._empty(1)
+        self._check(self.lib.axs_incident_point_sources(self.h, _ptr(s), _ptr(ab), s.shape[0],
+                                                        ctypes.c_void_p(v.data_ptr())))
+        return v
+
+    def eval_field(self, sigma, targets):
+        t = np.ascontiguousarray(np.atleast_2d(targets), dtype=np.float64)
+        ps, nrhs = self._vec(sigma)
+        u = self._empty(nrhs, t.shape[0])
+        self._check(self.lib.axs_eval_field(self.h, ps, nrhs, _ptr(t), t.shape[0], ctypes.c_void_p(u.data_ptr())))
+        return u
+
+    def far_field(self, sigma, xhat):
+        t = np.ascontiguousarray(np.atleast_2d(xhat), dtype=np.float64)
+        ps, nrhs = self._vec(sigma)
+        u = self._empty(nrhs, t.shape[0])
+        self._check(self.lib.axs_far_field(self.h, ps, nrhs, _ptr(t), t.shape[0], ctypes.c_void_p(u.data_ptr())))
+        return u
+
+    # -- instrumentation --------------------------------------------------------------
+    def set_timing(self, enable=True):
+        self._check(self.lib.axs_set_timing(self.h, int(bool(enable))))
+
+    def last_timing(self):
+        ms = np.zeros(5)
+        self._check(self.lib.axs_last_timing(self.h, _ptr(ms)))
+        return {"interbody": ms[0], "dft_forward": ms[1], "modal_apply": ms[2], "dft_inverse": ms[3],
+                "total": ms[4]}
+
+    def set_interbody_config(self, precision, targets_per_thread=0, block=0, splits=0):
+        self._check(self.lib.axs_set_interbody_config(self.h, int(precision), int(targets_per_thread), int(block),
+                                                      int(splits)))

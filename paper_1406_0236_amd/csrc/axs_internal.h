@@ -1,0 +1,203 @@
+// Internal declarations of the axs library (gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/axs.h"
+
+namespace axs {
+
+// ---------------------------------------------------------------------------
+// error handling: every HIP call is checked; failures become axs_status codes
+// ---------------------------------------------------------------------------
+struct Error {
+    axs_status code;
+    std::string msg;
+};
+
+#define AXS_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::axs::Error{AXS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define AXS_REQUIRE(cond, code, text)                          \
+    do {                                                       \
+        if (!(cond)) throw ::axs::Error{(code), (text)};       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory owned by a context
+// ---------------------------------------------------------------------------
+struct Ctx;
+
+struct Buffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// ---------------------------------------------------------------------------
+// geometry / shape tables
+// ---------------------------------------------------------------------------
+struct Shape {
+    int n_panels = 0, p = 0, NG = 0, M = 0, NF = 0, Nt = 0;
+    double kappa = 0, eta = 0;
+    std::vector<double> r, z, dr, dz, gw;   // host, per contour node
+    std::vector<int> bodies;                // body ids using this shape (build order)
+    // device (owned by ctx buffers)
+    double *A64 = nullptr;    // complex128 interleaved [M+1][NG][NG], A~_m row-major
+    double *S64 = nullptr;    // complex128 interleaved [M+1][NG][NG], S_m row-major
+    double *S64r = nullptr, *S64i = nullptr;   // planar, column-major [M+1][NG(k)][NG(i)]
+    float *S32r = nullptr, *S32i = nullptr;    // same in FP32
+    int64_t xoff = 0;         // offset (in complex elements per rhs) of this shape's
+                              // mode-major block in the DFT workspace
+};
+
+struct Body {
+    int shape = 0;
+    int local = 0;            // index among the bodies of its shape
+    double centre[3] = {0, 0, 0};
+    double rot[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    double bound_radius = 0;  // max |node - centre|
+    int64_t offset = 0;       // first global node index
+    int64_t n = 0;            // NG * NF
+};
+
+// Inter-body work item: one body-aligned target tile against up to two
+// contiguous source ranges (everything outside the target's body, cut into
+// `splits` chunks).  slot = chunk index; partial sums go to part[slot].
+struct IBWork {
+    int32_t t0, tn;
+    int32_t s0, s1, s2, s3;
+    int32_t slot, pad;
+};
+
+// Body descriptor used by the DFT kernels.  The DFT workspace holds, per
+// shape, a mode-major block of columns (column-major, leading dimension NG):
+// mode |m| owns nb*nrhs columns for m = 0 and 2*nb*nrhs otherwise; column
+// (sgn*nb + local)*nrhs + c holds body `local`, rhs c, sign sgn (1 for -m).
+// `xoff` is the shape block's element offset for nrhs = 1 (scale by nrhs).
+struct BodyDev {
+    int64_t offset;      // first global node
+    int64_t xoff;
+    int64_t twoff;       // offset of this body's N_F twiddle table
+    int32_t NG, NF, M, nb;   // nb = bodies of this shape
+    int32_t local, shape;
+};
+
+// Batched GEMM descriptor: Y = S_|m| X for one shape and mode, for nrhs = 1
+// (column counts and offsets scale with nrhs).
+struct GemmBatch {
+    int64_t a_off;       // element offset of S_|m| (planar, column-major NG x NG)
+    int64_t x_off;       // element offset of the column block for nrhs = 1
+    int32_t NG, ncols;   // ncols for nrhs = 1
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    axs_alloc_fn alloc = nullptr;
+    axs_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    std::string err;
+
+    bool have_k = false;
+    double kappa = 0, eta = 0;
+    std::vector<Shape> shapes;
+    std::vector<Body> bodies;
+    int64_t N = 0;
+    bool precomputed = false;
+
+    // global node arrays (device); FP64 and FP32 SoA
+    double *g64 = nullptr;    // [7][N]: x y z nx ny nz w
+    float *g32 = nullptr;     // [6][N]: x y z nx ny nz
+    std::vector<BodyDev> body_dev_host;
+    BodyDev *body_dev = nullptr;
+    double *tw64 = nullptr;   // per distinct NF: twiddles; indexed via twoff
+    float *tw32 = nullptr;
+    GemmBatch *gemm = nullptr;     // batched GEMM table (built at precompute)
+    int ngemm = 0, gemm_max_cols = 0, max_NG = 0;
+
+    // cached inter-body work tables, per precision (0 = fp64, 1 = fp32)
+    IBWork *ib_work[2] = {nullptr, nullptr};
+    int ib_nwork[2] = {0, 0};
+    int ib_key[2][3] = {{0, 0, 0}, {0, 0, 0}};
+
+    // launch configuration of the inter-body sum
+    int ib_tpt[2] = {0, 0};    // targets per thread [fp64, fp32]
+    int ib_block[2] = {0, 0};
+    int ib_splits[2] = {0, 0};
+
+    // timing
+    bool timing = false;
+    hipEvent_t ev[6] = {};
+    double last_ms[5] = {0, 0, 0, 0, 0};
+
+    // device allocations owned by the context
+    std::vector<void *> owned;
+    // named scratch buffers (grow-only)
+    Buffer ws[16];
+
+    void *dalloc(size_t bytes);
+    void dfree(void *p);
+    void *scratch(int slot, size_t bytes);
+    ~Ctx();
+};
+
+enum ScratchSlot {
+    WS_Q = 0,        // staged densities q (R2 [nrhs][N])
+    WS_PART = 1,     // inter-body partial sums (R2 [splits][nrhs][N])
+    WS_XR = 2,       // DFT workspace (planar re)
+    WS_XI = 3,       // DFT workspace (planar im)
+    WS_YR = 4,
+    WS_YI = 5,
+    WS_WORK = 6,     // inter-body work table
+    WS_TMP = 7,      // complex128 temporaries [nrhs][N]
+    WS_TMP2 = 8,
+    WS_KRYLOV = 9,   // Krylov bases
+    WS_RED = 10,     // reduction partials
+    WS_GEMM = 11,    // gemm batch table
+    WS_MISC = 12,
+    WS_TMP3 = 13,
+    WS_KRYLOV2 = 14,
+    WS_EVAL = 15,
+};
+
+// ---------------------------------------------------------------------------
+// launches (defined in the .hip files)
+// ---------------------------------------------------------------------------
+// setup.hip
+void precompute_shape(Ctx &c, Shape &s);
+// interbody.hip
+void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec);   // -> WS_PART
+void interbody_reduce_to_c128(Ctx &c, void *y, int nrhs, int prec);        // WS_PART -> y
+int interbody_splits(Ctx &c, int prec);
+void eval_field_launch(Ctx &c, const void *sigma, int nrhs, const double *tgt_dev, int nt,
+                       void *u);
+void far_field_launch(Ctx &c, const void *sigma, int nrhs, const double *xh_dev, int nd,
+                      void *u);
+void incident_plane_launch(Ctx &c, const double *dirs_dev, int nrhs, void *v);
+void incident_point_launch(Ctx &c, const double *src_dev, const double *amp_dev, int ns, void *v);
+// modal.hip
+// forward DFT from partial sums (src = 0) or from a complex128 vector (src = 1)
+void dft_forward(Ctx &c, int prec, int from_vec, const void *vec, int nrhs, int splits);
+void modal_gemm(Ctx &c, int prec, int nrhs);
+// y = alpha * sigma + beta * inverse DFT
+void dft_inverse(Ctx &c, int prec, const void *sigma, double alpha, double beta, void *y,
+                 int nrhs);
+// krylov.hip
+axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *sigma, int nrhs,
+                      int mode, double tol, int max_iters, axs_solve_info *info);
+// api-level helpers
+void apply_operator(Ctx &c, const void *sigma, void *y, int nrhs, int prec);  // y = sigma + D^-1 B sigma
+void apply_precond(Ctx &c, const void *x, void *y, int nrhs, int prec, double beta);  // y = beta D^-1 x
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace axs

@@ -1,0 +1,85 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol that
+include/axs.h declares, the binding's table matches the header, and the
+entry points reject bad handles without touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "axs.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(axs_[a-z_0-9]+)\s*\(", text))
+    return names - {"axs_alloc_fn", "axs_free_fn"}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1406_0236_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for f in ("axs_build_body", "axs_precompute_scattering", "axs_apply_matvec", "axs_solve"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1406_0236_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    missing = header_functions() - exported
+    assert not missing, missing
+    for name in header_functions():
+        getattr(lib, name)
+
+
+def test_binding_table_matches_header():
+    from paper_1406_0236_amd import _lib
+    assert set(_lib.EXPORTS) == header_functions()
+
+
+def test_null_handles_are_rejected(lib):
+    assert lib.axs_destroy(None) == -1
+    assert lib.axs_last_error(None) == b"null context"
+    assert lib.axs_precompute_scattering(None) == -1
+    assert lib.axs_apply_matvec(None, None, None, 1, 0) == -1
+    n = ctypes.c_int64()
+    assert lib.axs_num_unknowns(None, ctypes.byref(n)) == -1
+
+
+def test_create_rejects_bad_arguments(lib):
+    from paper_1406_0236_amd import _lib
+    h = ctypes.c_void_p()
+    # null output handle, and a device index that cannot exist
+    assert lib.axs_create(None, 0, None, _lib.ALLOC_FN(0), _lib.FREE_FN(0), None) == -1
+    assert lib.axs_create(ctypes.byref(h), 1 << 20, None, _lib.ALLOC_FN(0), _lib.FREE_FN(0), None) == -1
+    assert not h.value
+
+
+def test_product_path_has_no_fallback_when_library_is_missing(monkeypatch, tmp_path):
+    from paper_1406_0236_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()
+
+
+def test_package_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1406_0236_amd")
+    for dp, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dp, f)).read()
+                assert "oracle" not in re.sub(r"#.*|//.*", "", text), f

@@ -1,0 +1,273 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 reference.
+
+Tolerances (relative to the largest entry of the compared quantity):
+  * setup matrices A~_m and S_m (FP64 on the device):  1e-9 -- the two sides use
+    different quadratures (graded Gauss vs tanh-sinh) for the same exact
+    integrals; near-singular cancellation leaves ~1e-11..1e-10;
+  * FP64 operator / inter-body sum / preconditioner:   1e-11;
+  * FP32 operator:  3e-5 -- FP32 rounding of coordinates (kappa |x| 2^-24 phase),
+    the hardware sin/cos and FP32 accumulation over all sources;
+  * solves to tol 1e-11: 1e-8 (condition number of the second-kind system times tol).
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _ctx_for(wl):
+    from paper_1406_0236_amd import Context
+    ctx = Context(0).add_workload(wl)
+    ctx.precompute_scattering()
+    return ctx
+
+
+@pytest.fixture(scope="module")
+def small(small_system):
+    wl, S = small_system
+    print(f"[gpu] building context for {wl.name} N={wl.N}", flush=True)
+    return wl, S, _ctx_for(wl)
+
+
+def _rand(n, r, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((r, n)) + 1j * rng.standard_normal((r, n))
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+# --------------------------------------------------------------------------
+# setup: modal matrices and their inverses
+# --------------------------------------------------------------------------
+
+def test_modal_matrices_match_reference(small):
+    wl, S, ctx = small
+    for bid, body in enumerate(S.bodies):
+        sh = body.shape
+        A_gpu = ctx.modal_matrices(bid, 0, sh.M, sh.NG).cpu().numpy()
+        S_gpu = ctx.modal_matrices(bid, 1, sh.M, sh.NG).cpu().numpy()
+        e_a = rel(A_gpu, sh.modal_matrices())
+        e_s = rel(S_gpu, sh.inverses())
+        print(f"body {bid}: A~ rel err {e_a:.2e}, S rel err {e_s:.2e}")
+        assert e_a < 1e-9 and e_s < 1e-9
+
+
+def test_node_geometry_matches_reference(small):
+    wl, S, ctx = small
+    g = ctx.node_geometry()
+    assert rel(g[:, :3], S.x) < 1e-14
+    assert rel(g[:, 3:6], S.n) < 1e-14
+    assert rel(g[:, 6], S.w) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# operator pieces
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nrhs", [1, 3, 9])
+def test_interbody_sum_fp64_and_fp32(small, nrhs):
+    from paper_1406_0236_amd import FP32, FP64
+    wl, S, ctx = small
+    sig = _rand(S.N, nrhs, 10 + nrhs)
+    ref = S.apply_B(sig.T).T
+    y64 = ctx.apply_interbody(_dev(sig), FP64).cpu().numpy()
+    y32 = ctx.apply_interbody(_dev(sig), FP32).cpu().numpy()
+    assert rel(y64, ref) < 1e-11, rel(y64, ref)
+    assert rel(y32, ref) < 3e-5, rel(y32, ref)
+
+
+def test_preconditioner_matches_reference(small):
+    from paper_1406_0236_amd import FP32, FP64
+    wl, S, ctx = small
+    x = _rand(S.N, 2, 21)
+    ref = S.apply_Dinv(x.T).T
+    y64 = ctx.apply_precond(_dev(x), FP64).cpu().numpy()
+    y32 = ctx.apply_precond(_dev(x), FP32).cpu().numpy()
+    assert rel(y64, ref) < 1e-11, rel(y64, ref)
+    assert rel(y32, ref) < 3e-5, rel(y32, ref)
+
+
+@pytest.mark.parametrize("nrhs", [1, 4])
+def test_preconditioned_operator(small, nrhs):
+    from paper_1406_0236_amd import FP32, FP64
+    wl, S, ctx = small
+    sig = _rand(S.N, nrhs, 30 + nrhs)
+    ref = np.stack([S.matvec(s) for s in sig])
+    y64 = ctx.apply_matvec(_dev(sig), FP64).cpu().numpy()
+    y32 = ctx.apply_matvec(_dev(sig), FP32).cpu().numpy()
+    assert rel(y64, ref) < 1e-11, rel(y64, ref)
+    assert rel(y32, ref) < 3e-5, rel(y32, ref)
+
+
+def test_operator_is_bitwise_reproducible(small):
+    from paper_1406_0236_amd import FP32, FP64
+    wl, S, ctx = small
+    x = _dev(_rand(S.N, 2, 41))
+    for prec in (FP64, FP32):
+        a = ctx.apply_matvec(x, prec).cpu().numpy()
+        b = ctx.apply_matvec(x, prec).cpu().numpy()
+        assert np.array_equal(a, b)
+
+
+def test_interbody_launch_shapes_agree(small):
+    """Every supported launch shape computes the same sum (tiles, splits, ragged tails)."""
+    from paper_1406_0236_amd import FP32, FP64
+    wl, S, ctx = small
+    x = _dev(_rand(S.N, 3, 43))
+    ref = S.apply_B(x.cpu().numpy().T).T
+    for prec, tol in ((FP64, 1e-11), (FP32, 3e-5)):
+        for tpt, block, splits in ((1, 128, 1), (2, 256, 3), (4, 256, 7), (8, 256, 2), (4, 128, 16)):
+            ctx.set_interbody_config(prec, tpt, block, splits)
+            y = ctx.apply_interbody(x, prec).cpu().numpy()
+            assert rel(y, ref) < tol, (prec, tpt, block, splits, rel(y, ref))
+        ctx.set_interbody_config(prec, 0, 0, 0)
+
+
+# --------------------------------------------------------------------------
+# incident fields, field evaluation
+# --------------------------------------------------------------------------
+
+def test_incident_fields_and_field_evaluation(small):
+    wl, S, ctx = small
+    dirs = np.array([[0.0, 0.6, 0.8], [1.0, 0.0, 0.0]])
+    v = ctx.incident_plane_waves(dirs).cpu().numpy()
+    assert rel(v, S.plane_waves(dirs).T) < 1e-13
+    src = np.array([[0.1, 0.2, -0.1], [2.5, 0.5, -0.2]])
+    amp = np.array([1.0 + 0.5j, -0.3j])
+    vp = ctx.incident_point_sources(src, amp).cpu().numpy()[0]
+    assert rel(vp, S.point_source_field(src, amp, S.x)) < 1e-13
+    sig = _rand(S.N, 2, 51)
+    tg = np.array([[5.0, 1.0, 2.0], [-4.0, 3.0, 0.5], [0.5, 0.5, 6.0]])
+    u = ctx.eval_field(_dev(sig), tg).cpu().numpy()
+    assert rel(u, S.eval_field(sig.T, tg).T) < 1e-12
+    xh = np.array([[0.0, 0.0, 1.0], [0.6, 0.8, 0.0]])
+    uf = ctx.far_field(_dev(sig), xh).cpu().numpy()
+    assert rel(uf, S.far_field(sig.T, xh).T) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# solves
+# --------------------------------------------------------------------------
+
+def test_solves_match_dense_reference(small):
+    from paper_1406_0236_amd import SOLVE_FP64, SOLVE_MIXED
+    wl, S, ctx = small
+    dirs = np.array([[0.0, 0.6, 0.8], [0.48, -0.6, 0.64]])
+    v = S.plane_waves(dirs)
+    xd = np.stack([S.solve_dense(v[:, c]) for c in range(2)])
+    vd = ctx.incident_plane_waves(dirs)
+    for mode in (SOLVE_FP64, SOLVE_MIXED):
+        sol, info = ctx.solve(vd, mode=mode, tol=1e-11, max_iters=100)
+        x = sol.cpu().numpy()
+        err = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+        print(f"mode {mode}: {info} err {err:.2e}")
+        assert err < 1e-8, err
+        assert all(i["converged"] for i in info)
+        assert all(i["rel_residual"] <= 1e-11 for i in info)
+
+
+def test_warm_start_is_used_and_bad_guess_is_dropped(small):
+    from paper_1406_0236_amd import SOLVE_FP64
+    wl, S, ctx = small
+    vd = ctx.incident_plane_waves(wl.dirs)
+    sol, info = ctx.solve(vd, mode=SOLVE_FP64, tol=1e-10)
+    # exact guess: kept, converges immediately
+    sol2, info2 = ctx.solve(vd, sigma0=sol.clone(), mode=SOLVE_FP64, tol=1e-9)
+    assert info2[0]["used_warm_start"] == 1 and info2[0]["iterations"] == 0
+    # absurd guess: residual above ||b||, replaced by zero
+    bad = sol * 1e3
+    sol3, info3 = ctx.solve(vd, sigma0=bad, mode=SOLVE_FP64, tol=1e-10)
+    assert info3[0]["used_warm_start"] == 0
+    assert np.linalg.norm((sol3 - sol).cpu().numpy()) <= 1e-8 * np.linalg.norm(sol.cpu().numpy())
+
+
+def test_not_converged_status(small):
+    from paper_1406_0236_amd import SOLVE_FP64
+    wl, S, ctx = small
+    vd = ctx.incident_plane_waves(wl.dirs)
+    sol, info = ctx.solve(vd, mode=SOLVE_FP64, tol=1e-12, max_iters=1)
+    assert info[0]["converged"] == 0 and info[0]["iterations"] == 1
+
+
+# --------------------------------------------------------------------------
+# error paths through the ABI
+# --------------------------------------------------------------------------
+
+def test_error_paths():
+    from paper_1406_0236_amd import AxsError, Context, FP64
+    from workloads import geometry as geo
+    s = geo.sphere(1.0, 3, 10)
+    ctx = Context(0)
+    x = torch.zeros((1, 1), dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(AxsError, match="ESTATE"):
+        ctx.precompute_scattering()
+    ctx.build_body(s.rz, s.drz, s.gw, s.n_panels, s.p, 1.0, 1.0, 4, [0, 0, 0], np.eye(3))
+    with pytest.raises(AxsError, match="EINVAL"):   # overlapping bodies
+        ctx.build_body(s.rz, s.drz, s.gw, s.n_panels, s.p, 1.0, 1.0, 4, [1.0, 0, 0], np.eye(3))
+    with pytest.raises(AxsError, match="EINVAL"):   # kappa mismatch
+        ctx.build_body(s.rz, s.drz, s.gw, s.n_panels, s.p, 2.0, 2.0, 4, [5.0, 0, 0], np.eye(3))
+    with pytest.raises(AxsError, match="EINVAL"):   # wrong Gauss weights
+        ctx.build_body(s.rz, s.drz, s.gw * 1.01, s.n_panels, s.p, 1.0, 1.0, 4, [5.0, 0, 0], np.eye(3))
+    bad = s.rz.copy()
+    bad[3, 0] = np.nan
+    with pytest.raises(AxsError, match="ENONFINITE"):
+        ctx.build_body(bad, s.drz, s.gw, s.n_panels, s.p, 1.0, 1.0, 4, [5.0, 0, 0], np.eye(3))
+    with pytest.raises(AxsError, match="EINVAL"):   # rotation not orthonormal
+        ctx.build_body(s.rz, s.drz, s.gw, s.n_panels, s.p, 1.0, 1.0, 4, [5.0, 0, 0], 2 * np.eye(3))
+    y = torch.zeros((1, ctx.N), dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(AxsError, match="ESTATE"):   # matvec before precompute
+        ctx.apply_matvec(y.clone(), FP64, out=y)
+    ctx.precompute_scattering()
+    with pytest.raises(AxsError, match="ESTATE"):   # no bodies after precompute
+        ctx.build_body(s.rz, s.drz, s.gw, s.n_panels, s.p, 1.0, 1.0, 4, [5.0, 0, 0], np.eye(3))
+    with pytest.raises(AxsError, match="EINVAL"):   # output overlaps input
+        ctx.apply_matvec(y, FP64, out=y)
+    # a single body: no inter-body terms, the operator is the identity
+    z = torch.from_numpy(_rand(ctx.N, 1, 3)).to("cuda:0")
+    assert torch.equal(ctx.apply_matvec(z, FP64), z)
+    ctx.close()
+
+
+# --------------------------------------------------------------------------
+# the two-sphere workload (kappa = pi, N = 8200)
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c1(c1_system):
+    wl, S = c1_system
+    print(f"[gpu] building context for {wl.name} N={wl.N}", flush=True)
+    return wl, S, _ctx_for(wl)
+
+
+def test_two_spheres_modal_matrices(c1):
+    wl, S, ctx = c1
+    sh = S.bodies[0].shape
+    e = rel(ctx.modal_matrices(0, 1, sh.M, sh.NG).cpu().numpy(), sh.inverses())
+    print("S rel err", e)
+    assert e < 1e-9
+
+
+def test_two_spheres_solve_matches_reference(c1):
+    from oracle.multibody import gmres
+    from paper_1406_0236_amd import SOLVE_FP64, SOLVE_MIXED
+    wl, S, ctx = c1
+    v = S.plane_waves(wl.dirs)[:, 0]
+    x_ref, it, _ = gmres(S.matvec, S.rhs(v), tol=1e-13)
+    vd = ctx.incident_plane_waves(wl.dirs)
+    for mode in (SOLVE_FP64, SOLVE_MIXED):
+        sol, info = ctx.solve(vd, mode=mode, tol=1e-11)
+        err = np.linalg.norm(sol.cpu().numpy()[0] - x_ref) / np.linalg.norm(x_ref)
+        print(f"mode {mode}: {info[0]} err {err:.2e} (reference iterations {it})")
+        assert err < 1e-8
