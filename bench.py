@@ -151,6 +151,17 @@ def main():
     for _ in range(2):
         ctx.apply_interbody(x, FP64)
         ms64.append(ctx.last_timing()["interbody"])
+    variants = {}
+    for prec, pname in ((FP32, "fp32"), (FP64, "fp64")):
+        for var, vname in ((1, "points"), (2, "rings")):
+            ctx.set_interbody_config(prec, var, 0, 0, 0)
+            t = []
+            for _ in range(2):
+                ctx.apply_interbody(x, prec)
+                t.append(ctx.last_timing()["interbody"])
+            variants[f"{pname}_{vname}_ms"] = float(np.min(t))
+        ctx.set_interbody_config(prec, 0, 0, 0, 0)
+    log(f"inter-body sum by source order: {variants}")
     ctx.apply_matvec(x, FP32)
     stage32 = ctx.last_timing()
     ctx.apply_matvec(x, FP64)
@@ -193,6 +204,7 @@ def main():
         "gpairs_per_s_fp32": pairs / t_ib / 1e9,
         "gpairs_per_s_fp64": pairs / t_ib64 / 1e9,
         "pct_fp32_valu_peak": 100.0 * achieved / FP32_VECTOR_PEAK_TFLOPS,
+        "interbody_ms_by_variant": variants,
         "stage_ms_fp32": stage32,
         "stage_ms_fp64": stage64,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,

@@ -177,10 +177,56 @@ axs_status axs_far_field(axs_ctx *ctx, const void *sigma, int nrhs, const double
 axs_status axs_set_timing(axs_ctx *ctx, int enable);
 axs_status axs_last_timing(axs_ctx *ctx, double ms[5]);
 
-/* Inter-body sum launch shape (targets per thread, threads per block, source
- * splits); 0 = library default.  Used by the autotuner. */
-axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int targets_per_thread,
-                                    int block, int splits);
+/* Inter-body sum launch shape, per precision; 0 = library default for each field.
+ *  variant: 1 = sources streamed as points, 2 = sources streamed as azimuthal rings
+ *           (per target and ring, R^2 and n.d become two FMAs each; needs kappa > 0)
+ *  targets_per_thread: 1, 2, 4 or 8;  block: 128 or 256 threads;
+ *  splits: number of source chunks per target tile (partial sums reduced in order).
+ * Every shape computes the same sum; used by the launch-shape autotuner. */
+axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant,
+                                    int targets_per_thread, int block, int splits);
+
+/* ------------------------------------------------------------------------ *
+ * Learned warm start.  A multilayer perceptron maps (incident direction,
+ * scaled wavenumber) to the low azimuthal modes of the density; it is
+ * trained on solves of the method itself, and its prediction is decoded into
+ * an initial guess sigma0 for axs_solve, which keeps it only if its FP64
+ * residual is below || b || (the zero guess otherwise).
+ * ------------------------------------------------------------------------ */
+typedef struct axs_mlp axs_mlp;
+
+/* Network n_in -> width (x depth hidden layers, GELU) -> n_out (linear), FP32,
+ * on ctx's device and stream, parameters zero until axs_mlp_set_params.  The
+ * network must be destroyed before its context.  Parameters are packed layer by
+ * layer as [W_1 (n_in x width, row-major, input index first), b_1, W_2, b_2, ...]. */
+axs_status axs_mlp_create(axs_ctx *ctx, int n_in, int width, int depth, int n_out, axs_mlp **out);
+axs_status axs_mlp_destroy(axs_mlp *mlp);
+axs_status axs_mlp_num_params(const axs_mlp *mlp, int64_t *count);
+/* host float arrays of axs_mlp_num_params entries; set also resets the Adam state */
+axs_status axs_mlp_set_params(axs_mlp *mlp, const float *host_params);
+axs_status axs_mlp_get_params(axs_mlp *mlp, float *host_params);
+/* Y = network(X); X device float [batch][n_in], Y device float [batch][n_out] */
+axs_status axs_mlp_forward(axs_mlp *mlp, const float *X, float *Y, int batch);
+/* mean squared error L = sum (Y - T)^2 / (batch n_out) and dL/dparams (device
+ * float [num_params], may be NULL); loss may be NULL (else synchronises) */
+axs_status axs_mlp_gradient(axs_mlp *mlp, const float *X, const float *T, int batch, double *loss,
+                            float *grad);
+/* one Adam step on the batch (bias-corrected moments) */
+axs_status axs_mlp_adam_step(axs_mlp *mlp, const float *X, const float *T, int batch, double lr,
+                             double beta1, double beta2, double eps, double *loss);
+
+/* Floats per right-hand side of the mode encoding below:
+ * 2 * (2 m_max + 1) * sum over bodies of N_G. */
+axs_status axs_warm_start_size(axs_ctx *ctx, int mmax, int64_t *P);
+/* coeff[c] (device float [nrhs][P]): for body b (build order), contour node i,
+ * m = -m_max..m_max, (re, im) of e^{-i kappa d_c.centre_b} (1/N_F) sum_l
+ * sigma[c](b, i, l) e^{-i m theta_l}; dirs host [nrhs][3]. */
+axs_status axs_modes_from_density(axs_ctx *ctx, const void *sigma, const double *dirs, int nrhs,
+                                  int mmax, float *coeff);
+/* the inverse map on the retained modes: sigma[c](b, i, l) = e^{i kappa d_c.centre_b}
+ * sum_{|m| <= m_max} coeff e^{i m theta_l}; sigma device complex128 [nrhs][N]. */
+axs_status axs_density_from_modes(axs_ctx *ctx, const float *coeff, const double *dirs, int nrhs,
+                                  int mmax, void *sigma);
 
 #ifdef __cplusplus
 }

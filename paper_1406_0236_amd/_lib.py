@@ -70,7 +70,24 @@ EXPORTS = {
     "axs_set_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int]),
     "axs_last_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "axs_set_interbody_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                                  ctypes.c_int]),
+                                                  ctypes.c_int, ctypes.c_int]),
+    "axs_mlp_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "axs_mlp_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "axs_mlp_num_params": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "axs_mlp_set_params": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "axs_mlp_get_params": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "axs_mlp_forward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
+    "axs_mlp_gradient": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
+    "axs_mlp_adam_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "axs_warm_start_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
+    "axs_modes_from_density": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_void_p]),
+    "axs_density_from_modes": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_void_p]),
 }
 
 
@@ -124,6 +141,7 @@ class Context:
             raise AxsError(st, "axs_create failed")
         self.h = h
         self.N = 0
+        self.max_nf = 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -165,6 +183,7 @@ class Context:
         n = ctypes.c_int64()
         self.lib.axs_num_unknowns(self.h, ctypes.byref(n))
         self.N = n.value
+        self.max_nf = max(self.max_nf, 2 * int(M) + 1)
         return bid.value
 
     def add_workload(self, wl):
@@ -254,6 +273,100 @@ class Context:
         return {"interbody": ms[0], "dft_forward": ms[1], "modal_apply": ms[2], "dft_inverse": ms[3],
                 "total": ms[4]}
 
-    def set_interbody_config(self, precision, targets_per_thread=0, block=0, splits=0):
-        self._check(self.lib.axs_set_interbody_config(self.h, int(precision), int(targets_per_thread), int(block),
-                                                      int(splits)))
+    def set_interbody_config(self, precision, variant=0, targets_per_thread=0, block=0, splits=0):
+        """Launch shape of the inter-body sum (0 = default): variant 1 = points, 2 = rings."""
+        self._check(self.lib.axs_set_interbody_config(self.h, int(precision), int(variant), int(targets_per_thread),
+                                                      int(block), int(splits)))
+
+
+class Mlp:
+    """The warm-start network (include/axs.h, axs_mlp_*): FP32, on a context's
+    device and stream.  X, T, Y are float32 cuda tensors [batch][n]."""
+
+    def __init__(self, ctx: Context, n_in: int, width: int, depth: int, n_out: int):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.sizes = [n_in] + [width] * depth + [n_out]
+        h = ctypes.c_void_p()
+        st = self.lib.axs_mlp_create(ctx.h, n_in, width, depth, n_out, ctypes.byref(h))
+        ctx._check(st)
+        self.h = h
+        n = ctypes.c_int64()
+        self.lib.axs_mlp_num_params(self.h, ctypes.byref(n))
+        self.nparams = n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.axs_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f32(self, t, ncol):
+        torch = self.ctx._torch
+        assert t.dtype == torch.float32 and t.is_cuda and t.is_contiguous() and t.dim() == 2 and t.shape[1] == ncol
+        return ctypes.c_void_p(t.data_ptr()), t.shape[0]
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.nparams
+        self.ctx._check(self.lib.axs_mlp_set_params(self.h, _ptr(p)))
+
+    def get_params(self):
+        p = np.empty(self.nparams, dtype=np.float32)
+        self.ctx._check(self.lib.axs_mlp_get_params(self.h, _ptr(p)))
+        return p
+
+    def forward(self, X):
+        px, b = self._f32(X, self.sizes[0])
+        Y = self.ctx._torch.empty((b, self.sizes[-1]), dtype=self.ctx._torch.float32, device=X.device)
+        self.ctx._check(self.lib.axs_mlp_forward(self.h, px, ctypes.c_void_p(Y.data_ptr()), b))
+        return Y
+
+    def gradient(self, X, T):
+        px, b = self._f32(X, self.sizes[0])
+        pt, _ = self._f32(T, self.sizes[-1])
+        g = self.ctx._torch.empty(self.nparams, dtype=self.ctx._torch.float32, device=X.device)
+        loss = ctypes.c_double()
+        self.ctx._check(self.lib.axs_mlp_gradient(self.h, px, pt, b, ctypes.byref(loss), ctypes.c_void_p(g.data_ptr())))
+        return loss.value, g
+
+    def adam_step(self, X, T, lr, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=True):
+        px, b = self._f32(X, self.sizes[0])
+        pt, _ = self._f32(T, self.sizes[-1])
+        loss = ctypes.c_double()
+        self.ctx._check(self.lib.axs_mlp_adam_step(self.h, px, pt, b, float(lr), float(beta1), float(beta2),
+                                                   float(eps), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+
+def warm_start_size(ctx: Context, mmax: int) -> int:
+    n = ctypes.c_int64()
+    ctx._check(ctx.lib.axs_warm_start_size(ctx.h, int(mmax), ctypes.byref(n)))
+    return n.value
+
+
+def modes_from_density(ctx: Context, sigma, dirs, mmax: int):
+    torch = ctx._torch
+    ps, nrhs = ctx._vec(sigma)
+    d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+    assert d.shape == (nrhs, 3)
+    P = warm_start_size(ctx, mmax)
+    out = torch.empty((nrhs, P), dtype=torch.float32, device=sigma.device)
+    ctx._check(ctx.lib.axs_modes_from_density(ctx.h, ps, _ptr(d), nrhs, int(mmax), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def density_from_modes(ctx: Context, coeff, dirs, mmax: int):
+    torch = ctx._torch
+    d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+    nrhs = d.shape[0]
+    assert coeff.dtype == torch.float32 and coeff.is_contiguous() and coeff.shape == (nrhs, warm_start_size(ctx, mmax))
+    out = ctx._empty(nrhs)
+    ctx._check(ctx.lib.axs_density_from_modes(ctx.h, ctypes.c_void_p(coeff.data_ptr()), _ptr(d), nrhs, int(mmax),
+                                              ctypes.c_void_p(out.data_ptr())))
+    return out

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["api.hip", "interbody.hip", "modal.hip", "setup.hip", "krylov.hip"]
+SOURCES = ["api.hip", "interbody.hip", "modal.hip", "setup.hip", "krylov.hip", "mlp.hip"]
 LIB = os.path.join(HERE, "libaxs.so")
 
 

@@ -12,6 +12,7 @@ namespace axs {
 
 void gauss_legendre_public(int n, std::vector<double> &x, std::vector<double> &w);
 void split_planar(Ctx &c, Shape &s, double *r64, double *i64, float *r32, float *i32);
+void build_ring_tables(Ctx &c);
 
 void *Ctx::dalloc(size_t bytes) {
     if (bytes == 0) bytes = 256;
@@ -223,6 +224,7 @@ static void precompute_all(Ctx &c) {
     c.g32 = (float *)c.dalloc(6 * N * sizeof(float));
     AXS_HIP(hipMemcpy(c.g64, g.data(), 7 * N * sizeof(double), hipMemcpyHostToDevice));
     AXS_HIP(hipMemcpy(c.g32, g32.data(), 6 * N * sizeof(float), hipMemcpyHostToDevice));
+    build_ring_tables(c);
     AXS_HIP(hipStreamSynchronize(c.stream));
     c.precomputed = true;
 }
@@ -557,15 +559,17 @@ axs_status axs_last_timing(axs_ctx *ctx, double ms[5]) {
     });
 }
 
-axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int tpt, int block, int splits) {
+axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant, int tpt, int block, int splits) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         AXS_REQUIRE(precision == AXS_FP64 || precision == AXS_FP32, AXS_EINVAL, "bad precision");
+        AXS_REQUIRE(variant >= 0 && variant <= 2, AXS_EINVAL, "variant must be 0, 1 (points) or 2 (rings)");
         AXS_REQUIRE(tpt == 0 || tpt == 1 || tpt == 2 || tpt == 4 || tpt == 8, AXS_EINVAL,
                     "targets per thread must be 0, 1, 2, 4 or 8");
         AXS_REQUIRE(block == 0 || block == 128 || block == 256, AXS_EINVAL, "block must be 0, 128 or 256");
         AXS_REQUIRE(splits >= 0 && splits <= 256, AXS_EINVAL, "splits must be in [0, 256]");
         AXS_REQUIRE(!(tpt == 8 && block == 128), AXS_EINVAL, "unsupported combination");
         const int pi = precision == AXS_FP32 ? 1 : 0;
+        c.ib_variant[pi] = variant;
         c.ib_tpt[pi] = tpt;
         c.ib_block[pi] = block;
         c.ib_splits[pi] = splits;

@@ -127,12 +127,25 @@ struct Ctx {
     // cached inter-body work tables, per precision (0 = fp64, 1 = fp32)
     IBWork *ib_work[2] = {nullptr, nullptr};
     int ib_nwork[2] = {0, 0};
-    int ib_key[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    int ib_key[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 
-    // launch configuration of the inter-body sum
-    int ib_tpt[2] = {0, 0};    // targets per thread [fp64, fp32]
+    // launch configuration of the inter-body sum (0 = library default)
+    int ib_variant[2] = {0, 0};   // 1 = point sources, 2 = azimuthal rings
+    int ib_tpt[2] = {0, 0};       // targets per thread [fp64, fp32]
     int ib_block[2] = {0, 0};
     int ib_splits[2] = {0, 0};
+
+    // ring tables (one ring = one contour node of one body = its N_F azimuthal nodes)
+    int nrings = 0;
+    std::vector<int64_t> ring_base;      // first ring id of each body
+    int32_t *ring_i = nullptr;           // [3][nrings]: node offset, N_F, body
+    double *ring_g64 = nullptr;          // [4][nrings]: r, z, n_r, n_z
+    float *ring_g32 = nullptr;
+    double *frame64 = nullptr;           // [B][12]: centre, rotation (row-major)
+    float *frame32 = nullptr;
+    double *cs64 = nullptr;              // [2][N]: cos, sin of each node's azimuth
+    float *cs32 = nullptr;
+    int max_nf = 0;
 
     // timing
     bool timing = false;

@@ -14,7 +14,17 @@
 //     complex accumulators in registers;
 //   - FP32 path: phase reduced in revolutions (v_fract) and fed to the
 //     hardware sin/cos (which take revolutions), 1/R from v_rsq;
-//   - FP64 path: the same structure with libm sincospi / rsqrt.
+//   - FP64 path: the same structure with an octant-reduced Taylor sin/cos and
+//     a Newton-refined hardware 1/sqrt.
+// Two source orders ("variants") compute the same sum:
+//   - points: each staged source carries x, y, z, n and q;
+//   - rings: a body's N_F nodes on one contour node form a ring; per target
+//     and ring the constants p (target in the source body's frame), |p|^2 + r^2,
+//     r p_x, r p_y, n_r p_x, n_r p_y are formed once, after which R^2 and n.d
+//     cost two FMAs each per pair and the staged source carries only
+//     (cos th_l, sin th_l, q).  Coordinates are scaled by kappa / 2 pi inside
+//     those constants so that R * kappa / 2 pi (the phase in revolutions)
+//     is R^2 * rsq(R^2) with no further multiply.
 #include "axs_internal.h"
 
 namespace axs {
@@ -25,15 +35,52 @@ template <> struct C2T<double> { using T = double2; };
 
 __device__ __forceinline__ void sincos_rev(float ph, float &s, float &c) {
     float f = __builtin_amdgcn_fractf(ph);   // [0, 1)
-    s = __builtin_amdgcn_sinf(f);            // sin(2 pi f)
+    s = __builtin_amdgcn_sinf(f);            // hardware sin/cos take revolutions
     c = __builtin_amdgcn_cosf(f);
 }
-__device__ __forceinline__ void sincos_rev(double ph, double &s, double &c) {
-    double f = ph - rint(ph);                // exact, in [-1/2, 1/2]
-    sincospi(2.0 * f, &s, &c);
+
+// sin and cos of 2 pi t (t in revolutions) in FP64: reduction to an octant,
+// r = t - k/4 in [-1/8, 1/8] exactly, x = 2 pi r in [-pi/4, pi/4], Taylor
+// series (coefficients +-1/n!) to x^15 for sin and x^16 for cos, whose
+// truncation errors are below 1e-16 on that interval, then the quadrant turn.
+constexpr double inv_fact(int n) { return n <= 1 ? 1.0 : inv_fact(n - 1) / n; }
+__device__ __forceinline__ void sincos_rev(double t, double &s, double &c) {
+    const double f = t - rint(t);            // exact, [-1/2, 1/2]
+    const double kq = rint(4.0 * f);         // quadrant -2..2
+    const double r = fma(-0.25, kq, f);      // exact
+    const double x = r * 6.283185307179586476925287;
+    const double x2 = x * x;
+    double ps = -inv_fact(15);
+    ps = fma(x2, ps, inv_fact(13));
+    ps = fma(x2, ps, -inv_fact(11));
+    ps = fma(x2, ps, inv_fact(9));
+    ps = fma(x2, ps, -inv_fact(7));
+    ps = fma(x2, ps, inv_fact(5));
+    ps = fma(x2, ps, -inv_fact(3));
+    const double sx = fma(x * x2, ps, x);
+    double pc = inv_fact(16);
+    pc = fma(x2, pc, -inv_fact(14));
+    pc = fma(x2, pc, inv_fact(12));
+    pc = fma(x2, pc, -inv_fact(10));
+    pc = fma(x2, pc, inv_fact(8));
+    pc = fma(x2, pc, -inv_fact(6));
+    pc = fma(x2, pc, inv_fact(4));
+    pc = fma(x2, pc, -0.5);
+    const double cx = fma(x2, pc, 1.0);
+    const int q = ((int)kq) & 3;             // turn by q quarter revolutions
+    const double a = (q & 1) ? cx : sx, b = (q & 1) ? sx : cx;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
 }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+// 1/sqrt(x) for finite x > 0: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rsq(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
 
 // LDS stride (in elements) of one staged source: x y z nx ny nz + NR complex q,
 // rounded up to 16 bytes so the compiler can use 128-bit LDS reads.
@@ -53,6 +100,7 @@ __global__ __launch_bounds__(BS) void interbody_kernel(
 
     const IBWork w = work[blockIdx.x];
     const int tid = threadIdx.x;
+    const int cb = c0 + blockIdx.y * NR;   // first rhs of this block's group
     const R *gx = geo, *gy = geo + N, *gz = geo + 2 * N;
     const R *gnx = geo + 3 * N, *gny = geo + 4 * N, *gnz = geo + 5 * N;
 
@@ -88,7 +136,7 @@ __global__ __launch_bounds__(BS) void interbody_kernel(
                 d[5] = gnz[j];
 #pragma unroll
                 for (int c = 0; c < NR; ++c) {
-                    R2 v = q[(int64_t)(c0 + c) * N + j];
+                    R2 v = q[(int64_t)(cb + c) * N + j];
                     d[6 + 2 * c] = v.x;
                     d[7 + 2 * c] = v.y;
                 }
@@ -136,7 +184,164 @@ __global__ __launch_bounds__(BS) void interbody_kernel(
                 R2 v;
                 v.x = ar[k][c];
                 v.y = ai[k][c];
-                part[((int64_t)w.slot * nrhs + c0 + c) * N + w.t0 + t] = v;
+                part[((int64_t)w.slot * nrhs + cb + c) * N + w.t0 + t] = v;
+            }
+        }
+    }
+}
+
+// LDS stride of one staged ring node: cos, sin + NR complex q, 16-byte rounded.
+template <typename R, int NR> struct RingStride {
+    static constexpr int raw = 2 + 2 * NR;
+    static constexpr int per16 = 16 / sizeof(R);
+    static constexpr int value = (raw + per16 - 1) / per16 * per16;
+};
+
+// Ring variant.  Work items hold ring-id ranges; rings are numbered in node
+// order, so a ring range is a contiguous node range.  Sources are staged in
+// LDS a tile of whole rings at a time (at most BS nodes).
+struct RingTabs {
+    const int32_t *off, *nf, *body;   // [nrings]
+};
+
+template <typename R, int TPT, int NR, int BS>
+__global__ __launch_bounds__(BS) void interbody_ring_kernel(
+    const IBWork *__restrict__ work, const R *__restrict__ geo, const R *__restrict__ cs,
+    const typename C2T<R>::T *__restrict__ q, RingTabs rt, const R *__restrict__ rg, int nrings,
+    const R *__restrict__ frame, int64_t N, int nrhs, int c0, R k2pi, R eta, typename C2T<R>::T *__restrict__ part) {
+    using R2 = typename C2T<R>::T;
+    constexpr int ST = RingStride<R, NR>::value;
+    __shared__ __align__(16) R tile[BS * ST];
+
+    const IBWork w = work[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int cb = c0 + blockIdx.y * NR;   // first rhs of this block's group
+    const R *gx = geo, *gy = geo + N, *gz = geo + 2 * N;
+    const R *gc = cs, *gs = cs + N;
+    const R *rr_ = rg, *rz_ = rg + nrings, *rnr = rg + 2 * nrings, *rnz = rg + 3 * nrings;
+    const R s2 = k2pi * k2pi, c1 = k2pi * k2pi * k2pi;
+    const R etap = eta * k2pi;
+    const R twopi = R(6.283185307179586476925287);
+
+    R tx[TPT], ty[TPT], tz[TPT];
+    R px[TPT], py[TPT], pz[TPT];
+    R ar[TPT][NR], ai[TPT][NR];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        int t = tid + k * BS;
+        int64_t gi = w.t0 + (t < w.tn ? t : 0);
+        tx[k] = gx[gi];
+        ty[k] = gy[gi];
+        tz[k] = gz[gi];
+        px[k] = py[k] = pz[k] = R(0);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) ar[k][c] = ai[k][c] = R(0);
+    }
+    int prev_body = -1;
+
+#pragma unroll 1
+    for (int rng = 0; rng < 2; ++rng) {
+        const int lo = rng == 0 ? w.s0 : w.s2;
+        const int hi = rng == 0 ? w.s1 : w.s3;
+        int r0 = lo;
+#pragma unroll 1
+        while (r0 < hi) {
+            // a tile of whole rings [r0, r1) holding at most BS nodes
+            const int nb = rt.off[r0];
+            int r1 = r0, cnt = 0;
+            while (r1 < hi && cnt + rt.nf[r1] <= BS) {
+                cnt += rt.nf[r1];
+                ++r1;
+            }
+            if (r1 == r0) break;   // a ring wider than a tile: the host never launches this
+            __syncthreads();
+            if (tid < cnt) {
+                const int64_t j = (int64_t)nb + tid;
+                R *d = tile + tid * ST;
+                d[0] = gc[j];
+                d[1] = gs[j];
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    R2 v = q[(int64_t)(cb + c) * N + j];
+                    d[2 + 2 * c] = v.x;
+                    d[3 + 2 * c] = v.y;
+                }
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int ring = r0; ring < r1; ++ring) {
+                const int b = rt.body[ring];
+                if (b != prev_body) {
+                    // targets in the source body's frame: p = Rot^T (x - c)
+                    const R *f = frame + 12 * b;
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) {
+                        const R dx = tx[k] - f[0], dy = ty[k] - f[1], dz = tz[k] - f[2];
+                        px[k] = fma(f[3], dx, fma(f[6], dy, f[9] * dz));
+                        py[k] = fma(f[4], dx, fma(f[7], dy, f[10] * dz));
+                        pz[k] = fma(f[5], dx, fma(f[8], dy, f[11] * dz));
+                    }
+                    prev_body = b;
+                }
+                const R rj = rr_[ring], zj = rz_[ring], nrj = rnr[ring], nzj = rnz[ring];
+                const int nf = rt.nf[ring];
+                const R *src = tile + (rt.off[ring] - nb) * ST;
+                // per target: R'^2 = al + Ax cos + Ay sin, nd' = be + Bx cos + By sin
+                // (R' = R k/2pi, nd' = n.d (k/2pi)^3)
+                R al[TPT], Ax[TPT], Ay[TPT], Bx[TPT], By[TPT], be[TPT];
+#pragma unroll
+                for (int k = 0; k < TPT; ++k) {
+                    const R pzp = pz[k] - zj;
+                    al[k] = fma(px[k], px[k], fma(py[k], py[k], fma(pzp, pzp, rj * rj))) * s2;
+                    Ax[k] = (R(-2) * s2 * rj) * px[k];
+                    Ay[k] = (R(-2) * s2 * rj) * py[k];
+                    Bx[k] = (c1 * nrj) * px[k];
+                    By[k] = (c1 * nrj) * py[k];
+                    be[k] = fma(nzj, pzp, -nrj * rj) * c1;
+                }
+#pragma unroll 2
+                for (int l = 0; l < nf; ++l) {
+                    const R *s = src + l * ST;
+                    const R cl = s[0], sl = s[1];
+                    R qr[NR], qi[NR];
+#pragma unroll
+                    for (int c = 0; c < NR; ++c) {
+                        qr[c] = s[2 + 2 * c];
+                        qi[c] = s[3 + 2 * c];
+                    }
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) {
+                        const R r2 = fma(Ax[k], cl, fma(Ay[k], sl, al[k]));
+                        const R nd = fma(Bx[k], cl, fma(By[k], sl, be[k]));
+                        const R u = rsq(r2);                  // 1 / R'
+                        R sn, cs_;
+                        sincos_rev(r2 * u, sn, cs_);          // phase R' = kR / 2pi revolutions
+                        const R t = nd * (u * u);
+                        const R P = t * u;                    // n.d / R^3
+                        const R Q = fma(-twopi, t, etap * u);  // eta / R - k n.d / R^2
+                        const R gr = fma(cs_, P, -sn * Q);
+                        const R gi = fma(cs_, Q, sn * P);
+#pragma unroll
+                        for (int c = 0; c < NR; ++c) {
+                            ar[k][c] = fma(gr, qr[c], fma(-gi, qi[c], ar[k][c]));
+                            ai[k][c] = fma(gr, qi[c], fma(gi, qr[c], ai[k][c]));
+                        }
+                    }
+                }
+            }
+            r0 = r1;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k) {
+        int t = tid + k * BS;
+        if (t < w.tn) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                R2 v;
+                v.x = ar[k][c];
+                v.y = ai[k][c];
+                part[((int64_t)w.slot * nrhs + cb + c) * N + w.t0 + t] = v;
             }
         }
     }
@@ -173,44 +378,60 @@ __global__ void reduce_parts_kernel(const typename C2T<R>::T *__restrict__ part,
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static int default_tpt(int prec) { return prec == AXS_FP32 ? 4 : 2; }
-static int default_block(int) { return 256; }
+struct IBShape {
+    int variant, tpt, bs, splits;
+};
 
-int interbody_splits(Ctx &c, int prec) {
-    int pi = prec == AXS_FP32 ? 1 : 0;
-    if (c.ib_splits[pi] > 0) return c.ib_splits[pi];
-    // enough blocks to fill 256 CUs several times over
-    int tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : default_tpt(prec);
-    int bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : default_block(prec);
-    int64_t tiles = 0;
-    for (auto &b : c.bodies) tiles += ceil_div(b.n, (int64_t)tpt * bs);
-    int s = 1;
-    while (tiles * s < 4096 && s < 64) s *= 2;
+static IBShape launch_shape(Ctx &c, int prec) {
+    const int pi = prec == AXS_FP32 ? 1 : 0;
+    IBShape s;
+    s.tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : (prec == AXS_FP32 ? 4 : 2);
+    s.bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : 256;
+    const bool ring_ok = c.kappa > 0 && c.max_nf <= s.bs;
+    s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi] : (ring_ok ? 2 : 1);
+    AXS_REQUIRE(s.variant == 1 || ring_ok, AXS_EINVAL,
+                "ring variant needs kappa > 0 and N_F <= threads per block");
+    if (c.ib_splits[pi] > 0) {
+        s.splits = c.ib_splits[pi];
+    } else {
+        // enough blocks to fill 256 CUs several times over
+        int64_t tiles = 0;
+        for (auto &b : c.bodies) tiles += ceil_div(b.n, (int64_t)s.tpt * s.bs);
+        s.splits = 1;
+        while (tiles * s.splits < 4096 && s.splits < 64) s.splits *= 2;
+    }
     return s;
 }
 
-static std::vector<IBWork> build_work(Ctx &c, int tile, int splits) {
+int interbody_splits(Ctx &c, int prec) { return launch_shape(c, prec).splits; }
+
+// Work items: every body-aligned tile of `tile` targets against `splits`
+// chunks of the source units (nodes or rings) outside the target's body.
+static std::vector<IBWork> build_work(Ctx &c, int tile, int splits, bool rings) {
     std::vector<IBWork> out;
-    const int64_t N = c.N;
-    for (auto &b : c.bodies) {
-        const int64_t others = N - b.n;
+    const int64_t U = rings ? c.nrings : c.N;
+    for (size_t bi = 0; bi < c.bodies.size(); ++bi) {
+        const auto &b = c.bodies[bi];
+        const int64_t uoff = rings ? c.ring_base[bi] : b.offset;
+        const int64_t un = rings ? c.shapes[b.shape].NG : b.n;
+        const int64_t others = U - un;
         const int64_t chunk = ceil_div(std::max<int64_t>(others, 1), splits);
         for (int64_t t0 = 0; t0 < b.n; t0 += tile) {
             for (int s = 0; s < splits; ++s) {
                 IBWork w{};
                 w.t0 = (int32_t)(b.offset + t0);
                 w.tn = (int32_t)std::min<int64_t>(tile, b.n - t0);
-                int64_t v0 = std::min<int64_t>(others, (int64_t)s * chunk);
-                int64_t v1 = std::min<int64_t>(others, v0 + chunk);
-                // virtual index v < offset -> v ; v >= offset -> v + n
-                int64_t a0 = v0, a1 = std::min<int64_t>(v1, b.offset);
+                const int64_t v0 = std::min<int64_t>(others, (int64_t)s * chunk);
+                const int64_t v1 = std::min<int64_t>(others, v0 + chunk);
+                // virtual unit v < uoff -> v ; v >= uoff -> v + un (skips the own body)
+                int64_t a0 = v0, a1 = std::min<int64_t>(v1, uoff);
                 if (a1 < a0) a1 = a0;
-                int64_t b0 = std::max<int64_t>(v0, b.offset), b1 = v1;
+                int64_t b0 = std::max<int64_t>(v0, uoff), b1 = v1;
                 if (b1 < b0) b1 = b0;
                 w.s0 = (int32_t)a0;
                 w.s1 = (int32_t)a1;
-                w.s2 = (int32_t)(b0 + b.n);
-                w.s3 = (int32_t)(b1 + b.n);
+                w.s2 = (int32_t)(b0 + un);
+                w.s3 = (int32_t)(b1 + un);
                 w.slot = s;
                 out.push_back(w);
             }
@@ -219,41 +440,107 @@ static std::vector<IBWork> build_work(Ctx &c, int tile, int splits) {
     return out;
 }
 
+// ring tables, body frames and per-node azimuth cos/sin (built once)
+void build_ring_tables(Ctx &c) {
+    const int64_t N = c.N;
+    std::vector<int32_t> ri;
+    std::vector<double> rg, fr, csv(2 * N);
+    c.ring_base.clear();
+    int nr = 0;
+    c.max_nf = 0;
+    for (size_t bi = 0; bi < c.bodies.size(); ++bi) {
+        const auto &b = c.bodies[bi];
+        const Shape &s = c.shapes[b.shape];
+        c.ring_base.push_back(nr);
+        nr += s.NG;
+        c.max_nf = std::max(c.max_nf, s.NF);
+        for (int a = 0; a < 3; ++a) fr.push_back(b.centre[a]);
+        for (int a = 0; a < 9; ++a) fr.push_back(b.rot[a]);
+        for (int l = 0; l < s.NF; ++l) {
+            const double th = 2.0 * M_PI * l / s.NF;
+            for (int i = 0; i < s.NG; ++i) {
+                const int64_t j = b.offset + (int64_t)i * s.NF + l;
+                csv[j] = std::cos(th);
+                csv[N + j] = std::sin(th);
+            }
+        }
+    }
+    c.nrings = nr;
+    std::vector<int32_t> off(nr), nf(nr), body(nr);
+    std::vector<double> g(4 * (size_t)nr);
+    for (size_t bi = 0; bi < c.bodies.size(); ++bi) {
+        const auto &b = c.bodies[bi];
+        const Shape &s = c.shapes[b.shape];
+        for (int i = 0; i < s.NG; ++i) {
+            const int id = (int)c.ring_base[bi] + i;
+            off[id] = (int32_t)(b.offset + (int64_t)i * s.NF);
+            nf[id] = s.NF;
+            body[id] = (int32_t)bi;
+            const double sp = std::hypot(s.dr[i], s.dz[i]);
+            g[id] = s.r[i];
+            g[nr + id] = s.z[i];
+            g[2 * nr + id] = -s.dz[i] / sp;
+            g[3 * nr + id] = s.dr[i] / sp;
+        }
+    }
+    ri.insert(ri.end(), off.begin(), off.end());
+    ri.insert(ri.end(), nf.begin(), nf.end());
+    ri.insert(ri.end(), body.begin(), body.end());
+    c.ring_i = (int32_t *)c.dalloc(ri.size() * sizeof(int32_t));
+    AXS_HIP(hipMemcpy(c.ring_i, ri.data(), ri.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    auto up = [&](const std::vector<double> &h, double *&d64, float *&d32) {
+        std::vector<float> f(h.begin(), h.end());
+        d64 = (double *)c.dalloc(h.size() * sizeof(double));
+        d32 = (float *)c.dalloc(h.size() * sizeof(float));
+        AXS_HIP(hipMemcpy(d64, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+        AXS_HIP(hipMemcpy(d32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    };
+    up(g, c.ring_g64, c.ring_g32);
+    up(fr, c.frame64, c.frame32);
+    up(csv, c.cs64, c.cs32);
+}
+
 template <typename R, int TPT, int BS>
-static void launch_ib(Ctx &c, const IBWork *work, int nwork, const R *geo,
-                      const typename C2T<R>::T *q, int nrhs, typename C2T<R>::T *part) {
+static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const R *geo, const R *cs,
+                      const R *rg, const R *frame, const typename C2T<R>::T *q, int nrhs,
+                      typename C2T<R>::T *part) {
     const R kappa = (R)c.kappa, k2pi = (R)(c.kappa / (2.0 * M_PI)), eta = (R)c.eta;
+    const RingTabs rt{c.ring_i, c.ring_i + c.nrings, c.ring_i + 2 * c.nrings};
+    // one launch covers every body and every full group of NR right-hand sides
+    // (grid.y = groups); a remainder group gets one more launch
     int c0 = 0;
     while (c0 < nrhs) {
-        int left = nrhs - c0;
-        if (left >= 8) {
-            hipLaunchKernelGGL((interbody_kernel<R, TPT, 8, BS>), dim3(nwork), dim3(BS), 0, c.stream,
-                               work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, part);
-            c0 += 8;
-        } else if (left >= 4) {
-            hipLaunchKernelGGL((interbody_kernel<R, TPT, 4, BS>), dim3(nwork), dim3(BS), 0, c.stream,
-                               work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, part);
-            c0 += 4;
-        } else if (left >= 2) {
-            hipLaunchKernelGGL((interbody_kernel<R, TPT, 2, BS>), dim3(nwork), dim3(BS), 0, c.stream,
-                               work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, part);
-            c0 += 2;
-        } else {
-            hipLaunchKernelGGL((interbody_kernel<R, TPT, 1, BS>), dim3(nwork), dim3(BS), 0, c.stream,
-                               work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, part);
-            c0 += 1;
-        }
+        const int left = nrhs - c0;
+        const int nr = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        const int groups = left / nr;
+#define AXS_IB_NR(NR_)                                                                                     \
+    if (nr == NR_) {                                                                                       \
+        if (variant == 2)                                                                                  \
+            hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, NR_, BS>), dim3(nwork, groups), dim3(BS), 0, \
+                               c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta, \
+                               part);                                                                      \
+        else                                                                                               \
+            hipLaunchKernelGGL((interbody_kernel<R, TPT, NR_, BS>), dim3(nwork, groups), dim3(BS), 0,      \
+                               c.stream, work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, part);             \
+    }
+        AXS_IB_NR(8)
+        AXS_IB_NR(4)
+        AXS_IB_NR(2)
+        AXS_IB_NR(1)
+#undef AXS_IB_NR
         AXS_HIP(hipGetLastError());
+        c0 += nr * groups;
     }
 }
 
 template <typename R>
-static void dispatch_ib(Ctx &c, int tpt, int bs, const IBWork *work, int nwork, const R *geo,
-                        const typename C2T<R>::T *q, int nrhs, typename C2T<R>::T *part) {
-#define AXS_IB_CASE(T_, B_)                                                 \
-    if (tpt == T_ && bs == B_) {                                            \
-        launch_ib<R, T_, B_>(c, work, nwork, geo, q, nrhs, part);           \
-        return;                                                             \
+static void dispatch_ib(Ctx &c, const IBShape &s, const IBWork *work, int nwork, const R *geo, const R *cs,
+                        const R *rg, const R *frame, const typename C2T<R>::T *q, int nrhs,
+                        typename C2T<R>::T *part) {
+#define AXS_IB_CASE(T_, B_)                                                             \
+    if (s.tpt == T_ && s.bs == B_) {                                                    \
+        launch_ib<R, T_, B_>(c, s.variant, work, nwork, geo, cs, rg, frame, q, nrhs, part); \
+        return;                                                                         \
     }
     AXS_IB_CASE(1, 256)
     AXS_IB_CASE(2, 256)
@@ -268,12 +555,12 @@ static void dispatch_ib(Ctx &c, int tpt, int bs, const IBWork *work, int nwork, 
 
 void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
     const int pi = prec == AXS_FP32 ? 1 : 0;
-    const int tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : default_tpt(prec);
-    const int bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : default_block(prec);
-    const int splits = interbody_splits(c, prec);
-    if (!c.ib_work[pi] || c.ib_key[pi][0] != tpt || c.ib_key[pi][1] != bs || c.ib_key[pi][2] != splits) {
+    const IBShape s = launch_shape(c, prec);
+    const bool rings = s.variant == 2;
+    if (!c.ib_work[pi] || c.ib_key[pi][0] != s.tpt || c.ib_key[pi][1] != s.bs || c.ib_key[pi][2] != s.splits ||
+        c.ib_key[pi][3] != s.variant) {
         // work tables are cached per launch shape; rebuilt only when it changes
-        std::vector<IBWork> work = build_work(c, tpt * bs, splits);
+        std::vector<IBWork> work = build_work(c, s.tpt * s.bs, s.splits, rings);
         if (c.ib_work[pi]) {
             AXS_HIP(hipStreamSynchronize(c.stream));
             c.dfree(c.ib_work[pi]);
@@ -281,9 +568,10 @@ void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
         c.ib_work[pi] = (IBWork *)c.dalloc(work.size() * sizeof(IBWork));
         AXS_HIP(hipMemcpy(c.ib_work[pi], work.data(), work.size() * sizeof(IBWork), hipMemcpyHostToDevice));
         c.ib_nwork[pi] = (int)work.size();
-        c.ib_key[pi][0] = tpt;
-        c.ib_key[pi][1] = bs;
-        c.ib_key[pi][2] = splits;
+        c.ib_key[pi][0] = s.tpt;
+        c.ib_key[pi][1] = s.bs;
+        c.ib_key[pi][2] = s.splits;
+        c.ib_key[pi][3] = s.variant;
     }
     const IBWork *dwork = c.ib_work[pi];
     const int nwork = c.ib_nwork[pi];
@@ -291,18 +579,18 @@ void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
     const int thr = 256;
     if (prec == AXS_FP32) {
         float2 *q = (float2 *)c.scratch(WS_Q, total * sizeof(float2));
-        float2 *part = (float2 *)c.scratch(WS_PART, (size_t)splits * total * sizeof(float2));
+        float2 *part = (float2 *)c.scratch(WS_PART, (size_t)s.splits * total * sizeof(float2));
         hipLaunchKernelGGL(stage_density_kernel<float>, dim3(ceil_div(total, thr)), dim3(thr), 0,
                            c.stream, (const double2 *)sigma, c.g64 + 6 * c.N, c.N, total, q);
         AXS_HIP(hipGetLastError());
-        dispatch_ib<float>(c, tpt, bs, dwork, nwork, c.g32, q, nrhs, part);
+        dispatch_ib<float>(c, s, dwork, nwork, c.g32, c.cs32, c.ring_g32, c.frame32, q, nrhs, part);
     } else {
         double2 *q = (double2 *)c.scratch(WS_Q, total * sizeof(double2));
-        double2 *part = (double2 *)c.scratch(WS_PART, (size_t)splits * total * sizeof(double2));
+        double2 *part = (double2 *)c.scratch(WS_PART, (size_t)s.splits * total * sizeof(double2));
         hipLaunchKernelGGL(stage_density_kernel<double>, dim3(ceil_div(total, thr)), dim3(thr), 0,
                            c.stream, (const double2 *)sigma, c.g64 + 6 * c.N, c.N, total, q);
         AXS_HIP(hipGetLastError());
-        dispatch_ib<double>(c, tpt, bs, dwork, nwork, c.g64, q, nrhs, part);
+        dispatch_ib<double>(c, s, dwork, nwork, c.g64, c.cs64, c.ring_g64, c.frame64, q, nrhs, part);
     }
 }
 
