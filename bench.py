@@ -91,6 +91,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--small", action="store_true", help="two-sphere workload (quick check)")
+    ap.add_argument("--learned", action="store_true",
+                    help="learned warm start on the 8 mixed bodies: 64 wavenumbers x 64 directions of "
+                         "training solves, 8 x 64 held out")
+    ap.add_argument("--autotune", action="store_true", help="autotune the inter-body launch shape first")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -101,6 +105,9 @@ def main():
     import torch
     from paper_1406_0236_amd import FP32, FP64, SOLVE_FP64, SOLVE_MIXED, Context
     from workloads import configs
+
+    if args.learned:
+        return learned(args)
 
     wl = configs.two_spheres() if args.small else configs.sphere_lattice()
     log(f"workload {wl.name}: N={wl.N}, pairs={wl.pairs:.4g}")
@@ -114,6 +121,15 @@ def main():
     log(f"precompute (FP64, GPU) {t_pre:.2f} s")
     v = ctx.incident_plane_waves(wl.dirs)
     torch.cuda.synchronize()
+    tuned = None
+    if args.autotune:
+        from paper_1406_0236_amd import autotune
+        tuned = {}
+        for prec, name in ((FP32, "fp32"), (FP64, "fp64")):
+            cfg, tim = autotune.tune(ctx, prec, 1, ctx.max_nf, x=v, reps=1, cache_path=None,
+                                     verbose=True)
+            tuned[name] = {"config": cfg, "ms": min(tim.values())}
+        log(f"autotuned: {tuned}")
 
     infos = []
     for w in range(args.warmup):
@@ -212,9 +228,65 @@ def main():
                      "kernel": "interbody_kernel<float> (FP32 inter-body sum)",
                      "flop_per_launch": flops, "launch_ms": t_ib * 1e3},
         "cpu_baseline": cpu,
+        "autotuned": tuned,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def learned(args):
+    """Learned warm start: train on method-generated solves, evaluate held-out."""
+    import numpy as np
+    import torch
+    from paper_1406_0236_amd import Context
+    from paper_1406_0236_amd import warmstart as W
+    from workloads import configs
+
+    wl_at = lambda k: configs.mixed_bodies(kappa=k, disc_kappa=W.K_MAX, n_dirs=1)
+    rng = np.random.default_rng(4)
+    n_k, n_d = 64, 64
+    ks = rng.uniform(W.K_MIN, W.K_MAX, n_k)
+    dirs = [W.random_directions(n_d, rng) for _ in ks]
+    t0 = time.time()
+    X, Y = W.generate(wl_at, ks, dirs, mmax=8, tol=1e-8, log=log)
+    t_gen = time.time() - t0
+    log(f"training set: {X.shape[0]} solves, {Y.shape[1]} outputs, {t_gen:.1f} s")
+    dev = Context(0)
+    ws = W.WarmStart(dev, Y.shape[1], mmax=8, width=512, depth=4)
+    hist = ws.train(X, Y, epochs=200, batch=256, lr=1e-3, log=log)
+    rng2 = np.random.default_rng(40)
+    hk = rng2.uniform(W.K_MIN, W.K_MAX, 8)
+    hd = [W.random_directions(64, rng2) for _ in hk]
+    rows = W.evaluate(ws, wl_at, hk, hd, tol=args.tol, log=log)
+    agg = {}
+    for mode in ("fp64", "mixed"):
+        agg[mode] = {key: float(np.mean([r[mode][key] for r in rows]))
+                     for key in ("zero_iters", "warm_iters", "zero_inner", "warm_inner", "zero_s", "warm_s")}
+        agg[mode]["warm_used_fraction"] = float(np.sum([r[mode]["warm_used"] for r in rows]) / (8 * 64))
+    wl = wl_at(W.K_MAX)
+    out = {
+        "metric": "s to 1e-7 residual with learned warm start vs zero guess (64 rhs per solve)",
+        "value": agg["mixed"]["warm_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": len(rows),
+        "warmup": 0,
+        "ms_per_step": agg["mixed"]["warm_s"] * 1e3,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "mixed8_seed3 at k in [1.5 pi, 2.5 pi], discretised at 2.5 pi", "N": wl.N,
+                   "train_solves": int(X.shape[0]), "held_out": 8 * 64, "m_max": 8,
+                   "mlp": [4, 512, 512, 512, 512, int(Y.shape[1])], "epochs": 200, "batch": 256},
+        "held_out_mean": agg,
+        "per_k": rows,
+        "train_loss_first_last": [hist[0], hist[-1]],
+        "train_seconds": ws.train_seconds,
+        "generate_seconds": t_gen,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

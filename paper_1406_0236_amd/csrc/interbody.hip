@@ -299,7 +299,7 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                     By[k] = (c1 * nrj) * py[k];
                     be[k] = fma(nzj, pzp, -nrj * rj) * c1;
                 }
-#pragma unroll 2
+#pragma unroll(sizeof(R) == 4 ? 2 : 1)
                 for (int l = 0; l < nf; ++l) {
                     const R *s = src + l * ST;
                     const R cl = s[0], sl = s[1];
@@ -385,10 +385,12 @@ struct IBShape {
 static IBShape launch_shape(Ctx &c, int prec) {
     const int pi = prec == AXS_FP32 ? 1 : 0;
     IBShape s;
-    s.tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : (prec == AXS_FP32 ? 4 : 2);
+    // defaults from the launch-shape sweep on MI355X (27-sphere lattice):
+    // FP32 rings x 2 targets per thread, FP64 points x 4 targets per thread
+    s.tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : (prec == AXS_FP32 ? 2 : 4);
     s.bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : 256;
     const bool ring_ok = c.kappa > 0 && c.max_nf <= s.bs;
-    s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi] : (ring_ok ? 2 : 1);
+    s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi] : ((ring_ok && prec == AXS_FP32) ? 2 : 1);
     AXS_REQUIRE(s.variant == 1 || ring_ok, AXS_EINVAL,
                 "ring variant needs kappa > 0 and N_F <= threads per block");
     if (c.ib_splits[pi] > 0) {
