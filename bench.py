@@ -30,6 +30,12 @@ FLOP_PER_PAIR = 39.0            # algorithmic flops of one kernel evaluation + c
 FLOP_PER_EXTRA_RHS = 8.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X published FP32 vector peak
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+# HBM bytes per launch of the default FP32 inter-body kernel on this workload,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a calibration copy
+# (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
+# source they were taken on.
+TRAFFIC_BYTES = 80.14e6
+TRAFFIC_SOURCE_SHA = "d3dd28f14a699ceb"
 
 
 def log(msg):
@@ -95,6 +101,9 @@ def main():
                     help="learned warm start on the 8 mixed bodies: 64 wavenumbers x 64 directions of "
                          "training solves, 8 x 64 held out")
     ap.add_argument("--autotune", action="store_true", help="autotune the inter-body launch shape first")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="launch only what the hardware-counter passes measure: a 512 MiB device copy "
+                         "(calibration), then two FP32 and one FP64 inter-body sums on the 27 spheres")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -108,6 +117,8 @@ def main():
 
     if args.learned:
         return learned(args)
+    if args.pmc_probe:
+        return pmc_probe()
 
     wl = configs.two_spheres() if args.small else configs.sphere_lattice()
     log(f"workload {wl.name}: N={wl.N}, pairs={wl.pairs:.4g}")
@@ -187,6 +198,10 @@ def main():
     t_ib64 = float(np.median(ms64)) * 1e-3
     pairs = wl.pairs
     flops = FLOP_PER_PAIR * pairs
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1406_0236_amd", "csrc", "interbody.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    traffic = TRAFFIC_BYTES if (sha == TRAFFIC_SOURCE_SHA and not args.small and tuned is None) else None
     achieved = flops / t_ib / 1e12
     log(f"interbody fp32 {t_ib*1e3:.2f} ms ({pairs / t_ib / 1e9:.1f} Gpairs/s, {achieved:.2f} TFLOP/s); "
         f"fp64 {t_ib64*1e3:.2f} ms; stages fp32 {stage32} fp64 {stage64}")
@@ -224,7 +239,7 @@ def main():
         "stage_ms_fp32": stage32,
         "stage_ms_fp64": stage64,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "interbody_kernel<float> (FP32 inter-body sum)",
                      "flop_per_launch": flops, "launch_ms": t_ib * 1e3},
         "cpu_baseline": cpu,
@@ -287,6 +302,30 @@ def learned(args):
         "generate_seconds": t_gen,
     }
     print(json.dumps(out), flush=True)
+
+
+
+def pmc_probe():
+    """Known-size copy for counter calibration, then the dominant kernels."""
+    import torch
+    from paper_1406_0236_amd import FP32, FP64, Context
+    from workloads import configs
+    n = 512 * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("calibration copy: 512 MiB read + 512 MiB written")
+    wl = configs.sphere_lattice()
+    ctx = Context(0).add_workload(wl)
+    ctx.precompute_scattering()
+    v = ctx.incident_plane_waves(wl.dirs)
+    for prec in (FP32, FP32, FP64):
+        ctx.apply_interbody(v, prec)
+        torch.cuda.synchronize()
+    log("inter-body sums done")
+    ctx.close()
 
 
 if __name__ == "__main__":
