@@ -509,11 +509,15 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
     const R kappa = (R)c.kappa, k2pi = (R)(c.kappa / (2.0 * M_PI)), eta = (R)c.eta;
     const RingTabs rt{c.ring_i, c.ring_i + c.nrings, c.ring_i + 2 * c.nrings};
     // one launch covers every body and every full group of NR right-hand sides
-    // (grid.y = groups); a remainder group gets one more launch
+    // (grid.y = groups); a remainder group gets one more launch.  Wide groups
+    // (16, 32) share one kernel evaluation among more complex MACs; they exist
+    // for the FP32 ring order with 128-thread blocks (LDS tile <= 35 KB).
+    const bool wide = sizeof(R) == 4 && variant == 2 && BS == 128 && TPT <= 2;
     int c0 = 0;
     while (c0 < nrhs) {
         const int left = nrhs - c0;
-        const int nr = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        const int nr = (wide && left >= 32) ? 32 : (wide && left >= 16) ? 16 : left >= 8 ? 8 : left >= 4 ? 4
+                                                                                      : left >= 2 ? 2 : 1;
         const int groups = left / nr;
 #define AXS_IB_NR(NR_)                                                                                     \
     if (nr == NR_) {                                                                                       \
@@ -525,6 +529,18 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
             hipLaunchKernelGGL((interbody_kernel<R, TPT, NR_, BS>), dim3(nwork, groups), dim3(BS), 0,      \
                                c.stream, work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, part);             \
     }
+        if constexpr (sizeof(R) == 4 && BS == 128 && TPT <= 2) {
+            if (nr == 32)
+                hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, 32, BS>), dim3(nwork, groups), dim3(BS), 0,
+                                   c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta,
+                                   part);
+            if (nr == 16)
+                hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, 16, BS>), dim3(nwork, groups), dim3(BS), 0,
+                                   c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta,
+                                   part);
+        } else {
+            if (nr > 8) throw Error{AXS_EINVAL, "wide rhs groups need FP32 rings, 128 threads, <= 2 targets"};
+        }
         AXS_IB_NR(8)
         AXS_IB_NR(4)
         AXS_IB_NR(2)

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 
 #include "axs_internal.h"
 
@@ -163,6 +164,15 @@ static void scale(Ctx &c, const double2 *in, const std::vector<double> &s, doubl
     AXS_HIP(hipStreamSynchronize(c.stream));
 }
 
+// AXS_VERBOSE=1 in the environment prints one line per outer iteration to stderr
+static int verbose_level() {
+    static const int v = [] {
+        const char *e = std::getenv("AXS_VERBOSE");
+        return e ? std::atoi(e) : 0;
+    }();
+    return v;
+}
+
 // Arnoldi/GMRES state for nrhs independent systems sharing the operator.
 struct Gmres {
     int nrhs, maxit;
@@ -290,6 +300,12 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
                 if (rel_est[cc] <= tol || hn == 0.0) G.done_at[cc] = j + 1;
             }
             if (G.done_at[cc] < 0) all_done = false;
+        }
+        if (verbose_level() > 0) {
+            double worst = 0;
+            for (int cc = 0; cc < nrhs; ++cc) worst = std::max(worst, rel_est[cc]);
+            std::fprintf(stderr, "[axs] %s iteration %d: max relative residual %.3e\n",
+                         flexible ? "outer" : "gmres", j + 1, worst);
         }
         scale(c, w, sc, w, N, nrhs, sdev);
         if (all_done) {

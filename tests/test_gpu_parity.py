@@ -364,3 +364,18 @@ def test_autotuner_choice_is_valid(small, tmp_path):
     cfg2, _ = autotune.tune(ctx, FP32, 2, ctx.max_nf, cache_path=str(tmp_path / "cache.json"))
     assert list(cfg2) == list(cfg)
     ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+
+
+def test_wide_rhs_groups_fp32_rings(small):
+    """37 right-hand sides through 32-, 4- and 1-wide groups (FP32 rings, 128 threads)."""
+    from paper_1406_0236_amd import FP32
+    wl, S, ctx = small
+    sig = _rand(S.N, 37, 81)
+    ref = S.apply_B(sig.T).T
+    for tpt, splits in ((2, 0), (1, 3)):
+        ctx.set_interbody_config(FP32, 2, tpt, 128, splits)
+        y = ctx.apply_interbody(_dev(sig), FP32).cpu().numpy()
+        e = rel(y, ref)
+        print(f"tpt {tpt}: rel err {e:.2e}")
+        assert e < 3e-5, e
+    ctx.set_interbody_config(FP32, 0, 0, 0, 0)

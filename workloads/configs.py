@@ -89,19 +89,29 @@ def mixed_bodies(seed=3, kappa=2 * math.pi, n_dirs=64, disc_kappa=None) -> Workl
 
 def mixed_many(seed=5, kappa=4 * math.pi, n_bodies=64, box=24.0, gap=0.5, n_dirs=16,
                p=10) -> Workload:
-    """64 mixed bodies (spheres, prolate aspect 1-3, bowls) in a 24^3 box."""
+    """64 mixed bodies (spheres, spheroids of aspect U[1, 3], bowls) in a 24^3 box.
+
+    Contours at the 27-sphere lattice's density (20 panels per pi of arc
+    length, about 6.4 panels per wavelength at kappa = 4 pi), M from the
+    equatorial radius.
+    """
     rng = np.random.default_rng(seed)
+    per_len = 20.0 / math.pi
+
+    def npan(length, lo=1):
+        return max(lo, int(math.ceil(length * per_len - 1e-9)))
+
+    sph = geo.sphere(1.0, npan(math.pi), p)
+    al = 2.0 * math.pi / 3.0
+    bowl = geo.bowl(npan(0.8 * al), npan(0.1 * math.pi, 2), npan(al), p)
     shapes = []
-    sph = geo.sphere(1.0, 20, p)
-    bowl = geo.bowl_at_wavelength(kappa)
     for b in range(n_bodies):
         kind = b % 3
         if kind == 0:
             shapes.append(sph)
         elif kind == 1:
             c = float(rng.uniform(1.0, 3.0))
-            npan = max(20, geo.panels_for_wavelength(geo._prolate_length(1.0, c), kappa))
-            shapes.append(geo.prolate(1.0, c, npan, p))
+            shapes.append(geo.prolate(1.0, c, npan(geo._prolate_length(1.0, c)), p))
         else:
             shapes.append(bowl)
     centres = geo.place_bodies([s.bound_radius for s in shapes], box, gap, rng)
