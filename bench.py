@@ -35,7 +35,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
 # source they were taken on.
 TRAFFIC_BYTES = 80.14e6
-TRAFFIC_SOURCE_SHA = "d3dd28f14a699ceb"
+TRAFFIC_SOURCE_SHA = "61d3ea4c96348744"
 
 
 def log(msg):
