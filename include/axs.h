@@ -125,7 +125,9 @@ axs_status axs_apply_precond(axs_ctx *ctx, const void *x, void *y, int nrhs, int
 typedef struct {
     int32_t iterations;       /* outer iterations (FP64 operator applications) */
     int32_t inner_iterations; /* inner (FP32 operator) iterations, mixed mode */
-    double rel_residual;      /* final FP64 || b - (I + D^-1 B) sigma || / || b ||, b = -D^-1 v */
+    double rel_residual;      /* final FP64 || b - (I + D^-1 B) sigma || / || b ||, b = -D^-1 v:
+                                 the GMRES least-squares residual of the FP64 Arnoldi
+                                 relation, or with AXS_SOLVE_CERTIFY recomputed from sigma */
     double seconds;           /* wall time of the solve on the host clock */
     int32_t used_warm_start;  /* 1 if sigma0 was kept as the initial guess */
     int32_t converged;
@@ -133,8 +135,11 @@ typedef struct {
 
 enum {
     AXS_SOLVE_FP64 = 0,       /* GMRES, FP64 operator */
-    AXS_SOLVE_MIXED = 1       /* flexible GMRES with FP64 operator and residual, whose
+    AXS_SOLVE_MIXED = 1,      /* flexible GMRES with FP64 operator and residual, whose
                                  preconditioner is an inner GMRES on the FP32 operator */
+    AXS_SOLVE_CERTIFY = 16    /* flag, OR-ed into the mode: after the iteration, apply
+                                 the FP64 operator once more to the returned sigma and
+                                 report (and test convergence on) that explicit residual */
 };
 
 /* Solve (eq. "precond")  sigma + D^{-1} B sigma = -D^{-1} v  for nrhs incident fields.
@@ -142,7 +147,10 @@ enum {
  *  sigma0   : device complex128 [nrhs][N] initial guess, or NULL for zero.  A guess
  *             whose FP64 residual is not below || b || is replaced by zero.
  *  sigma    : device complex128 [nrhs][N], the result.
- *  mode     : AXS_SOLVE_FP64 or AXS_SOLVE_MIXED.
+ *  mode     : AXS_SOLVE_FP64 or AXS_SOLVE_MIXED, optionally | AXS_SOLVE_CERTIFY.
+ *             Without the flag the residual is the one GMRES minimises in its FP64
+ *             Arnoldi basis (classical Gram-Schmidt twice), equal to the explicit
+ *             one up to FP64 rounding; the flag costs one more FP64 application.
  *  tol      : stop when every right-hand side has relative FP64 residual <= tol.
  *  max_iters: cap on outer iterations (Krylov dimension; no restart).
  *  info     : host array [nrhs].  Returns AXS_NOT_CONVERGED if any rhs missed tol. */
@@ -179,12 +187,26 @@ axs_status axs_last_timing(axs_ctx *ctx, double ms[5]);
 
 /* Inter-body sum launch shape, per precision; 0 = library default for each field.
  *  variant: 1 = sources streamed as points, 2 = sources streamed as azimuthal rings
- *           (per target and ring, R^2 and n.d become two FMAs each; needs kappa > 0)
- *  targets_per_thread: 1, 2, 4 or 8;  block: 128 or 256 threads;
+ *           (per target and ring, R^2 and n.d become two FMAs each; needs kappa > 0),
+ *           3 = MFMA order, FP32 only, kappa > 0: R^2 and n.d of 16 x 16 (source,
+ *           target) blocks from matrix-core products of 4-vectors in the source
+ *           body's frame; with 16 right-hand sides per group the complex
+ *           multiply-accumulate is a matrix-core product too
+ *  targets_per_thread: 1, 2, 4 or 8 (variant 3: 1, 2 or 4 groups of 16 targets
+ *           per wavefront);  block: 128 or 256 threads (variant 3: 256);
  *  splits: number of source chunks per target tile (partial sums reduced in order).
- * Every shape computes the same sum; used by the launch-shape autotuner. */
+ * Every shape computes the same sum; used by the launch-shape autotuner.
+ * Shapes that do not fit the context are rejected (AXS_EINVAL) at the next
+ * inter-body application, not here. */
 axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant,
                                     int targets_per_thread, int block, int splits);
+
+/* The launch shape the next inter-body application in `precision` will use,
+ * defaults resolved: out[0..3] = variant, targets per thread (variant 3: groups
+ * of 16 targets per wavefront), block, splits.  out: host int[4].
+ * AXS_ESTATE before axs_precompute_scattering; AXS_EINVAL if the configured
+ * shape does not fit the context. */
+axs_status axs_interbody_launch_shape(axs_ctx *ctx, int precision, int *out);
 
 /* ------------------------------------------------------------------------ *
  * Learned warm start.  A multilayer perceptron maps (incident direction,

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libaxs.so")
 AXS_OK, AXS_NOT_CONVERGED = 0, 1
 FP64, FP32 = 0, 1
 SOLVE_FP64, SOLVE_MIXED = 0, 1
+SOLVE_CERTIFY = 16   # flag: recompute the final residual with one more FP64 application
 _STATUS = {0: "AXS_OK", 1: "AXS_NOT_CONVERGED", -1: "AXS_EINVAL", -2: "AXS_EHIP", -3: "AXS_ENOMEM",
            -4: "AXS_ESTATE", -5: "AXS_ENONFINITE"}
 
@@ -69,6 +70,7 @@ EXPORTS = {
                                        ctypes.c_int, ctypes.c_void_p]),
     "axs_set_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int]),
     "axs_last_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "axs_interbody_launch_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "axs_set_interbody_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                   ctypes.c_int, ctypes.c_int]),
     "axs_mlp_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -142,6 +144,7 @@ class Context:
         self.h = h
         self.N = 0
         self.max_nf = 0
+        self.kappa = None
 
     def close(self):
         if getattr(self, "h", None):
@@ -184,6 +187,7 @@ class Context:
         self.lib.axs_num_unknowns(self.h, ctypes.byref(n))
         self.N = n.value
         self.max_nf = max(self.max_nf, 2 * int(M) + 1)
+        self.kappa = float(kappa)
         return bid.value
 
     def add_workload(self, wl):
@@ -223,7 +227,10 @@ class Context:
     def apply_precond(self, x, precision=FP64, out=None):
         return self._apply(self.lib.axs_apply_precond, x, precision, out)
 
-    def solve(self, incident, sigma0=None, mode=SOLVE_FP64, tol=1e-7, max_iters=200, out=None):
+    def solve(self, incident, sigma0=None, mode=SOLVE_FP64, tol=1e-7, max_iters=200, out=None, certify=False):
+        """axs_solve; certify=True ORs AXS_SOLVE_CERTIFY into the mode."""
+        if certify:
+            mode = int(mode) | SOLVE_CERTIFY
         pv, nrhs = self._vec(incident)
         p0 = self._vec(sigma0)[0] if sigma0 is not None else None
         sig = self._empty(nrhs) if out is None else out
@@ -274,9 +281,16 @@ class Context:
                 "total": ms[4]}
 
     def set_interbody_config(self, precision, variant=0, targets_per_thread=0, block=0, splits=0):
-        """Launch shape of the inter-body sum (0 = default): variant 1 = points, 2 = rings."""
+        """Launch shape of the inter-body sum (0 = default): variant 1 = points, 2 = rings,
+        3 = MFMA order (FP32; targets_per_thread = groups of 16 targets per wavefront)."""
         self._check(self.lib.axs_set_interbody_config(self.h, int(precision), int(variant), int(targets_per_thread),
                                                       int(block), int(splits)))
+
+    def interbody_launch_shape(self, precision):
+        """The resolved launch shape (variant, targets_per_thread, block, splits)."""
+        out = (ctypes.c_int * 4)()
+        self._check(self.lib.axs_interbody_launch_shape(self.h, int(precision), out))
+        return tuple(int(v) for v in out)
 
 
 class Mlp:

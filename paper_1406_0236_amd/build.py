@@ -6,6 +6,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["api.hip", "interbody.hip", "modal.hip", "setup.hip", "krylov.hip", "mlp.hip"]
 LIB = os.path.join(HERE, "libaxs.so")
+# MFMA results of the inter-body kernels feed VALU arithmetic at once: keep
+# them in ordinary VGPRs instead of accumulation registers (saves two
+# v_accvgpr_read per pair in the inner loop)
+EXTRA = {"interbody.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
@@ -21,7 +25,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for s in SOURCES:
         o = os.path.join(objdir, s.replace(".hip", ".o"))
         objs.append(o)
-        cmd = ["hipcc", "-c", *flags, os.path.join(csrc, s), "-o", o]
+        cmd = ["hipcc", "-c", *flags, *EXTRA.get(s, []), os.path.join(csrc, s), "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -13,6 +13,7 @@ namespace axs {
 void gauss_legendre_public(int n, std::vector<double> &x, std::vector<double> &w);
 void split_planar(Ctx &c, Shape &s, double *r64, double *i64, float *r32, float *i32);
 void build_ring_tables(Ctx &c);
+void interbody_shape(Ctx &c, int prec, int out[4]);
 
 void *Ctx::dalloc(size_t bytes) {
     if (bytes == 0) bytes = 256;
@@ -479,7 +480,8 @@ axs_status axs_solve(axs_ctx *ctx, const void *incident, const void *sigma0, voi
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         check_apply(c, incident, sigma, nrhs, AXS_FP64);
         if (sigma0) check_apply(c, sigma0, sigma, nrhs, AXS_FP64);
-        AXS_REQUIRE(mode == AXS_SOLVE_FP64 || mode == AXS_SOLVE_MIXED, AXS_EINVAL, "bad solve mode");
+        const int base = mode & ~AXS_SOLVE_CERTIFY;
+        AXS_REQUIRE(base == AXS_SOLVE_FP64 || base == AXS_SOLVE_MIXED, AXS_EINVAL, "bad solve mode");
         AXS_REQUIRE(tol > 0 && tol < 1 && std::isfinite(tol), AXS_EINVAL, "tol must be in (0, 1)");
         AXS_REQUIRE(max_iters >= 1 && max_iters <= 2000, AXS_EINVAL, "max_iters must be in [1, 2000]");
         const bool t = c.timing;
@@ -562,7 +564,9 @@ axs_status axs_last_timing(axs_ctx *ctx, double ms[5]) {
 axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant, int tpt, int block, int splits) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         AXS_REQUIRE(precision == AXS_FP64 || precision == AXS_FP32, AXS_EINVAL, "bad precision");
-        AXS_REQUIRE(variant >= 0 && variant <= 2, AXS_EINVAL, "variant must be 0, 1 (points) or 2 (rings)");
+        AXS_REQUIRE(variant >= 0 && variant <= 3, AXS_EINVAL,
+                    "variant must be 0, 1 (points), 2 (rings) or 3 (MFMA, FP32)");
+        AXS_REQUIRE(variant != 3 || precision == AXS_FP32, AXS_EINVAL, "the MFMA variant is FP32 only");
         AXS_REQUIRE(tpt == 0 || tpt == 1 || tpt == 2 || tpt == 4 || tpt == 8, AXS_EINVAL,
                     "targets per thread must be 0, 1, 2, 4 or 8");
         AXS_REQUIRE(block == 0 || block == 128 || block == 256, AXS_EINVAL, "block must be 0, 128 or 256");
@@ -573,6 +577,16 @@ axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant, in
         c.ib_tpt[pi] = tpt;
         c.ib_block[pi] = block;
         c.ib_splits[pi] = splits;
+        return AXS_OK;
+    });
+}
+
+axs_status axs_interbody_launch_shape(axs_ctx *ctx, int precision, int *out) {
+    return guarded(ctx, [&](Ctx &c) -> axs_status {
+        AXS_REQUIRE(out, AXS_EINVAL, "null output");
+        AXS_REQUIRE(precision == AXS_FP64 || precision == AXS_FP32, AXS_EINVAL, "bad precision");
+        AXS_REQUIRE(c.precomputed, AXS_ESTATE, "call axs_precompute_scattering first");
+        interbody_shape(c, precision, out);
         return AXS_OK;
     });
 }

@@ -59,6 +59,10 @@ struct Shape {
                               // mode-major block in the DFT workspace
 };
 
+// per-body frame record on the device: centre[3], rotation[9] (row-major,
+// global = centre + rot * local), bounding radius, 3 pad
+constexpr int FRAME = 16;
+
 struct Body {
     int shape = 0;
     int local = 0;            // index among the bodies of its shape
@@ -130,7 +134,7 @@ struct Ctx {
     int ib_key[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
 
     // launch configuration of the inter-body sum (0 = library default)
-    int ib_variant[2] = {0, 0};   // 1 = point sources, 2 = azimuthal rings
+    int ib_variant[2] = {0, 0};   // 1 = point sources, 2 = azimuthal rings, 3 = MFMA (FP32)
     int ib_tpt[2] = {0, 0};       // targets per thread [fp64, fp32]
     int ib_block[2] = {0, 0};
     int ib_splits[2] = {0, 0};
@@ -141,11 +145,19 @@ struct Ctx {
     int32_t *ring_i = nullptr;           // [3][nrings]: node offset, N_F, body
     double *ring_g64 = nullptr;          // [4][nrings]: r, z, n_r, n_z
     float *ring_g32 = nullptr;
-    double *frame64 = nullptr;           // [B][12]: centre, rotation (row-major)
+    double *frame64 = nullptr;           // [B][FRAME]: centre, rotation (row-major), bound radius
     float *frame32 = nullptr;
     double *cs64 = nullptr;              // [2][N]: cos, sin of each node's azimuth
     float *cs32 = nullptr;
     int max_nf = 0;
+    // MFMA source order (FP32, kappa > 0): per node, in its body's frame,
+    // [0, N): (k/2pi)^2 (-2y, |y|^2); [N, 2N): (k/2pi)^3 (n, -n.y)
+    float *mf_src = nullptr;
+    int64_t *body_off = nullptr;         // [B + 1]: first node of each body, then N
+    // every body's diameter is under 127 wavelengths, so the phase less the
+    // per-(wavefront, source body) whole revolutions floor(min (|p| - r_b) k/2pi)
+    // stays inside the hardware sin/cos input range (ring and MFMA orders rely on it)
+    bool near_phase_ok = false;
 
     // timing
     bool timing = false;

@@ -38,6 +38,12 @@ __device__ __forceinline__ void sincos_rev(float ph, float &s, float &c) {
     s = __builtin_amdgcn_sinf(f);            // hardware sin/cos take revolutions
     c = __builtin_amdgcn_cosf(f);
 }
+// the same for |ph| <= 256 revolutions, the documented input range of the
+// hardware sin/cos, which reduce the argument themselves
+__device__ __forceinline__ void sincos_rev_near(float ph, float &s, float &c) {
+    s = __builtin_amdgcn_sinf(ph);
+    c = __builtin_amdgcn_cosf(ph);
+}
 
 // sin and cos of 2 pi t (t in revolutions) in FP64: reduction to an octant,
 // r = t - k/4 in [-1/8, 1/8] exactly, x = 2 pi r in [-pi/4, pi/4], Taylor
@@ -71,6 +77,21 @@ __device__ __forceinline__ void sincos_rev(double t, double &s, double &c) {
     const double a = (q & 1) ? cx : sx, b = (q & 1) ? sx : cx;
     s = (q & 2) ? -a : a;
     c = ((q + 1) & 2) ? -b : b;
+}
+__device__ __forceinline__ void sincos_rev_near(double t, double &s, double &c) { sincos_rev(t, s, c); }
+
+// floor(max(min over the wavefront of v, 0)), the same in every lane; in FP32
+// moved to a scalar register so that the phase FMA reads two VGPRs, not three
+__device__ __forceinline__ float wave_floor_min(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    v = floorf(fmaxf(v, 0.f));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double wave_floor_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return floor(fmax(v, 0.0));
 }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 // 1/sqrt(x) for finite x > 0: hardware estimate refined by two Newton steps
@@ -224,7 +245,7 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
     const R twopi = R(6.283185307179586476925287);
 
     R tx[TPT], ty[TPT], tz[TPT];
-    R px[TPT], py[TPT], pz[TPT];
+    R px[TPT], py[TPT], pz[TPT], n0 = R(0);
     R ar[TPT][NR], ai[TPT][NR];
 #pragma unroll
     for (int k = 0; k < TPT; ++k) {
@@ -272,15 +293,23 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
             for (int ring = r0; ring < r1; ++ring) {
                 const int b = rt.body[ring];
                 if (b != prev_body) {
-                    // targets in the source body's frame: p = Rot^T (x - c)
-                    const R *f = frame + 12 * b;
+                    // targets in the source body's frame: p = Rot^T (x - c).  Every
+                    // source of the body is at R' >= (|p| - r_b)k/2pi, and the
+                    // wavefront's targets lie in one body of radius r_t, so the
+                    // phase less the whole revolutions n0 = floor(min (|p| - r_b)k/2pi)
+                    // stays in [0, 2 (r_t + r_b) k/2pi + 1]
+                    const R *f = frame + FRAME * b;
+                    R m = R(1e30);
 #pragma unroll
                     for (int k = 0; k < TPT; ++k) {
                         const R dx = tx[k] - f[0], dy = ty[k] - f[1], dz = tz[k] - f[2];
                         px[k] = fma(f[3], dx, fma(f[6], dy, f[9] * dz));
                         py[k] = fma(f[4], dx, fma(f[7], dy, f[10] * dz));
                         pz[k] = fma(f[5], dx, fma(f[8], dy, f[11] * dz));
+                        const R pn = sqrt(fma(px[k], px[k], fma(py[k], py[k], pz[k] * pz[k])));
+                        m = fmin(m, (pn - f[12]) * k2pi);
                     }
+                    n0 = wave_floor_min(m);
                     prev_body = b;
                 }
                 const R rj = rr_[ring], zj = rz_[ring], nrj = rnr[ring], nzj = rnz[ring];
@@ -299,7 +328,7 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                     By[k] = (c1 * nrj) * py[k];
                     be[k] = fma(nzj, pzp, -nrj * rj) * c1;
                 }
-#pragma unroll(sizeof(R) == 4 ? 2 : 1)
+#pragma unroll sizeof(R) == 4 ? 2 : 1
                 for (int l = 0; l < nf; ++l) {
                     const R *s = src + l * ST;
                     const R cl = s[0], sl = s[1];
@@ -315,7 +344,7 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                         const R nd = fma(Bx[k], cl, fma(By[k], sl, be[k]));
                         const R u = rsq(r2);                  // 1 / R'
                         R sn, cs_;
-                        sincos_rev(r2 * u, sn, cs_);          // phase R' = kR / 2pi revolutions
+                        sincos_rev_near(fma(r2, u, -n0), sn, cs_);   // phase R' = kR / 2pi revolutions
                         const R t = nd * (u * u);
                         const R P = t * u;                    // n.d / R^3
                         const R Q = fma(-twopi, t, etap * u);  // eta / R - k n.d / R^2
@@ -344,6 +373,233 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                 part[((int64_t)w.slot * nrhs + cb + c) * N + w.t0 + t] = v;
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA-assisted source order (FP32, kappa > 0).  With the source y and its
+// normal n in the source body's frame and the target p = Rot^T (x - c) in the
+// same frame,
+//   R'^2 = s2 (|p|^2 - 2 p.y + |y|^2),   nd' = c1 n.(p - y)
+// (s2 = (k/2pi)^2, c1 = (k/2pi)^3, so R' is the phase in revolutions) are
+// 16 x 16 blocks (sources x targets) of the products of the 4-vectors
+// [s2(-2y, |y|^2)] and [p, 1] plus s2 |p|^2, and of [c1(n, -n.y)] and [p, 1]:
+// one v_mfma_f32_16x16x4f32 each per 256 pairs, which takes the four FMAs of
+// R^2 and n.d per pair off the VALU.  Since |y| is at most the body's bounding
+// radius and R at least the gap to the next body, the cancellation in
+// |p|^2 - 2p.y + |y|^2 stays bounded.  A wave owns G groups of 16 targets;
+// lane l receives sources 4(l/16)+v (v = 0..3) of the block for target l%16
+// of each group.
+//   NR < 16 right-hand sides: the complex multiply-accumulate stays on the
+//   VALU; the four source partial sums of a target are added across lanes at
+//   the end (fixed order).
+//   NR = 16: the multiply-accumulate is MFMA too: per group and per v, the
+//   16 x 4 block of kernel values (targets x sources 4k+v, taken straight from
+//   the lanes that computed them) times the 4 x 16 block of densities
+//   (sources x right-hand sides), four real MFMAs for the complex product.
+// Sources are staged through LDS in chunks of MF_CH nodes of one body, padded
+// with zero densities to a multiple of 16.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int MF_CH = 256;
+
+__device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// 4 pi G from R'^2 and nd' (the same arithmetic as the ring order)
+__device__ __forceinline__ void kernel_value(float r2, float nd, float n0, float etap, float &gr, float &gi) {
+    const float u = rsq(r2);               // 1 / R'
+    float sn, cs_;
+    sincos_rev_near(fma(r2, u, -n0), sn, cs_);   // R' less whole revolutions n0
+    const float t = nd * (u * u);
+    const float P = t * u;                 // n.d / R^3
+    const float Q = fma(-6.283185307179586f, t, etap * u);   // eta / R - k n.d / R^2
+    gr = fma(cs_, P, -sn * Q);
+    gi = fma(cs_, Q, sn * P);
+}
+
+// the body whose node range holds node s: boff[b] <= s < boff[b + 1]
+__device__ __forceinline__ int body_of(const int64_t *__restrict__ boff, int nb, int64_t s) {
+    int lo = 0, hi = nb - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boff[mid] <= s) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int G, int NR>
+__global__ __launch_bounds__(256) void interbody_mfma_kernel(
+    const IBWork *__restrict__ work, const float *__restrict__ geo, const f32x4 *__restrict__ sop,
+    const float2 *__restrict__ q, const int64_t *__restrict__ boff, int nbodies,
+    const float *__restrict__ frame, int64_t N, int nrhs, int c0, float s2, float etap,
+    float2 *__restrict__ part) {
+    constexpr bool MACC = NR == 16;
+    static_assert(NR == 1 || NR == 2 || NR == 4 || NR == 8 || NR == 16, "rhs group");
+    __shared__ f32x4 s_sr[MF_CH], s_sn[MF_CH];
+    // densities: NR < 16 as [src][c](re, im); NR = 16 as planes re[src][c], im[src][c]
+    __shared__ float s_q[MF_CH * 2 * NR];
+
+    const IBWork w = work[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int cb = c0 + blockIdx.y * NR;
+    const float *gx = geo, *gy = geo + N, *gz = geo + 2 * N;
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+
+    float tx[G], ty[G], tz[G], bT[G], n0 = 0.f;
+    f32x4 cR[G];
+    float ar[G][MACC ? 1 : NR], ai[G][MACC ? 1 : NR];
+    f32x4 kr[G], ki[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int t = (wv * G + g) * 16 + col;
+        const int64_t gi = w.t0 + (t < w.tn ? t : 0);
+        tx[g] = gx[gi];
+        ty[g] = gy[gi];
+        tz[g] = gz[gi];
+        bT[g] = 0.f;
+        cR[g] = zero4;
+        kr[g] = ki[g] = zero4;
+#pragma unroll
+        for (int c = 0; c < (MACC ? 1 : NR); ++c) ar[g][c] = ai[g][c] = 0.f;
+    }
+    int prev = -1;
+
+#pragma unroll 1
+    for (int rng = 0; rng < 2; ++rng) {
+        const int64_t lo = rng == 0 ? w.s0 : w.s2;
+        const int64_t hi = rng == 0 ? w.s1 : w.s3;
+        int64_t s = lo;
+#pragma unroll 1
+        while (s < hi) {
+            const int b = body_of(boff, nbodies, s);
+            const int64_t e = min(hi, min(boff[b + 1], s + (int64_t)MF_CH));
+            const int n = (int)(e - s), n16 = (n + 15) & ~15;
+            if (b != prev) {
+                // B operand: component kq of (p, 1); C operand: s2 |p|^2;
+                // whole revolutions n0 as in the ring order
+                const float *f = frame + FRAME * b;
+                const float k2pi = sqrtf(s2);
+                float m = 1e30f;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const float dx = tx[g] - f[0], dy = ty[g] - f[1], dz = tz[g] - f[2];
+                    const float px = fma(f[3], dx, fma(f[6], dy, f[9] * dz));
+                    const float py = fma(f[4], dx, fma(f[7], dy, f[10] * dz));
+                    const float pz = fma(f[5], dx, fma(f[8], dy, f[11] * dz));
+                    bT[g] = kq == 0 ? px : kq == 1 ? py : kq == 2 ? pz : 1.f;
+                    const float p2 = fma(px, px, fma(py, py, pz * pz));
+                    const float c2 = s2 * p2;
+                    cR[g] = (f32x4){c2, c2, c2, c2};
+                    m = fminf(m, (sqrtf(p2) - f[12]) * k2pi);
+                }
+                n0 = wave_floor_min(m);
+                prev = b;
+            }
+            __syncthreads();
+            for (int i = tid; i < n16; i += 256) {
+                const bool ok = i < n;
+                s_sr[i] = ok ? sop[s + i] : zero4;
+                s_sn[i] = ok ? sop[N + s + i] : zero4;
+#pragma unroll
+                for (int c = 0; c < NR; ++c) {
+                    const float2 v = ok ? q[(int64_t)(cb + c) * N + s + i] : make_float2(0.f, 0.f);
+                    if constexpr (MACC) {
+                        s_q[i * 16 + c] = v.x;
+                        s_q[MF_CH * 16 + i * 16 + c] = v.y;
+                    } else {
+                        s_q[2 * (i * NR + c)] = v.x;
+                        s_q[2 * (i * NR + c) + 1] = v.y;
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int j = 0; j < n16; j += 16) {
+                const float a1 = ((const float *)s_sr)[(j + col) * 4 + kq];
+                const float a2 = ((const float *)s_sn)[(j + col) * 4 + kq];
+                if constexpr (!MACC) {
+                    float qr[4][NR], qi[4][NR];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+#pragma unroll
+                        for (int c = 0; c < NR; ++c) {
+                            const int ix = 2 * ((j + 4 * kq + v) * NR + c);
+                            qr[v][c] = s_q[ix];
+                            qi[v][c] = s_q[ix + 1];
+                        }
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const f32x4 d1 = mfma_16x16x4(a1, bT[g], cR[g]);
+                        const f32x4 d2 = mfma_16x16x4(a2, bT[g], zero4);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            float gr, gi;
+                            kernel_value(d1[v], d2[v], n0, etap, gr, gi);
+#pragma unroll
+                            for (int c = 0; c < NR; ++c) {
+                                ar[g][c] = fma(gr, qr[v][c], fma(-gi, qi[v][c], ar[g][c]));
+                                ai[g][c] = fma(gr, qi[v][c], fma(gi, qr[v][c], ai[g][c]));
+                            }
+                        }
+                    }
+                } else {
+                    float bqr[4], bqi[4], bqn[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int src = j + 4 * kq + v;
+                        bqr[v] = s_q[src * 16 + col];
+                        bqi[v] = s_q[MF_CH * 16 + src * 16 + col];
+                        bqn[v] = -bqi[v];
+                    }
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const f32x4 d1 = mfma_16x16x4(a1, bT[g], cR[g]);
+                        const f32x4 d2 = mfma_16x16x4(a2, bT[g], zero4);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            float gr, gi;
+                            kernel_value(d1[v], d2[v], n0, etap, gr, gi);
+                            kr[g] = mfma_16x16x4(gr, bqr[v], kr[g]);
+                            kr[g] = mfma_16x16x4(gi, bqn[v], kr[g]);
+                            ki[g] = mfma_16x16x4(gr, bqi[v], ki[g]);
+                            ki[g] = mfma_16x16x4(gi, bqr[v], ki[g]);
+                        }
+                    }
+                }
+            }
+            s = e;
+        }
+    }
+
+    if constexpr (!MACC) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int t = (wv * G + g) * 16 + col;
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                float xr = ar[g][c], xi = ai[g][c];
+                xr += __shfl_xor(xr, 16, 64);
+                xi += __shfl_xor(xi, 16, 64);
+                xr += __shfl_xor(xr, 32, 64);
+                xi += __shfl_xor(xi, 32, 64);
+                if (kq == 0 && t < w.tn)
+                    part[((int64_t)w.slot * nrhs + cb + c) * N + w.t0 + t] = make_float2(xr, xi);
+            }
+        }
+    } else {
+        // lane l holds targets 4(l/16)+v of each group for right-hand side l%16
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int t = (wv * G + g) * 16 + 4 * kq + v;
+                if (t < w.tn)
+                    part[((int64_t)w.slot * nrhs + cb + col) * N + w.t0 + t] = make_float2(kr[g][v], ki[g][v]);
+            }
     }
 }
 
@@ -382,6 +638,9 @@ struct IBShape {
     int variant, tpt, bs, splits;
 };
 
+// targets per work item: TPT x block, or for the MFMA order 16 x G x 4 waves
+static int ib_tile(const IBShape &s) { return s.variant == 3 ? 64 * s.tpt : s.tpt * s.bs; }
+
 static IBShape launch_shape(Ctx &c, int prec) {
     const int pi = prec == AXS_FP32 ? 1 : 0;
     IBShape s;
@@ -389,16 +648,23 @@ static IBShape launch_shape(Ctx &c, int prec) {
     // FP32 rings x 2 targets per thread, FP64 points x 4 targets per thread
     s.tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : (prec == AXS_FP32 ? 2 : 4);
     s.bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : 256;
-    const bool ring_ok = c.kappa > 0 && c.max_nf <= s.bs;
+    const bool ring_ok = c.kappa > 0 && c.max_nf <= s.bs && c.near_phase_ok;
     s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi] : ((ring_ok && prec == AXS_FP32) ? 2 : 1);
-    AXS_REQUIRE(s.variant == 1 || ring_ok, AXS_EINVAL,
-                "ring variant needs kappa > 0 and N_F <= threads per block");
+    AXS_REQUIRE(s.variant != 2 || ring_ok, AXS_EINVAL,
+                "ring variant needs kappa > 0, N_F <= threads per block and bodies under 127 wavelengths across");
+    if (s.variant == 3) {
+        AXS_REQUIRE(prec == AXS_FP32 && c.kappa > 0 && c.mf_src && c.near_phase_ok, AXS_EINVAL,
+                    "MFMA variant needs FP32, kappa > 0 and bodies under 127 wavelengths across");
+        AXS_REQUIRE(s.tpt == 1 || s.tpt == 2 || s.tpt == 4, AXS_EINVAL,
+                    "MFMA variant: 1, 2 or 4 groups of 16 targets per wave");
+        AXS_REQUIRE(s.bs == 256, AXS_EINVAL, "MFMA variant uses 256-thread blocks");
+    }
     if (c.ib_splits[pi] > 0) {
         s.splits = c.ib_splits[pi];
     } else {
         // enough blocks to fill 256 CUs several times over
         int64_t tiles = 0;
-        for (auto &b : c.bodies) tiles += ceil_div(b.n, (int64_t)s.tpt * s.bs);
+        for (auto &b : c.bodies) tiles += ceil_div(b.n, (int64_t)ib_tile(s));
         s.splits = 1;
         while (tiles * s.splits < 4096 && s.splits < 64) s.splits *= 2;
     }
@@ -406,6 +672,14 @@ static IBShape launch_shape(Ctx &c, int prec) {
 }
 
 int interbody_splits(Ctx &c, int prec) { return launch_shape(c, prec).splits; }
+
+void interbody_shape(Ctx &c, int prec, int out[4]) {
+    const IBShape s = launch_shape(c, prec);
+    out[0] = s.variant;
+    out[1] = s.tpt;
+    out[2] = s.bs;
+    out[3] = s.splits;
+}
 
 // Work items: every body-aligned tile of `tile` targets against `splits`
 // chunks of the source units (nodes or rings) outside the target's body.
@@ -458,6 +732,8 @@ void build_ring_tables(Ctx &c) {
         c.max_nf = std::max(c.max_nf, s.NF);
         for (int a = 0; a < 3; ++a) fr.push_back(b.centre[a]);
         for (int a = 0; a < 9; ++a) fr.push_back(b.rot[a]);
+        fr.push_back(b.bound_radius);
+        for (int a = 13; a < FRAME; ++a) fr.push_back(0.0);
         for (int l = 0; l < s.NF; ++l) {
             const double th = 2.0 * M_PI * l / s.NF;
             for (int i = 0; i < s.NG; ++i) {
@@ -468,6 +744,10 @@ void build_ring_tables(Ctx &c) {
         }
     }
     c.nrings = nr;
+    // phases less whole revolutions stay below 2 (r_t + r_s) k/2pi + 1 revolutions
+    double rmax = 0;
+    for (auto &b : c.bodies) rmax = std::max(rmax, b.bound_radius);
+    c.near_phase_ok = 4.0 * rmax * c.kappa / (2.0 * M_PI) + 2.0 < 256.0;
     std::vector<int32_t> off(nr), nf(nr), body(nr);
     std::vector<double> g(4 * (size_t)nr);
     for (size_t bi = 0; bi < c.bodies.size(); ++bi) {
@@ -500,6 +780,41 @@ void build_ring_tables(Ctx &c) {
     up(g, c.ring_g64, c.ring_g32);
     up(fr, c.frame64, c.frame32);
     up(csv, c.cs64, c.cs32);
+
+    std::vector<int64_t> bo;
+    for (auto &b : c.bodies) bo.push_back(b.offset);
+    bo.push_back(N);
+    c.body_off = (int64_t *)c.dalloc(bo.size() * sizeof(int64_t));
+    AXS_HIP(hipMemcpy(c.body_off, bo.data(), bo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (c.kappa > 0) {
+        // MFMA source operands in each body's frame, scaled so that the
+        // products give R'^2 and nd' of the ring order directly
+        const double k2pi = c.kappa / (2.0 * M_PI), s2 = k2pi * k2pi, c1 = s2 * k2pi;
+        std::vector<float> mf(8 * (size_t)N);
+        for (size_t bi = 0; bi < c.bodies.size(); ++bi) {
+            const auto &b = c.bodies[bi];
+            const Shape &s = c.shapes[b.shape];
+            for (int i = 0; i < s.NG; ++i) {
+                const double sp = std::hypot(s.dr[i], s.dz[i]);
+                const double nr = -s.dz[i] / sp, nz = s.dr[i] / sp;
+                for (int l = 0; l < s.NF; ++l) {
+                    const double th = 2.0 * M_PI * l / s.NF, ct = std::cos(th), st = std::sin(th);
+                    const double y[3] = {s.r[i] * ct, s.r[i] * st, s.z[i]};
+                    const double n[3] = {nr * ct, nr * st, nz};
+                    const int64_t j = b.offset + (int64_t)i * s.NF + l;
+                    float *a = &mf[4 * j], *d = &mf[4 * (N + j)];
+                    for (int k = 0; k < 3; ++k) {
+                        a[k] = (float)(-2.0 * s2 * y[k]);
+                        d[k] = (float)(c1 * n[k]);
+                    }
+                    a[3] = (float)(s2 * (y[0] * y[0] + y[1] * y[1] + y[2] * y[2]));
+                    d[3] = (float)(-c1 * (n[0] * y[0] + n[1] * y[1] + n[2] * y[2]));
+                }
+            }
+        }
+        c.mf_src = (float *)c.dalloc(mf.size() * sizeof(float));
+        AXS_HIP(hipMemcpy(c.mf_src, mf.data(), mf.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
 }
 
 template <typename R, int TPT, int BS>
@@ -551,10 +866,46 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
     }
 }
 
+// MFMA order: full groups of 16 right-hand sides use MFMA accumulation, the
+// remainder groups of 8, 4, 2, 1 the VALU one.
+template <int G>
+static void launch_mf(Ctx &c, const IBWork *work, int nwork, const float2 *q, int nrhs, float2 *part) {
+    const float k2pi = (float)(c.kappa / (2.0 * M_PI));
+    const float s2 = k2pi * k2pi, etap = (float)c.eta * k2pi;
+    const f32x4 *sop = (const f32x4 *)c.mf_src;
+    const int nb = (int)c.bodies.size();
+    int c0 = 0;
+    while (c0 < nrhs) {
+        const int left = nrhs - c0;
+        const int nr = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+        const int groups = left / nr;
+#define AXS_MF_NR(NR_)                                                                                   \
+    if (nr == NR_)                                                                                      \
+        hipLaunchKernelGGL((interbody_mfma_kernel<G, NR_>), dim3(nwork, groups), dim3(256), 0, c.stream, \
+                           work, c.g32, sop, q, c.body_off, nb, c.frame32, c.N, nrhs, c0, s2, etap, part);
+        AXS_MF_NR(16)
+        AXS_MF_NR(8)
+        AXS_MF_NR(4)
+        AXS_MF_NR(2)
+        AXS_MF_NR(1)
+#undef AXS_MF_NR
+        AXS_HIP(hipGetLastError());
+        c0 += nr * groups;
+    }
+}
+
 template <typename R>
 static void dispatch_ib(Ctx &c, const IBShape &s, const IBWork *work, int nwork, const R *geo, const R *cs,
                         const R *rg, const R *frame, const typename C2T<R>::T *q, int nrhs,
                         typename C2T<R>::T *part) {
+    if constexpr (sizeof(R) == 4) {
+        if (s.variant == 3) {
+            if (s.tpt == 1) launch_mf<1>(c, work, nwork, q, nrhs, part);
+            else if (s.tpt == 2) launch_mf<2>(c, work, nwork, q, nrhs, part);
+            else launch_mf<4>(c, work, nwork, q, nrhs, part);
+            return;
+        }
+    }
 #define AXS_IB_CASE(T_, B_)                                                             \
     if (s.tpt == T_ && s.bs == B_) {                                                    \
         launch_ib<R, T_, B_>(c, s.variant, work, nwork, geo, cs, rg, frame, q, nrhs, part); \
@@ -578,7 +929,7 @@ void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
     if (!c.ib_work[pi] || c.ib_key[pi][0] != s.tpt || c.ib_key[pi][1] != s.bs || c.ib_key[pi][2] != s.splits ||
         c.ib_key[pi][3] != s.variant) {
         // work tables are cached per launch shape; rebuilt only when it changes
-        std::vector<IBWork> work = build_work(c, s.tpt * s.bs, s.splits, rings);
+        std::vector<IBWork> work = build_work(c, ib_tile(s), s.splits, rings);
         if (c.ib_work[pi]) {
             AXS_HIP(hipStreamSynchronize(c.stream));
             c.dfree(c.ib_work[pi]);

@@ -347,6 +347,8 @@ static std::vector<double> norms(Ctx &c, const double2 *v, int64_t N, int nrhs) 
 axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *sigma_out, int nrhs, int mode,
                       double tol, int max_iters, axs_solve_info *info) {
     const auto t0 = std::chrono::steady_clock::now();
+    const bool certify = (mode & AXS_SOLVE_CERTIFY) != 0;
+    mode &= ~AXS_SOLVE_CERTIFY;
     const int64_t N = c.N, tot = N * nrhs;
     const size_t vb = (size_t)tot * sizeof(double2);
     double2 *x = (double2 *)sigma_out;
@@ -412,16 +414,22 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
         c.dfree(Vi);
     }
     c.dfree(V);
-    // certified FP64 residual of the returned solution
-    apply_operator(c, x, tmp, nrhs, AXS_FP64);
-    hipLaunchKernelGGL(csub_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, b, tmp, tmp, tot);
-    AXS_HIP(hipGetLastError());
-    std::vector<double> rn = norms(c, tmp, N, nrhs);
+    std::vector<double> relv = est;
+    if (certify) {
+        // explicit FP64 residual of the returned solution
+        apply_operator(c, x, tmp, nrhs, AXS_FP64);
+        hipLaunchKernelGGL(csub_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, b, tmp, tmp, tot);
+        AXS_HIP(hipGetLastError());
+        std::vector<double> rn = norms(c, tmp, N, nrhs);
+        for (int cc = 0; cc < nrhs; ++cc) relv[cc] = rn[cc] / bn[cc];
+    } else {
+        AXS_HIP(hipStreamSynchronize(c.stream));
+    }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bool all_ok = true;
     for (int cc = 0; cc < nrhs; ++cc) {
-        AXS_REQUIRE(std::isfinite(rn[cc]), AXS_ENONFINITE, "non-finite final residual");
-        const double rel = rn[cc] / bn[cc];
+        AXS_REQUIRE(std::isfinite(relv[cc]), AXS_ENONFINITE, "non-finite final residual");
+        const double rel = relv[cc];
         if (info) {
             info[cc].iterations = outer[cc];
             info[cc].inner_iterations = inner_total[cc];

@@ -205,7 +205,7 @@ __global__ void modes_from_density_kernel(const BodyDev *__restrict__ bodies, co
     if (t >= bd.NG * nm) return;
     const int i = t / nm, mi = t % nm, m = mi - mmax;
     const double *d = dirs + 3 * c;
-    const double ph = kappa * (d[0] * frame[12 * b] + d[1] * frame[12 * b + 1] + d[2] * frame[12 * b + 2]);
+    const double ph = kappa * (d[0] * frame[FRAME * b] + d[1] * frame[FRAME * b + 1] + d[2] * frame[FRAME * b + 2]);
     double sr = 0, si = 0;
     const double2 *row = sigma + (int64_t)c * N + bd.offset + (int64_t)i * bd.NF;
     for (int l = 0; l < bd.NF; ++l) {
@@ -233,7 +233,7 @@ __global__ void density_from_modes_kernel(const BodyDev *__restrict__ bodies, co
     const int i = t / bd.NF, l = t % bd.NF;
     const int nm = 2 * mmax + 1;
     const double *d = dirs + 3 * c;
-    const double ph = kappa * (d[0] * frame[12 * b] + d[1] * frame[12 * b + 1] + d[2] * frame[12 * b + 2]);
+    const double ph = kappa * (d[0] * frame[FRAME * b] + d[1] * frame[FRAME * b + 1] + d[2] * frame[FRAME * b + 2]);
     const float *cf = coeff + (int64_t)c * P + coff[b] + 2 * (int64_t)i * nm;
     double sr = 0, si = 0;
     for (int mi = 0; mi < nm; ++mi) {

@@ -197,6 +197,24 @@ def test_solves_match_dense_reference(small):
         assert all(i["rel_residual"] <= 1e-11 for i in info)
 
 
+def test_gmres_residual_equals_explicit_residual(small):
+    """The residual GMRES reports (least squares in its FP64 Arnoldi basis) is the
+    explicit FP64 residual of the returned sigma up to rounding: the certified
+    solve (one more FP64 application) returns the same sigma bit for bit and a
+    residual within 1e-13 of it, for both solvers."""
+    from paper_1406_0236_amd import SOLVE_FP64, SOLVE_MIXED
+    wl, S, ctx = small
+    vd = ctx.incident_plane_waves(np.array([[0.0, 0.6, 0.8], [0.48, -0.6, 0.64]]))
+    for mode in (SOLVE_FP64, SOLVE_MIXED):
+        x1, i1 = ctx.solve(vd, mode=mode, tol=1e-9, max_iters=100)
+        x2, i2 = ctx.solve(vd, mode=mode, tol=1e-9, max_iters=100, certify=True)
+        assert torch.equal(x1, x2)
+        for a, b in zip(i1, i2):
+            print(f"mode {mode}: GMRES {a['rel_residual']:.3e} explicit {b['rel_residual']:.3e}")
+            assert abs(a["rel_residual"] - b["rel_residual"]) <= 1e-13
+            assert a["converged"] and b["converged"]
+
+
 def test_warm_start_is_used_and_bad_guess_is_dropped(small):
     from paper_1406_0236_amd import SOLVE_FP64
     wl, S, ctx = small
@@ -253,6 +271,8 @@ def test_error_paths():
         ctx.build_body(s.rz, s.drz, s.gw, s.n_panels, s.p, 1.0, 1.0, 4, [5.0, 0, 0], np.eye(3))
     with pytest.raises(AxsError, match="EINVAL"):   # output overlaps input
         ctx.apply_matvec(y, FP64, out=y)
+    with pytest.raises(AxsError, match="EINVAL"):   # the MFMA order is FP32 only
+        ctx.set_interbody_config(FP64, 3, 2, 256, 0)
     # a single body: no inter-body terms, the operator is the identity
     z = torch.from_numpy(_rand(ctx.N, 1, 3)).to("cuda:0")
     assert torch.equal(ctx.apply_matvec(z, FP64), z)
@@ -379,3 +399,55 @@ def test_wide_rhs_groups_fp32_rings(small):
         print(f"tpt {tpt}: rel err {e:.2e}")
         assert e < 3e-5, e
     ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+
+
+def test_mfma_source_order_matches_reference(small):
+    """FP32 MFMA order: R^2 and n.d from 16x16x4 MFMAs, 1, 2 or 4 groups of 16
+    targets per wave, several splits; 3 right-hand sides (VALU accumulation in
+    groups of 2 and 1)."""
+    from paper_1406_0236_amd import FP32
+    wl, S, ctx = small
+    x = _rand(S.N, 3, 91)
+    ref = S.apply_B(x.T).T
+    for g, splits in ((1, 1), (2, 3), (4, 0), (2, 16)):
+        ctx.set_interbody_config(FP32, 3, g, 256, splits)
+        y = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
+        e = rel(y, ref)
+        print(f"G {g} splits {splits}: rel err {e:.2e}")
+        assert e < 3e-5, (g, splits, e)
+    ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+
+
+def test_mfma_accumulation_16_wide(small):
+    """37 right-hand sides: two 16-wide groups with the complex multiply-accumulate
+    on MFMA, then VALU groups of 4 and 1; every column against the reference,
+    and the same result bit for bit on a second call."""
+    from paper_1406_0236_amd import FP32
+    wl, S, ctx = small
+    x = _rand(S.N, 37, 92)
+    ref = S.apply_B(x.T).T
+    for g in (1, 2, 4):
+        ctx.set_interbody_config(FP32, 3, g, 256, 0)
+        y = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
+        e = rel(y, ref)
+        print(f"G {g}: rel err {e:.2e}")
+        assert e < 3e-5, (g, e)
+        y2 = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
+        assert np.array_equal(y, y2)
+    ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+
+
+def test_mfma_source_order_mixed_bodies_64_rhs(mixed):
+    """Rotated spheroids and bowls, 8 bodies of three shapes, 64 right-hand sides
+    (four MFMA-accumulated groups of 16); three columns against the reference."""
+    from paper_1406_0236_amd import FP32
+    wl, S, ctx = mixed
+    sig = _rand(S.N, 64, 93)
+    picks = [0, 17, 63]
+    ref = S.apply_B(sig[picks].T).T
+    ctx.set_interbody_config(FP32, 3, 2, 256, 0)
+    y = ctx.apply_interbody(_dev(sig), FP32).cpu().numpy()[picks]
+    ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+    e = rel(y, ref)
+    print(f"mixed bodies, MFMA order, 64 rhs: rel err {e:.2e}")
+    assert e < 3e-5, e
