@@ -201,12 +201,13 @@ axs_status axs_last_timing(axs_ctx *ctx, double ms[5]);
 axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant,
                                     int targets_per_thread, int block, int splits);
 
-/* The launch shape the next inter-body application in `precision` will use,
- * defaults resolved: out[0..3] = variant, targets per thread (variant 3: groups
- * of 16 targets per wavefront), block, splits.  out: host int[4].
- * AXS_ESTATE before axs_precompute_scattering; AXS_EINVAL if the configured
- * shape does not fit the context. */
-axs_status axs_interbody_launch_shape(axs_ctx *ctx, int precision, int *out);
+/* The launch shape an inter-body application in `precision` on nrhs right-hand
+ * sides will use, defaults resolved: out[0..3] = variant, targets per thread
+ * (variant 3: groups of 16 targets per wavefront), block, splits.  out: host
+ * int[4].  The FP32 default is the ring order below 16 right-hand sides and the
+ * MFMA order from 16 on.  AXS_ESTATE before axs_precompute_scattering;
+ * AXS_EINVAL if the configured shape does not fit the context. */
+axs_status axs_interbody_launch_shape(axs_ctx *ctx, int precision, int nrhs, int *out);
 
 /* ------------------------------------------------------------------------ *
  * Learned warm start.  A multilayer perceptron maps (incident direction,

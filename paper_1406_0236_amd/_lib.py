@@ -70,7 +70,8 @@ EXPORTS = {
                                        ctypes.c_int, ctypes.c_void_p]),
     "axs_set_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int]),
     "axs_last_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
-    "axs_interbody_launch_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "axs_interbody_launch_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                                    ctypes.POINTER(ctypes.c_int)]),
     "axs_set_interbody_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                   ctypes.c_int, ctypes.c_int]),
     "axs_mlp_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -286,10 +287,10 @@ class Context:
         self._check(self.lib.axs_set_interbody_config(self.h, int(precision), int(variant), int(targets_per_thread),
                                                       int(block), int(splits)))
 
-    def interbody_launch_shape(self, precision):
-        """The resolved launch shape (variant, targets_per_thread, block, splits)."""
+    def interbody_launch_shape(self, precision, nrhs=1):
+        """The resolved launch shape (variant, targets_per_thread, block, splits) for nrhs."""
         out = (ctypes.c_int * 4)()
-        self._check(self.lib.axs_interbody_launch_shape(self.h, int(precision), out))
+        self._check(self.lib.axs_interbody_launch_shape(self.h, int(precision), int(nrhs), out))
         return tuple(int(v) for v in out)
 
 

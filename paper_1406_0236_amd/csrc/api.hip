@@ -13,7 +13,7 @@ namespace axs {
 void gauss_legendre_public(int n, std::vector<double> &x, std::vector<double> &w);
 void split_planar(Ctx &c, Shape &s, double *r64, double *i64, float *r32, float *i32);
 void build_ring_tables(Ctx &c);
-void interbody_shape(Ctx &c, int prec, int out[4]);
+void interbody_shape(Ctx &c, int prec, int nrhs, int out[4]);
 
 void *Ctx::dalloc(size_t bytes) {
     if (bytes == 0) bytes = 256;
@@ -86,7 +86,7 @@ void apply_operator(Ctx &c, const void *sigma, void *y, int nrhs, int prec) {
     rec(c, 0);
     interbody_partials(c, sigma, nrhs, prec);
     rec(c, 1);
-    dft_forward(c, prec, 0, nullptr, nrhs, interbody_splits(c, prec));
+    dft_forward(c, prec, 0, nullptr, nrhs, interbody_splits(c, prec, nrhs));
     rec(c, 2);
     modal_gemm(c, prec, nrhs);
     rec(c, 3);
@@ -581,12 +581,13 @@ axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant, in
     });
 }
 
-axs_status axs_interbody_launch_shape(axs_ctx *ctx, int precision, int *out) {
+axs_status axs_interbody_launch_shape(axs_ctx *ctx, int precision, int nrhs, int *out) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         AXS_REQUIRE(out, AXS_EINVAL, "null output");
         AXS_REQUIRE(precision == AXS_FP64 || precision == AXS_FP32, AXS_EINVAL, "bad precision");
+        AXS_REQUIRE(nrhs >= 1, AXS_EINVAL, "nrhs must be positive");
         AXS_REQUIRE(c.precomputed, AXS_ESTATE, "call axs_precompute_scattering first");
-        interbody_shape(c, precision, out);
+        interbody_shape(c, precision, nrhs, out);
         return AXS_OK;
     });
 }

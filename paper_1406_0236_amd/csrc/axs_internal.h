@@ -129,9 +129,11 @@ struct Ctx {
     int ngemm = 0, gemm_max_cols = 0, max_NG = 0;
 
     // cached inter-body work tables, per precision (0 = fp64, 1 = fp32)
-    IBWork *ib_work[2] = {nullptr, nullptr};
-    int ib_nwork[2] = {0, 0};
-    int ib_key[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    // [precision][0: point / ring orders, 1: MFMA order], so that alternating
+    // single and batched calls do not rebuild them
+    IBWork *ib_work[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    int ib_nwork[2][2] = {{0, 0}, {0, 0}};
+    int ib_key[2][2][4] = {};
 
     // launch configuration of the inter-body sum (0 = library default)
     int ib_variant[2] = {0, 0};   // 1 = point sources, 2 = azimuthal rings, 3 = MFMA (FP32)
@@ -202,7 +204,7 @@ void precompute_shape(Ctx &c, Shape &s);
 // interbody.hip
 void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec);   // -> WS_PART
 void interbody_reduce_to_c128(Ctx &c, void *y, int nrhs, int prec);        // WS_PART -> y
-int interbody_splits(Ctx &c, int prec);
+int interbody_splits(Ctx &c, int prec, int nrhs);
 void eval_field_launch(Ctx &c, const void *sigma, int nrhs, const double *tgt_dev, int nt,
                        void *u);
 void far_field_launch(Ctx &c, const void *sigma, int nrhs, const double *xh_dev, int nd,

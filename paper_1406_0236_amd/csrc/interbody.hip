@@ -396,7 +396,12 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
 //   NR = 16: the multiply-accumulate is MFMA too: per group and per v, the
 //   16 x 4 block of kernel values (targets x sources 4k+v, taken straight from
 //   the lanes that computed them) times the 4 x 16 block of densities
-//   (sources x right-hand sides), four real MFMAs for the complex product.
+//   (sources x right-hand sides), three real MFMAs for the complex product.
+// FP32 MFMAs and VALU instructions do not overlap on a SIMD (the co-execution
+// counter stays at zero for this kernel), and one 16x16x4 MFMA costs what the
+// 16 VALU FMAs it replaces cost, so the order pays off only where it takes
+// the complex multiply-accumulate of many right-hand sides at the matrix
+// cores' twice-VALU FMA rate.
 // Sources are staged through LDS in chunks of MF_CH nodes of one body, padded
 // with zero densities to a multiple of 16.
 // ---------------------------------------------------------------------------
@@ -452,7 +457,7 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
     float tx[G], ty[G], tz[G], bT[G], n0 = 0.f;
     f32x4 cR[G];
     float ar[G][MACC ? 1 : NR], ai[G][MACC ? 1 : NR];
-    f32x4 kr[G], ki[G];
+    f32x4 kr[G], ki[G], ks[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int t = (wv * G + g) * 16 + col;
@@ -462,7 +467,7 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
         tz[g] = gz[gi];
         bT[g] = 0.f;
         cR[g] = zero4;
-        kr[g] = ki[g] = zero4;
+        kr[g] = ki[g] = ks[g] = zero4;
 #pragma unroll
         for (int c = 0; c < (MACC ? 1 : NR); ++c) ar[g][c] = ai[g][c] = 0.f;
     }
@@ -547,13 +552,16 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
                         }
                     }
                 } else {
-                    float bqr[4], bqi[4], bqn[4];
+                    // complex product with three real MFMAs (Gauss):
+                    // K1 += Gr qr, K2 += Gi qi, K3 += (Gr + Gi)(qr + qi);
+                    // Re = K1 - K2, Im = K3 - K1 - K2 after the last source
+                    float bqr[4], bqi[4], bqs[4];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int src = j + 4 * kq + v;
                         bqr[v] = s_q[src * 16 + col];
                         bqi[v] = s_q[MF_CH * 16 + src * 16 + col];
-                        bqn[v] = -bqi[v];
+                        bqs[v] = bqr[v] + bqi[v];
                     }
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
@@ -564,9 +572,8 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
                             float gr, gi;
                             kernel_value(d1[v], d2[v], n0, etap, gr, gi);
                             kr[g] = mfma_16x16x4(gr, bqr[v], kr[g]);
-                            kr[g] = mfma_16x16x4(gi, bqn[v], kr[g]);
-                            ki[g] = mfma_16x16x4(gr, bqi[v], ki[g]);
-                            ki[g] = mfma_16x16x4(gi, bqr[v], ki[g]);
+                            ki[g] = mfma_16x16x4(gi, bqi[v], ki[g]);
+                            ks[g] = mfma_16x16x4(gr + gi, bqs[v], ks[g]);
                         }
                     }
                 }
@@ -598,7 +605,8 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
             for (int v = 0; v < 4; ++v) {
                 const int t = (wv * G + g) * 16 + 4 * kq + v;
                 if (t < w.tn)
-                    part[((int64_t)w.slot * nrhs + cb + col) * N + w.t0 + t] = make_float2(kr[g][v], ki[g][v]);
+                    part[((int64_t)w.slot * nrhs + cb + col) * N + w.t0 + t] =
+                        make_float2(kr[g][v] - ki[g][v], ks[g][v] - kr[g][v] - ki[g][v]);
             }
     }
 }
@@ -641,15 +649,20 @@ struct IBShape {
 // targets per work item: TPT x block, or for the MFMA order 16 x G x 4 waves
 static int ib_tile(const IBShape &s) { return s.variant == 3 ? 64 * s.tpt : s.tpt * s.bs; }
 
-static IBShape launch_shape(Ctx &c, int prec) {
+static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
     const int pi = prec == AXS_FP32 ? 1 : 0;
     IBShape s;
-    // defaults from the launch-shape sweep on MI355X (27-sphere lattice):
-    // FP32 rings x 2 targets per thread, FP64 points x 4 targets per thread
+    // defaults from the launch-shape sweeps on MI355X (27-sphere lattice, one
+    // rhs; 8 mixed bodies, 64 rhs): FP32 rings x 2 targets per thread below 16
+    // rhs, the MFMA order with 2 groups of 16 targets per wavefront from 16 rhs
+    // on, FP64 points x 4 targets per thread
     s.tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : (prec == AXS_FP32 ? 2 : 4);
     s.bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : 256;
     const bool ring_ok = c.kappa > 0 && c.max_nf <= s.bs && c.near_phase_ok;
-    s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi] : ((ring_ok && prec == AXS_FP32) ? 2 : 1);
+    const bool mf_default = prec == AXS_FP32 && nrhs >= 16 && c.kappa > 0 && c.mf_src && c.near_phase_ok &&
+                            s.bs == 256 && s.tpt <= 4;
+    s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi]
+                                     : mf_default ? 3 : ((ring_ok && prec == AXS_FP32) ? 2 : 1);
     AXS_REQUIRE(s.variant != 2 || ring_ok, AXS_EINVAL,
                 "ring variant needs kappa > 0, N_F <= threads per block and bodies under 127 wavelengths across");
     if (s.variant == 3) {
@@ -671,10 +684,10 @@ static IBShape launch_shape(Ctx &c, int prec) {
     return s;
 }
 
-int interbody_splits(Ctx &c, int prec) { return launch_shape(c, prec).splits; }
+int interbody_splits(Ctx &c, int prec, int nrhs) { return launch_shape(c, prec, nrhs).splits; }
 
-void interbody_shape(Ctx &c, int prec, int out[4]) {
-    const IBShape s = launch_shape(c, prec);
+void interbody_shape(Ctx &c, int prec, int nrhs, int out[4]) {
+    const IBShape s = launch_shape(c, prec, nrhs);
     out[0] = s.variant;
     out[1] = s.tpt;
     out[2] = s.bs;
@@ -924,26 +937,27 @@ static void dispatch_ib(Ctx &c, const IBShape &s, const IBWork *work, int nwork,
 
 void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
     const int pi = prec == AXS_FP32 ? 1 : 0;
-    const IBShape s = launch_shape(c, prec);
+    const IBShape s = launch_shape(c, prec, nrhs);
     const bool rings = s.variant == 2;
-    if (!c.ib_work[pi] || c.ib_key[pi][0] != s.tpt || c.ib_key[pi][1] != s.bs || c.ib_key[pi][2] != s.splits ||
-        c.ib_key[pi][3] != s.variant) {
+    const int wi = s.variant == 3 ? 1 : 0;
+    int *key = c.ib_key[pi][wi];
+    if (!c.ib_work[pi][wi] || key[0] != s.tpt || key[1] != s.bs || key[2] != s.splits || key[3] != s.variant) {
         // work tables are cached per launch shape; rebuilt only when it changes
         std::vector<IBWork> work = build_work(c, ib_tile(s), s.splits, rings);
-        if (c.ib_work[pi]) {
+        if (c.ib_work[pi][wi]) {
             AXS_HIP(hipStreamSynchronize(c.stream));
-            c.dfree(c.ib_work[pi]);
+            c.dfree(c.ib_work[pi][wi]);
         }
-        c.ib_work[pi] = (IBWork *)c.dalloc(work.size() * sizeof(IBWork));
-        AXS_HIP(hipMemcpy(c.ib_work[pi], work.data(), work.size() * sizeof(IBWork), hipMemcpyHostToDevice));
-        c.ib_nwork[pi] = (int)work.size();
-        c.ib_key[pi][0] = s.tpt;
-        c.ib_key[pi][1] = s.bs;
-        c.ib_key[pi][2] = s.splits;
-        c.ib_key[pi][3] = s.variant;
+        c.ib_work[pi][wi] = (IBWork *)c.dalloc(work.size() * sizeof(IBWork));
+        AXS_HIP(hipMemcpy(c.ib_work[pi][wi], work.data(), work.size() * sizeof(IBWork), hipMemcpyHostToDevice));
+        c.ib_nwork[pi][wi] = (int)work.size();
+        key[0] = s.tpt;
+        key[1] = s.bs;
+        key[2] = s.splits;
+        key[3] = s.variant;
     }
-    const IBWork *dwork = c.ib_work[pi];
-    const int nwork = c.ib_nwork[pi];
+    const IBWork *dwork = c.ib_work[pi][wi];
+    const int nwork = c.ib_nwork[pi][wi];
     const int64_t total = (int64_t)nrhs * c.N;
     const int thr = 256;
     if (prec == AXS_FP32) {
@@ -964,7 +978,7 @@ void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
 }
 
 void interbody_reduce_to_c128(Ctx &c, void *y, int nrhs, int prec) {
-    const int splits = interbody_splits(c, prec);
+    const int splits = interbody_splits(c, prec, nrhs);
     const int64_t total = (int64_t)nrhs * c.N;
     const int thr = 256;
     if (prec == AXS_FP32)
