@@ -188,7 +188,7 @@ axs_status axs_last_timing(axs_ctx *ctx, double ms[5]);
 /* Inter-body sum launch shape, per precision; 0 = library default for each field.
  *  variant: 1 = sources streamed as points, 2 = sources streamed as azimuthal rings
  *           (per target and ring, R^2 and n.d become two FMAs each; needs kappa > 0),
- *           3 = MFMA order, FP32 only, kappa > 0: R^2 and n.d of 16 x 16 (source,
+ *           3 = MFMA order, kappa > 0: R^2 and n.d of 16 x 16 (source,
  *           target) blocks from matrix-core products of 4-vectors in the source
  *           body's frame; with 16 right-hand sides per group the complex
  *           multiply-accumulate is a matrix-core product too

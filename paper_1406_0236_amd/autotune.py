@@ -22,7 +22,7 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotu
 CANDIDATES = [
     # (variant, targets per thread, block); FP32 rings with 128 threads and
     # <= 2 targets per thread also get 16- and 32-wide right-hand-side groups;
-    # the MFMA order (FP32) takes 1, 2 or 4 groups of 16 targets per wavefront
+    # the MFMA order takes 1, 2 or 4 groups of 16 targets per wavefront
     (3, 2, 256), (3, 1, 256), (3, 4, 256),
     (2, 4, 256), (2, 2, 256), (2, 8, 256), (2, 4, 128), (2, 2, 128), (2, 1, 128), (2, 1, 256),
     (1, 4, 256), (1, 2, 256), (1, 8, 256),
@@ -77,7 +77,7 @@ def tune(ctx, precision, nrhs, max_nf, x=None, reps=2, cache_path=DEFAULT_CACHE,
         for variant, tpt, block in CANDIDATES:
             if variant == 2 and max_nf > block:
                 continue
-            if variant == 3 and (precision != FP32 or not (ctx.kappa or 0) > 0):
+            if variant == 3 and not (ctx.kappa or 0) > 0:
                 continue
             for splits in SPLITS:
                 cfg = (variant, tpt, block, splits)

@@ -155,6 +155,7 @@ struct Ctx {
     // MFMA source order (FP32, kappa > 0): per node, in its body's frame,
     // [0, N): (k/2pi)^2 (-2y, |y|^2); [N, 2N): (k/2pi)^3 (n, -n.y)
     float *mf_src = nullptr;
+    double *mf_src64 = nullptr;          // the same in FP64
     int64_t *body_off = nullptr;         // [B + 1]: first node of each body, then N
     // every body's diameter is under 127 wavelengths, so the phase less the
     // per-(wavefront, source body) whole revolutions floor(min (|p| - r_b) k/2pi)

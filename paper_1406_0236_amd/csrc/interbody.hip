@@ -377,49 +377,67 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// MFMA-assisted source order (FP32, kappa > 0).  With the source y and its
-// normal n in the source body's frame and the target p = Rot^T (x - c) in the
-// same frame,
+// MFMA-assisted source order (kappa > 0).  With the source y and its normal n
+// in the source body's frame and the target p = Rot^T (x - c) in the same frame,
 //   R'^2 = s2 (|p|^2 - 2 p.y + |y|^2),   nd' = c1 n.(p - y)
 // (s2 = (k/2pi)^2, c1 = (k/2pi)^3, so R' is the phase in revolutions) are
 // 16 x 16 blocks (sources x targets) of the products of the 4-vectors
 // [s2(-2y, |y|^2)] and [p, 1] plus s2 |p|^2, and of [c1(n, -n.y)] and [p, 1]:
-// one v_mfma_f32_16x16x4f32 each per 256 pairs, which takes the four FMAs of
-// R^2 and n.d per pair off the VALU.  Since |y| is at most the body's bounding
-// radius and R at least the gap to the next body, the cancellation in
-// |p|^2 - 2p.y + |y|^2 stays bounded.  A wave owns G groups of 16 targets;
-// lane l receives sources 4(l/16)+v (v = 0..3) of the block for target l%16
-// of each group.
+// one 16x16x4 MFMA each per 256 pairs, which takes the FMAs of R^2 and n.d
+// off the VALU.  Since |y| is at most the body's bounding radius and R at
+// least the gap to the next body, the cancellation in |p|^2 - 2p.y + |y|^2
+// stays bounded.  A wave owns G groups of 16 targets; lane l receives four
+// sources of each 16-source block for target l%16 of each group: sources
+// 4(l/16)+v in FP32 and (l/16)+4v in FP64 (v = 0..3; the two MFMAs place their
+// result rows differently).
 //   NR < 16 right-hand sides: the complex multiply-accumulate stays on the
 //   VALU; the four source partial sums of a target are added across lanes at
 //   the end (fixed order).
 //   NR = 16: the multiply-accumulate is MFMA too: per group and per v, the
-//   16 x 4 block of kernel values (targets x sources 4k+v, taken straight from
-//   the lanes that computed them) times the 4 x 16 block of densities
-//   (sources x right-hand sides), three real MFMAs for the complex product.
-// FP32 MFMAs and VALU instructions do not overlap on a SIMD (the co-execution
+//   16 x 4 block of kernel values (targets x the lane's sources, taken straight
+//   from the lanes that computed them) times the 4 x 16 block of densities
+//   (sources x right-hand sides), three real MFMAs for the complex product
+//   (Gauss: Gr qr, Gi qi, (Gr + Gi)(qr + qi)).
+// MFMAs and VALU instructions do not overlap on a SIMD (the co-execution
 // counter stays at zero for this kernel), and one 16x16x4 MFMA costs what the
-// 16 VALU FMAs it replaces cost, so the order pays off only where it takes
-// the complex multiply-accumulate of many right-hand sides at the matrix
-// cores' twice-VALU FMA rate.
-// Sources are staged through LDS in chunks of MF_CH nodes of one body, padded
-// with zero densities to a multiple of 16.
+// VALU FMAs it replaces cost (FP32: 16 instructions at twice the FMA rate;
+// FP64: the same rate), so the order pays off where it shares one kernel
+// evaluation among 16 right-hand sides without holding 16 complex
+// accumulators per target in registers.
+// Sources are staged through LDS in chunks of MfChunk nodes of one body,
+// padded with zero densities to a multiple of 16.
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int MF_CH = 256;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename R> struct MfT;
+template <> struct MfT<float> {
+    using V = f32x4;
+    static constexpr int chunk = 256;
+    // row of the lane's v-th result in a 16x16x4 MFMA output block
+    static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
+};
+template <> struct MfT<double> {
+    using V = f64x4;
+    static constexpr int chunk = 128;
+    static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
+};
 
 __device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f64x4 mfma_16x16x4(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // 4 pi G from R'^2 and nd' (the same arithmetic as the ring order)
-__device__ __forceinline__ void kernel_value(float r2, float nd, float n0, float etap, float &gr, float &gi) {
-    const float u = rsq(r2);               // 1 / R'
-    float sn, cs_;
+template <typename R>
+__device__ __forceinline__ void kernel_value(R r2, R nd, R n0, R etap, R &gr, R &gi) {
+    const R u = rsq(r2);                   // 1 / R'
+    R sn, cs_;
     sincos_rev_near(fma(r2, u, -n0), sn, cs_);   // R' less whole revolutions n0
-    const float t = nd * (u * u);
-    const float P = t * u;                 // n.d / R^3
-    const float Q = fma(-6.283185307179586f, t, etap * u);   // eta / R - k n.d / R^2
+    const R t = nd * (u * u);
+    const R P = t * u;                     // n.d / R^3
+    const R Q = fma(R(-6.283185307179586476925287), t, etap * u);   // eta / R - k n.d / R^2
     gr = fma(cs_, P, -sn * Q);
     gi = fma(cs_, Q, sn * P);
 }
@@ -435,29 +453,31 @@ __device__ __forceinline__ int body_of(const int64_t *__restrict__ boff, int nb,
     return lo;
 }
 
-template <int G, int NR>
+template <typename R, int G, int NR>
 __global__ __launch_bounds__(256) void interbody_mfma_kernel(
-    const IBWork *__restrict__ work, const float *__restrict__ geo, const f32x4 *__restrict__ sop,
-    const float2 *__restrict__ q, const int64_t *__restrict__ boff, int nbodies,
-    const float *__restrict__ frame, int64_t N, int nrhs, int c0, float s2, float etap,
-    float2 *__restrict__ part) {
+    const IBWork *__restrict__ work, const R *__restrict__ geo, const typename MfT<R>::V *__restrict__ sop,
+    const typename C2T<R>::T *__restrict__ q, const int64_t *__restrict__ boff, int nbodies,
+    const R *__restrict__ frame, int64_t N, int nrhs, int c0, R s2, R etap, typename C2T<R>::T *__restrict__ part) {
+    using V = typename MfT<R>::V;
+    using R2 = typename C2T<R>::T;
+    constexpr int CH = MfT<R>::chunk;
     constexpr bool MACC = NR == 16;
     static_assert(NR == 1 || NR == 2 || NR == 4 || NR == 8 || NR == 16, "rhs group");
-    __shared__ f32x4 s_sr[MF_CH], s_sn[MF_CH];
+    __shared__ V s_sr[CH], s_sn[CH];
     // densities: NR < 16 as [src][c](re, im); NR = 16 as planes re[src][c], im[src][c]
-    __shared__ float s_q[MF_CH * 2 * NR];
+    __shared__ R s_q[CH * 2 * NR];
 
     const IBWork w = work[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int col = lane & 15, kq = lane >> 4;
     const int cb = c0 + blockIdx.y * NR;
-    const float *gx = geo, *gy = geo + N, *gz = geo + 2 * N;
-    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    const R *gx = geo, *gy = geo + N, *gz = geo + 2 * N;
+    const V zero4 = {R(0), R(0), R(0), R(0)};
 
-    float tx[G], ty[G], tz[G], bT[G], n0 = 0.f;
-    f32x4 cR[G];
-    float ar[G][MACC ? 1 : NR], ai[G][MACC ? 1 : NR];
-    f32x4 kr[G], ki[G], ks[G];
+    R tx[G], ty[G], tz[G], bT[G], n0 = R(0);
+    V cR[G];
+    R ar[G][MACC ? 1 : NR], ai[G][MACC ? 1 : NR];
+    V kr[G], ki[G], ks[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int t = (wv * G + g) * 16 + col;
@@ -465,11 +485,11 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
         tx[g] = gx[gi];
         ty[g] = gy[gi];
         tz[g] = gz[gi];
-        bT[g] = 0.f;
+        bT[g] = R(0);
         cR[g] = zero4;
         kr[g] = ki[g] = ks[g] = zero4;
 #pragma unroll
-        for (int c = 0; c < (MACC ? 1 : NR); ++c) ar[g][c] = ai[g][c] = 0.f;
+        for (int c = 0; c < (MACC ? 1 : NR); ++c) ar[g][c] = ai[g][c] = R(0);
     }
     int prev = -1;
 
@@ -481,25 +501,25 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
 #pragma unroll 1
         while (s < hi) {
             const int b = body_of(boff, nbodies, s);
-            const int64_t e = min(hi, min(boff[b + 1], s + (int64_t)MF_CH));
+            const int64_t e = min(hi, min(boff[b + 1], s + (int64_t)CH));
             const int n = (int)(e - s), n16 = (n + 15) & ~15;
             if (b != prev) {
                 // B operand: component kq of (p, 1); C operand: s2 |p|^2;
                 // whole revolutions n0 as in the ring order
-                const float *f = frame + FRAME * b;
-                const float k2pi = sqrtf(s2);
-                float m = 1e30f;
+                const R *f = frame + FRAME * b;
+                const R k2pi = sqrt(s2);
+                R m = R(1e30);
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    const float dx = tx[g] - f[0], dy = ty[g] - f[1], dz = tz[g] - f[2];
-                    const float px = fma(f[3], dx, fma(f[6], dy, f[9] * dz));
-                    const float py = fma(f[4], dx, fma(f[7], dy, f[10] * dz));
-                    const float pz = fma(f[5], dx, fma(f[8], dy, f[11] * dz));
-                    bT[g] = kq == 0 ? px : kq == 1 ? py : kq == 2 ? pz : 1.f;
-                    const float p2 = fma(px, px, fma(py, py, pz * pz));
-                    const float c2 = s2 * p2;
-                    cR[g] = (f32x4){c2, c2, c2, c2};
-                    m = fminf(m, (sqrtf(p2) - f[12]) * k2pi);
+                    const R dx = tx[g] - f[0], dy = ty[g] - f[1], dz = tz[g] - f[2];
+                    const R px = fma(f[3], dx, fma(f[6], dy, f[9] * dz));
+                    const R py = fma(f[4], dx, fma(f[7], dy, f[10] * dz));
+                    const R pz = fma(f[5], dx, fma(f[8], dy, f[11] * dz));
+                    bT[g] = kq == 0 ? px : kq == 1 ? py : kq == 2 ? pz : R(1);
+                    const R p2 = fma(px, px, fma(py, py, pz * pz));
+                    const R c2 = s2 * p2;
+                    cR[g] = (V){c2, c2, c2, c2};
+                    m = fmin(m, (sqrt(p2) - f[12]) * k2pi);
                 }
                 n0 = wave_floor_min(m);
                 prev = b;
@@ -511,10 +531,12 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
                 s_sn[i] = ok ? sop[N + s + i] : zero4;
 #pragma unroll
                 for (int c = 0; c < NR; ++c) {
-                    const float2 v = ok ? q[(int64_t)(cb + c) * N + s + i] : make_float2(0.f, 0.f);
+                    R2 v;
+                    v.x = v.y = R(0);
+                    if (ok) v = q[(int64_t)(cb + c) * N + s + i];
                     if constexpr (MACC) {
                         s_q[i * 16 + c] = v.x;
-                        s_q[MF_CH * 16 + i * 16 + c] = v.y;
+                        s_q[CH * 16 + i * 16 + c] = v.y;
                     } else {
                         s_q[2 * (i * NR + c)] = v.x;
                         s_q[2 * (i * NR + c) + 1] = v.y;
@@ -524,26 +546,26 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
             __syncthreads();
 #pragma unroll 1
             for (int j = 0; j < n16; j += 16) {
-                const float a1 = ((const float *)s_sr)[(j + col) * 4 + kq];
-                const float a2 = ((const float *)s_sn)[(j + col) * 4 + kq];
+                const R a1 = ((const R *)s_sr)[(j + col) * 4 + kq];
+                const R a2 = ((const R *)s_sn)[(j + col) * 4 + kq];
                 if constexpr (!MACC) {
-                    float qr[4][NR], qi[4][NR];
+                    R qr[4][NR], qi[4][NR];
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
 #pragma unroll
                         for (int c = 0; c < NR; ++c) {
-                            const int ix = 2 * ((j + 4 * kq + v) * NR + c);
+                            const int ix = 2 * ((j + MfT<R>::row(kq, v)) * NR + c);
                             qr[v][c] = s_q[ix];
                             qi[v][c] = s_q[ix + 1];
                         }
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
-                        const f32x4 d1 = mfma_16x16x4(a1, bT[g], cR[g]);
-                        const f32x4 d2 = mfma_16x16x4(a2, bT[g], zero4);
+                        const V d1 = mfma_16x16x4(a1, bT[g], cR[g]);
+                        const V d2 = mfma_16x16x4(a2, bT[g], zero4);
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            float gr, gi;
-                            kernel_value(d1[v], d2[v], n0, etap, gr, gi);
+                            R gr, gi;
+                            kernel_value<R>(d1[v], d2[v], n0, etap, gr, gi);
 #pragma unroll
                             for (int c = 0; c < NR; ++c) {
                                 ar[g][c] = fma(gr, qr[v][c], fma(-gi, qi[v][c], ar[g][c]));
@@ -555,22 +577,22 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
                     // complex product with three real MFMAs (Gauss):
                     // K1 += Gr qr, K2 += Gi qi, K3 += (Gr + Gi)(qr + qi);
                     // Re = K1 - K2, Im = K3 - K1 - K2 after the last source
-                    float bqr[4], bqi[4], bqs[4];
+                    R bqr[4], bqi[4], bqs[4];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int src = j + 4 * kq + v;
+                        const int src = j + MfT<R>::row(kq, v);
                         bqr[v] = s_q[src * 16 + col];
-                        bqi[v] = s_q[MF_CH * 16 + src * 16 + col];
+                        bqi[v] = s_q[CH * 16 + src * 16 + col];
                         bqs[v] = bqr[v] + bqi[v];
                     }
 #pragma unroll
                     for (int g = 0; g < G; ++g) {
-                        const f32x4 d1 = mfma_16x16x4(a1, bT[g], cR[g]);
-                        const f32x4 d2 = mfma_16x16x4(a2, bT[g], zero4);
+                        const V d1 = mfma_16x16x4(a1, bT[g], cR[g]);
+                        const V d2 = mfma_16x16x4(a2, bT[g], zero4);
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            float gr, gi;
-                            kernel_value(d1[v], d2[v], n0, etap, gr, gi);
+                            R gr, gi;
+                            kernel_value<R>(d1[v], d2[v], n0, etap, gr, gi);
                             kr[g] = mfma_16x16x4(gr, bqr[v], kr[g]);
                             ki[g] = mfma_16x16x4(gi, bqi[v], ki[g]);
                             ks[g] = mfma_16x16x4(gr + gi, bqs[v], ks[g]);
@@ -588,25 +610,32 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
             const int t = (wv * G + g) * 16 + col;
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
-                float xr = ar[g][c], xi = ai[g][c];
+                R xr = ar[g][c], xi = ai[g][c];
                 xr += __shfl_xor(xr, 16, 64);
                 xi += __shfl_xor(xi, 16, 64);
                 xr += __shfl_xor(xr, 32, 64);
                 xi += __shfl_xor(xi, 32, 64);
-                if (kq == 0 && t < w.tn)
-                    part[((int64_t)w.slot * nrhs + cb + c) * N + w.t0 + t] = make_float2(xr, xi);
+                if (kq == 0 && t < w.tn) {
+                    R2 o;
+                    o.x = xr;
+                    o.y = xi;
+                    part[((int64_t)w.slot * nrhs + cb + c) * N + w.t0 + t] = o;
+                }
             }
         }
     } else {
-        // lane l holds targets 4(l/16)+v of each group for right-hand side l%16
+        // the lane holds target rows row(kq, v) of each group for right-hand side l%16
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int t = (wv * G + g) * 16 + 4 * kq + v;
-                if (t < w.tn)
-                    part[((int64_t)w.slot * nrhs + cb + col) * N + w.t0 + t] =
-                        make_float2(kr[g][v] - ki[g][v], ks[g][v] - kr[g][v] - ki[g][v]);
+                const int t = (wv * G + g) * 16 + MfT<R>::row(kq, v);
+                if (t < w.tn) {
+                    R2 o;
+                    o.x = kr[g][v] - ki[g][v];
+                    o.y = ks[g][v] - kr[g][v] - ki[g][v];
+                    part[((int64_t)w.slot * nrhs + cb + col) * N + w.t0 + t] = o;
+                }
             }
     }
 }
@@ -666,8 +695,8 @@ static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
     AXS_REQUIRE(s.variant != 2 || ring_ok, AXS_EINVAL,
                 "ring variant needs kappa > 0, N_F <= threads per block and bodies under 127 wavelengths across");
     if (s.variant == 3) {
-        AXS_REQUIRE(prec == AXS_FP32 && c.kappa > 0 && c.mf_src && c.near_phase_ok, AXS_EINVAL,
-                    "MFMA variant needs FP32, kappa > 0 and bodies under 127 wavelengths across");
+        AXS_REQUIRE(c.kappa > 0 && c.mf_src && c.near_phase_ok, AXS_EINVAL,
+                    "MFMA variant needs kappa > 0 and bodies under 127 wavelengths across");
         AXS_REQUIRE(s.tpt == 1 || s.tpt == 2 || s.tpt == 4, AXS_EINVAL,
                     "MFMA variant: 1, 2 or 4 groups of 16 targets per wave");
         AXS_REQUIRE(s.bs == 256, AXS_EINVAL, "MFMA variant uses 256-thread blocks");
@@ -803,7 +832,7 @@ void build_ring_tables(Ctx &c) {
         // MFMA source operands in each body's frame, scaled so that the
         // products give R'^2 and nd' of the ring order directly
         const double k2pi = c.kappa / (2.0 * M_PI), s2 = k2pi * k2pi, c1 = s2 * k2pi;
-        std::vector<float> mf(8 * (size_t)N);
+        std::vector<double> mf64(8 * (size_t)N);
         for (size_t bi = 0; bi < c.bodies.size(); ++bi) {
             const auto &b = c.bodies[bi];
             const Shape &s = c.shapes[b.shape];
@@ -815,18 +844,21 @@ void build_ring_tables(Ctx &c) {
                     const double y[3] = {s.r[i] * ct, s.r[i] * st, s.z[i]};
                     const double n[3] = {nr * ct, nr * st, nz};
                     const int64_t j = b.offset + (int64_t)i * s.NF + l;
-                    float *a = &mf[4 * j], *d = &mf[4 * (N + j)];
+                    double *a = &mf64[4 * j], *d = &mf64[4 * (N + j)];
                     for (int k = 0; k < 3; ++k) {
-                        a[k] = (float)(-2.0 * s2 * y[k]);
-                        d[k] = (float)(c1 * n[k]);
+                        a[k] = -2.0 * s2 * y[k];
+                        d[k] = c1 * n[k];
                     }
-                    a[3] = (float)(s2 * (y[0] * y[0] + y[1] * y[1] + y[2] * y[2]));
-                    d[3] = (float)(-c1 * (n[0] * y[0] + n[1] * y[1] + n[2] * y[2]));
+                    a[3] = s2 * (y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+                    d[3] = -c1 * (n[0] * y[0] + n[1] * y[1] + n[2] * y[2]);
                 }
             }
         }
+        const std::vector<float> mf(mf64.begin(), mf64.end());
         c.mf_src = (float *)c.dalloc(mf.size() * sizeof(float));
         AXS_HIP(hipMemcpy(c.mf_src, mf.data(), mf.size() * sizeof(float), hipMemcpyHostToDevice));
+        c.mf_src64 = (double *)c.dalloc(mf64.size() * sizeof(double));
+        AXS_HIP(hipMemcpy(c.mf_src64, mf64.data(), mf64.size() * sizeof(double), hipMemcpyHostToDevice));
     }
 }
 
@@ -881,21 +913,24 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
 
 // MFMA order: full groups of 16 right-hand sides use MFMA accumulation, the
 // remainder groups of 8, 4, 2, 1 the VALU one.
-template <int G>
-static void launch_mf(Ctx &c, const IBWork *work, int nwork, const float2 *q, int nrhs, float2 *part) {
-    const float k2pi = (float)(c.kappa / (2.0 * M_PI));
-    const float s2 = k2pi * k2pi, etap = (float)c.eta * k2pi;
-    const f32x4 *sop = (const f32x4 *)c.mf_src;
+template <typename R, int G>
+static void launch_mf(Ctx &c, const IBWork *work, int nwork, const typename C2T<R>::T *q, int nrhs,
+                      typename C2T<R>::T *part) {
+    const R k2pi = (R)(c.kappa / (2.0 * M_PI));
+    const R s2 = k2pi * k2pi, etap = (R)c.eta * k2pi;
+    const R *geo = sizeof(R) == 4 ? (const R *)c.g32 : (const R *)c.g64;
+    const R *frame = sizeof(R) == 4 ? (const R *)c.frame32 : (const R *)c.frame64;
+    const auto *sop = (const typename MfT<R>::V *)(sizeof(R) == 4 ? (const void *)c.mf_src : (const void *)c.mf_src64);
     const int nb = (int)c.bodies.size();
     int c0 = 0;
     while (c0 < nrhs) {
         const int left = nrhs - c0;
         const int nr = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
         const int groups = left / nr;
-#define AXS_MF_NR(NR_)                                                                                   \
-    if (nr == NR_)                                                                                      \
-        hipLaunchKernelGGL((interbody_mfma_kernel<G, NR_>), dim3(nwork, groups), dim3(256), 0, c.stream, \
-                           work, c.g32, sop, q, c.body_off, nb, c.frame32, c.N, nrhs, c0, s2, etap, part);
+#define AXS_MF_NR(NR_)                                                                                      \
+    if (nr == NR_)                                                                                         \
+        hipLaunchKernelGGL((interbody_mfma_kernel<R, G, NR_>), dim3(nwork, groups), dim3(256), 0, c.stream, \
+                           work, geo, sop, q, c.body_off, nb, frame, c.N, nrhs, c0, s2, etap, part);
         AXS_MF_NR(16)
         AXS_MF_NR(8)
         AXS_MF_NR(4)
@@ -911,13 +946,11 @@ template <typename R>
 static void dispatch_ib(Ctx &c, const IBShape &s, const IBWork *work, int nwork, const R *geo, const R *cs,
                         const R *rg, const R *frame, const typename C2T<R>::T *q, int nrhs,
                         typename C2T<R>::T *part) {
-    if constexpr (sizeof(R) == 4) {
-        if (s.variant == 3) {
-            if (s.tpt == 1) launch_mf<1>(c, work, nwork, q, nrhs, part);
-            else if (s.tpt == 2) launch_mf<2>(c, work, nwork, q, nrhs, part);
-            else launch_mf<4>(c, work, nwork, q, nrhs, part);
-            return;
-        }
+    if (s.variant == 3) {
+        if (s.tpt == 1) launch_mf<R, 1>(c, work, nwork, q, nrhs, part);
+        else if (s.tpt == 2) launch_mf<R, 2>(c, work, nwork, q, nrhs, part);
+        else launch_mf<R, 4>(c, work, nwork, q, nrhs, part);
+        return;
     }
 #define AXS_IB_CASE(T_, B_)                                                             \
     if (s.tpt == T_ && s.bs == B_) {                                                    \

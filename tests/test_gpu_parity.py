@@ -271,8 +271,8 @@ def test_error_paths():
         ctx.build_body(s.rz, s.drz, s.gw, s.n_panels, s.p, 1.0, 1.0, 4, [5.0, 0, 0], np.eye(3))
     with pytest.raises(AxsError, match="EINVAL"):   # output overlaps input
         ctx.apply_matvec(y, FP64, out=y)
-    with pytest.raises(AxsError, match="EINVAL"):   # the MFMA order is FP32 only
-        ctx.set_interbody_config(FP64, 3, 2, 256, 0)
+    with pytest.raises(AxsError, match="EINVAL"):   # no such source order
+        ctx.set_interbody_config(FP64, 4, 2, 256, 0)
     # a single body: no inter-body terms, the operator is the identity
     z = torch.from_numpy(_rand(ctx.N, 1, 3)).to("cuda:0")
     assert torch.equal(ctx.apply_matvec(z, FP64), z)
@@ -402,39 +402,41 @@ def test_wide_rhs_groups_fp32_rings(small):
 
 
 def test_mfma_source_order_matches_reference(small):
-    """FP32 MFMA order: R^2 and n.d from 16x16x4 MFMAs, 1, 2 or 4 groups of 16
-    targets per wave, several splits; 3 right-hand sides (VALU accumulation in
-    groups of 2 and 1)."""
-    from paper_1406_0236_amd import FP32
+    """MFMA order: R^2 and n.d from 16x16x4 MFMAs (FP32 and FP64, whose result rows
+    differ), 1, 2 or 4 groups of 16 targets per wave, several splits; 3
+    right-hand sides (VALU accumulation in groups of 2 and 1)."""
+    from paper_1406_0236_amd import FP32, FP64
     wl, S, ctx = small
     x = _rand(S.N, 3, 91)
     ref = S.apply_B(x.T).T
-    for g, splits in ((1, 1), (2, 3), (4, 0), (2, 16)):
-        ctx.set_interbody_config(FP32, 3, g, 256, splits)
-        y = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
-        e = rel(y, ref)
-        print(f"G {g} splits {splits}: rel err {e:.2e}")
-        assert e < 3e-5, (g, splits, e)
-    ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+    for prec, tol in ((FP32, 3e-5), (FP64, 1e-12)):
+        for g, splits in ((1, 1), (2, 3), (4, 0), (2, 16)):
+            ctx.set_interbody_config(prec, 3, g, 256, splits)
+            y = ctx.apply_interbody(_dev(x), prec).cpu().numpy()
+            e = rel(y, ref)
+            print(f"prec {prec} G {g} splits {splits}: rel err {e:.2e}")
+            assert e < tol, (prec, g, splits, e)
+        ctx.set_interbody_config(prec, 0, 0, 0, 0)
 
 
 def test_mfma_accumulation_16_wide(small):
     """37 right-hand sides: two 16-wide groups with the complex multiply-accumulate
     on MFMA, then VALU groups of 4 and 1; every column against the reference,
-    and the same result bit for bit on a second call."""
-    from paper_1406_0236_amd import FP32
+    and the same result bit for bit on a second call; FP32 and FP64."""
+    from paper_1406_0236_amd import FP32, FP64
     wl, S, ctx = small
     x = _rand(S.N, 37, 92)
     ref = S.apply_B(x.T).T
-    for g in (1, 2, 4):
-        ctx.set_interbody_config(FP32, 3, g, 256, 0)
-        y = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
-        e = rel(y, ref)
-        print(f"G {g}: rel err {e:.2e}")
-        assert e < 3e-5, (g, e)
-        y2 = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
-        assert np.array_equal(y, y2)
-    ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+    for prec, tol in ((FP32, 3e-5), (FP64, 1e-12)):
+        for g in (1, 2, 4):
+            ctx.set_interbody_config(prec, 3, g, 256, 0)
+            y = ctx.apply_interbody(_dev(x), prec).cpu().numpy()
+            e = rel(y, ref)
+            print(f"prec {prec} G {g}: rel err {e:.2e}")
+            assert e < tol, (prec, g, e)
+            y2 = ctx.apply_interbody(_dev(x), prec).cpu().numpy()
+            assert np.array_equal(y, y2)
+        ctx.set_interbody_config(prec, 0, 0, 0, 0)
 
 
 def test_mfma_source_order_mixed_bodies_64_rhs(mixed):
