@@ -24,6 +24,15 @@ def sphere_eigenvalue(l, kappa, a, eta):
                                              + 1j * eta * spherical_jn(l, ka))
 
 
+def laplace_sphere_eigenvalue(l, a, eta):
+    """Eigenvalue of 1/2 + K + eta S on Y_l for the sphere of radius a at kappa = 0, with
+    S the single layer 1/(4 pi R) and K the double layer n(y).(x-y)/(4 pi R^3):
+    S Y_l = a/(2l+1) Y_l (expansion of 1/|x-y| in Legendre polynomials with the
+    addition theorem), and on the sphere n(y).(x-y) = -|x-y|^2/(2a), so K = -S/(2a):
+    lambda_l = 1/2 - 1/(2(2l+1)) + eta a/(2l+1) = (l + eta a)/(2l+1)."""
+    return (l + eta * a) / (2 * l + 1)
+
+
 def mie_scattered(x, kappa, a, d, lmax=None):
     x = np.atleast_2d(x)
     rr = np.linalg.norm(x, axis=1)

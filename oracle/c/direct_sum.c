@@ -1,7 +1,8 @@
 /* Reference inter-body sum, FP64, OpenMP.  TEST INFRASTRUCTURE ONLY.
  *
  * (B q)_i = sum_{j : body(j) != body(i)} G(x_i, x_j) q_j  with q_j = w_j sigma_j,
- * G(x, y) = d phi/d n(y) + i eta phi,  phi = exp(i kappa R) / (4 pi R),  R = |x - y|
+ * G(x, y) = d phi/d n(y) + gamma phi,  phi = exp(i kappa R) / (4 pi R),  R = |x - y|,
+ * gamma = i eta for kappa > 0, eta at kappa = 0 (the Laplace equation of Sec. 6.1)
  * (the combined-field kernel of Sec. 2 and the naive Nystrom entries of the
  * off-diagonal blocks, Sec. 3.3).  Written straight from the definition:
  * one complex exponential per pair, no blocking, no reordering.
@@ -25,10 +26,11 @@ int oracle_num_threads(void) {
 }
 
 int oracle_direct_rows(int64_t N, const double *x, const double *n, const double *q,
-                       const int64_t *body, double kappa, double eta, int64_t r,
+                       const int64_t *body, double kappa, double gam_re, double gam_im, int64_t r,
                        const int64_t *rows, int64_t nrows, double *out) {
     const double complex *qc = (const double complex *)q;
     double complex *oc = (double complex *)out;
+    const double complex gam = gam_re + I * gam_im;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t a = 0; a < nrows; ++a) {
         int64_t i = rows[a];
@@ -40,7 +42,7 @@ int oracle_direct_rows(int64_t N, const double *x, const double *n, const double
             double R = sqrt(dx * dx + dy * dy + dz * dz);
             double nd = n[3 * j] * dx + n[3 * j + 1] * dy + n[3 * j + 2] * dz;
             double complex phi = cexp(I * kappa * R) / (4.0 * M_PI * R);
-            double complex G = phi * (nd * (1.0 - I * kappa * R) / (R * R) + I * eta);
+            double complex G = phi * (nd * (1.0 - I * kappa * R) / (R * R) + gam);
             for (int64_t c = 0; c < r; ++c) oc[c * nrows + a] += G * qc[c * N + j];
         }
     }

@@ -20,7 +20,11 @@ R(t)^2 = 2 r r' (chi - cos t):
           Q = Legendre function of the second kind (toroidal harmonic).
 
   k^D_m = n_r' d/dr' k^S_m + n_z' d/dz' k^S_m  (normal derivative at the source)
-  k^G_m = (k^D_m + i eta k^S_m) / (4 pi)       (eq. for G_kappa, 1/(4pi) from phi)
+  k^G_m = (k^D_m + gamma k^S_m) / (4 pi)       (eq. for G_kappa, 1/(4pi) from phi)
+
+with the single-layer coupling gamma = i eta for kappa > 0 (Sec. 2) and
+gamma = eta at kappa = 0, where the paper's Laplace equation (Sec. 6.1) adds
+the single layer with a real coefficient (eta = 1 there).
 
 All modes are even in m because G depends on t only through cos t.
 """
@@ -119,6 +123,12 @@ def default_nt(kappa: float, r_max: float) -> int:
     return nt
 
 
+def coupling(kappa: float, eta: float) -> complex:
+    """Coefficient of the single layer in G: i eta (Helmholtz, Sec. 2), eta at kappa = 0
+    (the Laplace equation of Sec. 6.1)."""
+    return 1j * eta if kappa > 0 else complex(eta)
+
+
 def modal_kernels(r, rp, dr, dz, nrp, nzp, kappa: float, eta: float, M: int, Nt: int):
     """k^S_m, k^D_m, k^G_m for m = 0..M; arrays broadcast to a common shape P.
 
@@ -169,5 +179,5 @@ def modal_kernels(r, rp, dr, dz, nrp, nzp, kappa: float, eta: float, M: int, Nt:
     kS = np.einsum("pl,pml->pm", cl, qi) + 1j * s[:, :M + 1]
     kD = (np.einsum("pl,pml->pm", dcl, qi) + np.einsum("pl,pml->pm", cl, dqi)
           + 1j * ds[:, :M + 1])
-    kG = (kD + 1j * eta * kS) / (4.0 * math.pi)
+    kG = (kD + coupling(kappa, eta) * kS) / (4.0 * math.pi)
     return kS, kD, kG

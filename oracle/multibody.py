@@ -18,6 +18,7 @@ import os
 
 import numpy as np
 
+from .modal import coupling
 from .nystrom import Shape
 
 
@@ -48,6 +49,7 @@ class System:
         self.bodies = list(bodies)
         self.kappa = self.bodies[0].shape.kappa
         self.eta = self.bodies[0].shape.eta
+        self.gamma = coupling(self.kappa, self.eta)
         for b in self.bodies:
             assert b.shape.kappa == self.kappa and b.shape.eta == self.eta
         self.offsets = np.cumsum([0] + [b.size for b in self.bodies])
@@ -71,13 +73,14 @@ class System:
 
     # -- kernel -------------------------------------------------------------
     def kernel(self, xt, xs, ns):
-        """G_kappa(x_t, x_s) = d phi/d n(x_s) + i eta phi, phi = e^{i k R}/(4 pi R) (eq. Gkappa)."""
+        """G_kappa(x_t, x_s) = d phi/d n(x_s) + gamma phi, phi = e^{i k R}/(4 pi R) (eq. Gkappa),
+        gamma = i eta (kappa > 0) or eta (kappa = 0, the Laplace equation of Sec. 6.1)."""
         d = xt[:, None, :] - xs[None, :, :]
         R = np.sqrt(np.sum(d * d, axis=-1))
         nd = np.sum(ns[None, :, :] * d, axis=-1)
         k = self.kappa
         e = np.exp(1j * k * R) / (4.0 * math.pi * R)
-        return e * (nd * (1.0 - 1j * k * R) / (R * R) + 1j * self.eta)
+        return e * (nd * (1.0 - 1j * k * R) / (R * R) + self.gamma)
 
     # -- operators on global vectors (N,) or (N, r) ------------------------------
     def apply_B(self, sigma, rows=None):
@@ -175,6 +178,8 @@ class System:
 
     def far_field(self, sigma, xhat):
         """u_inf(xh) = (1/4pi) sum_j (-i k xh.n_j + i eta) e^{-i k xh.x_j} w_j sigma_j."""
+        if not self.kappa > 0:
+            raise ValueError("no far field at kappa = 0")
         xh = np.atleast_2d(xhat)
         sig = np.asarray(sigma, dtype=np.complex128)
         q = self.w[:, None] * (sig[:, None] if sig.ndim == 1 else sig)
@@ -253,7 +258,8 @@ def _clib():
         dp = ctypes.POINTER(ctypes.c_double)
         lp = ctypes.POINTER(ctypes.c_int64)
         lib.oracle_direct_rows.argtypes = [ctypes.c_int64, dp, dp, dp, lp, ctypes.c_double,
-                                          ctypes.c_double, ctypes.c_int64, lp, ctypes.c_int64, dp]
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_int64, lp,
+                                          ctypes.c_int64, dp]
         lib.oracle_direct_rows.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         _LIB = lib
@@ -278,7 +284,8 @@ def apply_B_c(system: System, sigma, rows=None):
     lp = ctypes.POINTER(ctypes.c_int64)
     rc = lib.oracle_direct_rows(system.N, x.ctypes.data_as(dp), n.ctypes.data_as(dp),
                                 q.view(np.float64).ctypes.data_as(dp), body.ctypes.data_as(lp),
-                                system.kappa, system.eta, r, rows.ctypes.data_as(lp), rows.size,
+                                system.kappa, system.gamma.real, system.gamma.imag, r,
+                                rows.ctypes.data_as(lp), rows.size,
                                 out.view(np.float64).ctypes.data_as(dp))
     if rc != 0:
         raise RuntimeError("oracle_direct_rows failed")

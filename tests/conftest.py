@@ -36,3 +36,14 @@ def small_system():
                                         configs.BodySpec(pr, np.array([2.6, 0.4, -0.3]), rot, 8)],
                           np.array([[0.0, 0.6, 0.8]]))
     return wl, System.from_workload(wl)
+
+
+@pytest.fixture(scope="session")
+def laplace_system():
+    """Zero frequency (kappa = 0, single-layer coefficient eta = 1, the Laplace equation
+    of Sec. 6.1): sphere, rotated spheroid and rotated bowl."""
+    import numpy as np
+    from oracle.multibody import System
+    from workloads import configs
+    wl = configs.laplace_small()
+    return wl, System.from_workload(wl)

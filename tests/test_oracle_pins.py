@@ -162,6 +162,33 @@ def test_sphere_eigenvalue_pin_detects_wrong_sign_of_coupling(sphere_shape):
     assert np.max(np.abs(At[0] @ v - lam_wrong * v)) > 1e-2
 
 
+@pytest.fixture(scope="module")
+def laplace_sphere_shape():
+    c = geo.sphere(1.0, 10, 10)
+    return Shape(c.rz, c.drz, c.gw, c.n_panels, c.p, 0.0, 1.0, 20), c
+
+
+def test_laplace_sphere_modal_matrices_have_closed_form_eigenvalues(laplace_sphere_shape):
+    """kappa = 0, eta = 1 (Sec. 6.1): 1/2 + K + S has eigenvalues (l + 1)/(2l + 1) on the
+    unit sphere; the same pin with eta = -1 must fail."""
+    sh, c = laplace_sphere_shape
+    At = sh.modal_matrices()
+    x = c.rz[:, 1]
+    worst, worst_low = 0.0, 0.0
+    for m in (0, 1, 2, 5, 9):
+        for l in range(m, 11):
+            lam = analytic.laplace_sphere_eigenvalue(l, 1.0, sh.eta)
+            v = lpmv(m, l, x)
+            err = np.max(np.abs(At[m] @ v - lam * v)) / np.max(np.abs(lam * v))
+            worst = max(worst, err)
+            if l <= 5:
+                worst_low = max(worst_low, err)
+    assert worst < 1e-9, worst
+    assert worst_low < 1e-12, worst_low
+    v = lpmv(0, 3, x)
+    assert np.max(np.abs(At[0] @ v - analytic.laplace_sphere_eigenvalue(3, 1.0, -1.0) * v)) > 1e-2
+
+
 def test_modal_inverse_is_inverse(sphere_shape):
     sh, _ = sphere_shape
     S = sh.inverses()
@@ -196,14 +223,16 @@ def test_single_sphere_matches_mie_series():
 # inter-body operator and multibody solves (Secs. 3.3, 4)
 # --------------------------------------------------------------------------
 
-def test_interbody_sum_rows_match_mpmath(small_system):
-    wl, S = small_system
+@pytest.mark.parametrize("which", ["helmholtz", "laplace"])
+def test_interbody_sum_rows_match_mpmath(which, small_system, laplace_system):
+    wl, S = small_system if which == "helmholtz" else laplace_system
     rng = np.random.default_rng(3)
     sig = rng.standard_normal(S.N) + 1j * rng.standard_normal(S.N)
     rows = np.array([0, 17, S.N - 1, S.offsets[1] + 5])
     out = apply_B_c(S, sig, rows)
     mp.mp.dps = 30
     k, eta = S.kappa, S.eta
+    gam = 1j * eta if k > 0 else eta          # single-layer coupling (Secs. 2 and 6.1)
     for a, i in enumerate(rows):
         acc = mp.mpc(0)
         for j in range(S.N):
@@ -213,13 +242,14 @@ def test_interbody_sum_rows_match_mpmath(small_system):
             R = mp.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
             nd = sum(mp.mpf(S.n[j, c]) * d[c] for c in range(3))
             phi = mp.exp(1j * k * R) / (4 * mp.pi * R)
-            acc += phi * (nd * (1 - 1j * k * R) / R ** 2 + 1j * eta) * mp.mpf(S.w[j]) * mp.mpc(sig[j])
+            acc += phi * (nd * (1 - 1j * k * R) / R ** 2 + gam) * mp.mpf(S.w[j]) * mp.mpc(sig[j])
         ref = complex(acc)
         assert abs(out[a] - ref) <= 1e-13 * max(abs(ref), 1e-3), (i, out[a], ref)
 
 
-def test_c_sum_matches_numpy_sum(small_system):
-    wl, S = small_system
+@pytest.mark.parametrize("which", ["helmholtz", "laplace"])
+def test_c_sum_matches_numpy_sum(which, small_system, laplace_system):
+    wl, S = small_system if which == "helmholtz" else laplace_system
     rng = np.random.default_rng(4)
     sig = rng.standard_normal((S.N, 3)) + 1j * rng.standard_normal((S.N, 3))
     a = apply_B_c(S, sig)
@@ -257,6 +287,26 @@ def test_greens_identity_point_sources(small_system):
     ref = -S.point_source_field(src, amp, xt)
     err = np.max(np.abs(u - ref)) / np.max(np.abs(ref))
     assert err < 1e-6, err
+
+
+def test_laplace_greens_identity_point_sources(laplace_system):
+    """kappa = 0: interior point sources 1/(4 pi R) give the exterior field exactly
+    (the accuracy protocol of Sec. 6 for the Laplace examples).  Sources sit in the
+    sphere and the spheroid; the bowl's thin wall (0.2) would need panels of its own
+    scale for a source inside it, so it only scatters."""
+    wl, S = laplace_system
+    src = configs.point_sources(wl, seed=13)
+    amp = np.array([1.0, -0.7, 0.0])
+    v = S.point_source_field(src, amp, S.x)
+    x, it, _ = gmres(S.matvec, S.rhs(v), tol=1e-12)
+    xt = configs.exterior_targets(wl, 10, seed=14)
+    u = S.eval_field(x, xt)
+    ref = -S.point_source_field(src, amp, xt)
+    err = np.max(np.abs(u - ref)) / np.max(np.abs(ref))
+    print(f"Laplace Green's identity: {it} iterations, rel err {err:.2e}")
+    assert err < 1e-6, err
+    assert np.isrealobj(S.kernel(S.x[:2], S.x[-2:], S.n[-2:])) is False   # complex dtype kept
+    assert np.max(np.abs(S.kernel(S.x[:2], S.x[-2:], S.n[-2:]).imag)) == 0.0  # but real at kappa = 0
 
 
 def test_reciprocity_and_optical_theorem(small_system):

@@ -123,6 +123,31 @@ def mixed_many(seed=5, kappa=4 * math.pi, n_bodies=64, box=24.0, gap=0.5, n_dirs
                     geo.fibonacci_directions(n_dirs), "64 mixed bodies in 24^3, gap 0.5")
 
 
+def laplace_small() -> Workload:
+    """kappa = 0, eta = 1: unit sphere, spheroid 0.8 x 1.3 and a bowl, rotated, gaps > 0.5."""
+    rng = np.random.default_rng(21)
+    s = geo.sphere(1.0, 4, 10)
+    pr = geo.prolate(0.8, 1.3, 5, 10)
+    bw = geo.bowl(3, 2, 4, 10)
+    bodies = [BodySpec(s, np.array([0.0, 0.0, 0.0]), np.eye(3), 8),
+              BodySpec(pr, np.array([2.7, 0.4, -0.3]), geo.random_rotation(rng), 8),
+              BodySpec(bw, np.array([-0.5, 2.6, 0.6]), geo.random_rotation(rng), 8)]
+    return Workload("laplace_small", 0.0, 1.0, bodies, np.zeros((1, 3)),
+                    "kappa = 0: sphere, spheroid, bowl")
+
+
+def laplace_ellipsoids(per_side=5, spacing=2.05, n_panels=10, p=10, M=50) -> Workload:
+    """125 prolate spheroids (axes 2 x 1 x 1) on a 5^3 lattice of spacing 2.05, all along z,
+    so that neighbouring tips are 0.05 apart inside [0, 10.2]^3; kappa = 0, eta = 1;
+    10 x 10 contour nodes x 101 azimuthal nodes = 10,100 nodes per body."""
+    c = geo.prolate(0.5, 1.0, n_panels, p)
+    offs = 1.0 + spacing * np.arange(per_side)
+    bodies = [BodySpec(c, np.array(xyz, dtype=np.float64), np.eye(3), M)
+              for xyz in itertools.product(offs, offs, offs)]
+    return Workload("laplace_ellipsoids_125", 0.0, 1.0, bodies, np.zeros((1, 3)),
+                    "125 spheroids 2 x 1 x 1, 5^3 lattice, spacing 2.05, kappa = 0")
+
+
 def single_sphere(a=1.0, n_panels=10, p=10, M=20, kappa=math.pi) -> Workload:
     c = geo.sphere(a, n_panels, p)
     return Workload("single_sphere", kappa, kappa, [BodySpec(c, np.zeros(3), np.eye(3), M)],
