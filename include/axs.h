@@ -137,12 +137,18 @@ enum {
     AXS_SOLVE_FP64 = 0,       /* GMRES, FP64 operator */
     AXS_SOLVE_MIXED = 1,      /* flexible GMRES with FP64 operator and residual, whose
                                  preconditioner is an inner GMRES on the FP32 operator */
-    AXS_SOLVE_CERTIFY = 16    /* flag, OR-ed into the mode: after the iteration, apply
+    AXS_SOLVE_CERTIFY = 16,   /* flag, OR-ed into the mode: after the iteration, apply
                                  the FP64 operator once more to the returned sigma and
                                  report (and test convergence on) that explicit residual */
+    AXS_SOLVE_UNPRECONDITIONED = 32  /* flag, FP64 mode only: GMRES on (D + B) sigma = -v,
+                                 the system of Sec. 3.3 without the block-diagonal
+                                 preconditioner of Sec. 4 (residual relative to ||v||);
+                                 for the comparison the paper makes at zero frequency
+                                 (Sec. 6.1), where it finds the preconditioner superfluous */
 };
 
-/* Solve (eq. "precond")  sigma + D^{-1} B sigma = -D^{-1} v  for nrhs incident fields.
+/* Solve (eq. "precond")  sigma + D^{-1} B sigma = -D^{-1} v  for nrhs incident fields
+ * (with AXS_SOLVE_UNPRECONDITIONED: (D + B) sigma = -v).
  *  incident : device complex128 [nrhs][N], v at the nodes.
  *  sigma0   : device complex128 [nrhs][N] initial guess, or NULL for zero.  A guess
  *             whose FP64 residual is not below || b || is replaced by zero.

@@ -16,6 +16,7 @@ AXS_OK, AXS_NOT_CONVERGED = 0, 1
 FP64, FP32 = 0, 1
 SOLVE_FP64, SOLVE_MIXED = 0, 1
 SOLVE_CERTIFY = 16   # flag: recompute the final residual with one more FP64 application
+SOLVE_UNPRECONDITIONED = 32   # flag (FP64 mode): GMRES on (D + B) sigma = -v
 _STATUS = {0: "AXS_OK", 1: "AXS_NOT_CONVERGED", -1: "AXS_EINVAL", -2: "AXS_EHIP", -3: "AXS_ENOMEM",
            -4: "AXS_ESTATE", -5: "AXS_ENONFINITE"}
 
@@ -228,10 +229,14 @@ class Context:
     def apply_precond(self, x, precision=FP64, out=None):
         return self._apply(self.lib.axs_apply_precond, x, precision, out)
 
-    def solve(self, incident, sigma0=None, mode=SOLVE_FP64, tol=1e-7, max_iters=200, out=None, certify=False):
-        """axs_solve; certify=True ORs AXS_SOLVE_CERTIFY into the mode."""
+    def solve(self, incident, sigma0=None, mode=SOLVE_FP64, tol=1e-7, max_iters=200, out=None, certify=False,
+              precondition=True):
+        """axs_solve; certify=True ORs AXS_SOLVE_CERTIFY into the mode, precondition=False
+        AXS_SOLVE_UNPRECONDITIONED."""
         if certify:
             mode = int(mode) | SOLVE_CERTIFY
+        if not precondition:
+            mode = int(mode) | SOLVE_UNPRECONDITIONED
         pv, nrhs = self._vec(incident)
         p0 = self._vec(sigma0)[0] if sigma0 is not None else None
         sig = self._empty(nrhs) if out is None else out

@@ -11,7 +11,7 @@
 namespace axs {
 
 void gauss_legendre_public(int n, std::vector<double> &x, std::vector<double> &w);
-void split_planar(Ctx &c, Shape &s, double *r64, double *i64, float *r32, float *i32);
+void split_planar(Ctx &c, Shape &s, const double *src, double *r64, double *i64, float *r32, float *i32);
 void build_ring_tables(Ctx &c);
 void interbody_shape(Ctx &c, int prec, int nrhs, int out[4]);
 
@@ -95,6 +95,22 @@ void apply_operator(Ctx &c, const void *sigma, void *y, int nrhs, int prec) {
     finish_timing(c, true);
 }
 
+// y = (D + B) x in FP64: per-body DFT, A~_m products, inverse DFT, plus the
+// inter-body sum (the system matrix A of Sec. 3.3 without the preconditioner)
+void apply_unpreconditioned(Ctx &c, const void *x, void *y, int nrhs) {
+    rec(c, 0);
+    interbody_partials(c, x, nrhs, AXS_FP64);
+    rec(c, 1);
+    dft_forward(c, AXS_FP64, 1, x, nrhs, 0);
+    rec(c, 2);
+    modal_gemm(c, AXS_FP64, nrhs, true);
+    rec(c, 3);
+    dft_inverse(c, AXS_FP64, nullptr, 0.0, 1.0, y, nrhs);
+    interbody_reduce_to_c128(c, y, nrhs, AXS_FP64, true);
+    rec(c, 4);
+    finish_timing(c, true);
+}
+
 void apply_precond(Ctx &c, const void *x, void *y, int nrhs, int prec, double beta) {
     rec(c, 1);
     dft_forward(c, prec, 1, x, nrhs, 0);
@@ -123,13 +139,19 @@ static void precompute_all(Ctx &c) {
     double *i64 = (double *)c.dalloc(total * sizeof(double));
     float *r32 = (float *)c.dalloc(total * sizeof(float));
     float *i32 = (float *)c.dalloc(total * sizeof(float));
+    // the same layout for A~_m itself (FP64), used only by the unpreconditioned operator
+    double *ar64 = (double *)c.dalloc(total * sizeof(double));
+    double *ai64 = (double *)c.dalloc(total * sizeof(double));
     for (size_t k = 0; k < c.shapes.size(); ++k) {
         Shape &s = c.shapes[k];
         s.S64r = r64 + soff[k];
         s.S64i = i64 + soff[k];
         s.S32r = r32 + soff[k];
         s.S32i = i32 + soff[k];
-        split_planar(c, s, s.S64r, s.S64i, s.S32r, s.S32i);
+        split_planar(c, s, s.S64, s.S64r, s.S64i, s.S32r, s.S32i);
+        s.A64r = ar64 + soff[k];
+        s.A64i = ai64 + soff[k];
+        split_planar(c, s, s.A64, s.A64r, s.A64i, nullptr, nullptr);
     }
     // DFT workspace layout per shape and the batched GEMM table
     std::vector<GemmBatch> gb;
@@ -385,6 +407,8 @@ axs_status axs_build_body(axs_ctx *ctx, const double *rz, const double *drz, con
         c.have_k = true;
         c.kappa = kappa;
         c.eta = eta;
+        c.gam_re = kappa > 0 ? 0.0 : eta;
+        c.gam_im = kappa > 0 ? eta : 0.0;
         *body_id = (int)c.bodies.size() - 1;
         return AXS_OK;
     });
@@ -480,8 +504,10 @@ axs_status axs_solve(axs_ctx *ctx, const void *incident, const void *sigma0, voi
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         check_apply(c, incident, sigma, nrhs, AXS_FP64);
         if (sigma0) check_apply(c, sigma0, sigma, nrhs, AXS_FP64);
-        const int base = mode & ~AXS_SOLVE_CERTIFY;
+        const int base = mode & ~(AXS_SOLVE_CERTIFY | AXS_SOLVE_UNPRECONDITIONED);
         AXS_REQUIRE(base == AXS_SOLVE_FP64 || base == AXS_SOLVE_MIXED, AXS_EINVAL, "bad solve mode");
+        AXS_REQUIRE(!(mode & AXS_SOLVE_UNPRECONDITIONED) || base == AXS_SOLVE_FP64, AXS_EINVAL,
+                    "the unpreconditioned solve is FP64 GMRES only");
         AXS_REQUIRE(tol > 0 && tol < 1 && std::isfinite(tol), AXS_EINVAL, "tol must be in (0, 1)");
         AXS_REQUIRE(max_iters >= 1 && max_iters <= 2000, AXS_EINVAL, "max_iters must be in [1, 2000]");
         const bool t = c.timing;
@@ -538,6 +564,7 @@ axs_status axs_far_field(axs_ctx *ctx, const void *sigma, int nrhs, const double
         AXS_REQUIRE(c.precomputed, AXS_ESTATE, "call axs_precompute_scattering first");
         AXS_REQUIRE(sigma && xhat && out && nd >= 1 && nrhs >= 1 && nd <= 65535 && nrhs <= 4096, AXS_EINVAL,
                     "bad arguments");
+        AXS_REQUIRE(c.kappa > 0, AXS_EINVAL, "no far field at kappa = 0");
         double *d = (double *)c.scratch(axs::WS_EVAL, 3 * nd * sizeof(double));
         AXS_HIP(hipMemcpy(d, xhat, 3 * nd * sizeof(double), hipMemcpyHostToDevice));
         axs::far_field_launch(c, sigma, nrhs, d, nd, out);

@@ -55,6 +55,7 @@ struct Shape {
     double *S64 = nullptr;    // complex128 interleaved [M+1][NG][NG], S_m row-major
     double *S64r = nullptr, *S64i = nullptr;   // planar, column-major [M+1][NG(k)][NG(i)]
     float *S32r = nullptr, *S32i = nullptr;    // same in FP32
+    double *A64r = nullptr, *A64i = nullptr;   // planar A~_m (FP64), for the unpreconditioned operator
     int64_t xoff = 0;         // offset (in complex elements per rhs) of this shape's
                               // mode-major block in the DFT workspace
 };
@@ -113,6 +114,9 @@ struct Ctx {
 
     bool have_k = false;
     double kappa = 0, eta = 0;
+    // single-layer coupling gamma of G = d phi/dn' + gamma phi: i eta for kappa > 0
+    // (Sec. 2), eta at kappa = 0 (the Laplace equation of Sec. 6.1)
+    double gam_re = 0, gam_im = 0;
     std::vector<Shape> shapes;
     std::vector<Body> bodies;
     int64_t N = 0;
@@ -204,7 +208,7 @@ enum ScratchSlot {
 void precompute_shape(Ctx &c, Shape &s);
 // interbody.hip
 void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec);   // -> WS_PART
-void interbody_reduce_to_c128(Ctx &c, void *y, int nrhs, int prec);        // WS_PART -> y
+void interbody_reduce_to_c128(Ctx &c, void *y, int nrhs, int prec, bool add = false);  // WS_PART -> (+)y
 int interbody_splits(Ctx &c, int prec, int nrhs);
 void eval_field_launch(Ctx &c, const void *sigma, int nrhs, const double *tgt_dev, int nt,
                        void *u);
@@ -215,7 +219,8 @@ void incident_point_launch(Ctx &c, const double *src_dev, const double *amp_dev,
 // modal.hip
 // forward DFT from partial sums (src = 0) or from a complex128 vector (src = 1)
 void dft_forward(Ctx &c, int prec, int from_vec, const void *vec, int nrhs, int splits);
-void modal_gemm(Ctx &c, int prec, int nrhs);
+// per-mode products with S_m = A~_m^{-1}, or with A~_m itself (forward = true, FP64)
+void modal_gemm(Ctx &c, int prec, int nrhs, bool forward = false);
 // y = alpha * sigma + beta * inverse DFT
 void dft_inverse(Ctx &c, int prec, const void *sigma, double alpha, double beta, void *y,
                  int nrhs);
@@ -225,6 +230,7 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
 // api-level helpers
 void apply_operator(Ctx &c, const void *sigma, void *y, int nrhs, int prec);  // y = sigma + D^-1 B sigma
 void apply_precond(Ctx &c, const void *x, void *y, int nrhs, int prec, double beta);  // y = beta D^-1 x
+void apply_unpreconditioned(Ctx &c, const void *x, void *y, int nrhs);  // y = (D + B) x, FP64
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

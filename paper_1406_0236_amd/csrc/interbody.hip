@@ -111,7 +111,7 @@ template <typename R, int NR> struct SrcStride {
     static constexpr int value = (raw + per16 - 1) / per16 * per16;
 };
 
-template <typename R, int TPT, int NR, int BS>
+template <typename R, int TPT, int NR, int BS, bool LAP>
 __global__ __launch_bounds__(BS) void interbody_kernel(
     const IBWork *__restrict__ work, const R *__restrict__ geo, const typename C2T<R>::T *__restrict__ q,
     int64_t N, int nrhs, int c0, R kappa, R k2pi, R eta, typename C2T<R>::T *__restrict__ part) {
@@ -178,8 +178,18 @@ __global__ __launch_bounds__(BS) void interbody_kernel(
                     const R dx = tx[k] - sx, dy = ty[k] - sy, dz = tz[k] - sz;
                     const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
                     const R ri = rsq(r2);
-                    const R rr = r2 * ri;
                     const R nd = fma(snx, dx, fma(sny, dy, snz * dz));
+                    if constexpr (LAP) {
+                        // kappa = 0 (Sec. 6.1): 4 pi G = (n.d / R^2 + eta) / R, real
+                        const R G = ri * fma(nd, ri * ri, eta);
+#pragma unroll
+                        for (int c = 0; c < NR; ++c) {
+                            ar[k][c] = fma(G, qr[c], ar[k][c]);
+                            ai[k][c] = fma(G, qi[c], ai[k][c]);
+                        }
+                        continue;
+                    }
+                    const R rr = r2 * ri;
                     R sn, cs;
                     sincos_rev(rr * k2pi, sn, cs);
                     const R a = nd * ri * ri;                 // (n.d)/R^2
@@ -225,7 +235,7 @@ struct RingTabs {
     const int32_t *off, *nf, *body;   // [nrings]
 };
 
-template <typename R, int TPT, int NR, int BS>
+template <typename R, int TPT, int NR, int BS, bool LAP>
 __global__ __launch_bounds__(BS) void interbody_ring_kernel(
     const IBWork *__restrict__ work, const R *__restrict__ geo, const R *__restrict__ cs,
     const typename C2T<R>::T *__restrict__ q, RingTabs rt, const R *__restrict__ rg, int nrings,
@@ -309,7 +319,7 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                         const R pn = sqrt(fma(px[k], px[k], fma(py[k], py[k], pz[k] * pz[k])));
                         m = fmin(m, (pn - f[12]) * k2pi);
                     }
-                    n0 = wave_floor_min(m);
+                    if constexpr (!LAP) n0 = wave_floor_min(m);
                     prev_body = b;
                 }
                 const R rj = rr_[ring], zj = rz_[ring], nrj = rnr[ring], nzj = rnz[ring];
@@ -343,6 +353,16 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                         const R r2 = fma(Ax[k], cl, fma(Ay[k], sl, al[k]));
                         const R nd = fma(Bx[k], cl, fma(By[k], sl, be[k]));
                         const R u = rsq(r2);                  // 1 / R'
+                        if constexpr (LAP) {
+                            // kappa = 0 (scale factor 1): 4 pi G = (n.d / R^2 + eta) / R, real
+                            const R G = u * fma(nd, u * u, eta);
+#pragma unroll
+                            for (int c = 0; c < NR; ++c) {
+                                ar[k][c] = fma(G, qr[c], ar[k][c]);
+                                ai[k][c] = fma(G, qi[c], ai[k][c]);
+                            }
+                            continue;
+                        }
                         R sn, cs_;
                         sincos_rev_near(fma(r2, u, -n0), sn, cs_);   // phase R' = kR / 2pi revolutions
                         const R t = nd * (u * u);
@@ -656,10 +676,14 @@ __global__ void stage_density_kernel(const double2 *__restrict__ sigma, const do
 
 template <typename R>
 __global__ void reduce_parts_kernel(const typename C2T<R>::T *__restrict__ part, int splits,
-                                    int64_t total, double2 *__restrict__ y) {
+                                    int64_t total, int add, double2 *__restrict__ y) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     double re = 0, im = 0;
+    if (add) {
+        re = y[i].x;
+        im = y[i].y;
+    }
     for (int s = 0; s < splits; ++s) {
         auto v = part[(int64_t)s * total + i];
         re += (double)v.x;
@@ -687,13 +711,13 @@ static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
     // on, FP64 points x 4 targets per thread
     s.tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : (prec == AXS_FP32 ? 2 : 4);
     s.bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : 256;
-    const bool ring_ok = c.kappa > 0 && c.max_nf <= s.bs && c.near_phase_ok;
+    const bool ring_ok = c.max_nf <= s.bs && (c.kappa == 0 || c.near_phase_ok);
     const bool mf_default = prec == AXS_FP32 && nrhs >= 16 && c.kappa > 0 && c.mf_src && c.near_phase_ok &&
                             s.bs == 256 && s.tpt <= 4;
     s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi]
                                      : mf_default ? 3 : ((ring_ok && prec == AXS_FP32) ? 2 : 1);
     AXS_REQUIRE(s.variant != 2 || ring_ok, AXS_EINVAL,
-                "ring variant needs kappa > 0, N_F <= threads per block and bodies under 127 wavelengths across");
+                "ring variant needs N_F <= threads per block and bodies under 127 wavelengths across");
     if (s.variant == 3) {
         AXS_REQUIRE(c.kappa > 0 && c.mf_src && c.near_phase_ok, AXS_EINVAL,
                     "MFMA variant needs kappa > 0 and bodies under 127 wavelengths across");
@@ -862,11 +886,12 @@ void build_ring_tables(Ctx &c) {
     }
 }
 
-template <typename R, int TPT, int BS>
+template <typename R, int TPT, int BS, bool LAP>
 static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const R *geo, const R *cs,
                       const R *rg, const R *frame, const typename C2T<R>::T *q, int nrhs,
                       typename C2T<R>::T *part) {
-    const R kappa = (R)c.kappa, k2pi = (R)(c.kappa / (2.0 * M_PI)), eta = (R)c.eta;
+    // at kappa = 0 the ring order runs unscaled (k/2pi replaced by 1, no phase)
+    const R kappa = (R)c.kappa, k2pi = LAP ? R(1) : (R)(c.kappa / (2.0 * M_PI)), eta = (R)c.eta;
     const RingTabs rt{c.ring_i, c.ring_i + c.nrings, c.ring_i + 2 * c.nrings};
     // one launch covers every body and every full group of NR right-hand sides
     // (grid.y = groups); a remainder group gets one more launch.  Wide groups
@@ -882,20 +907,20 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
 #define AXS_IB_NR(NR_)                                                                                     \
     if (nr == NR_) {                                                                                       \
         if (variant == 2)                                                                                  \
-            hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, NR_, BS>), dim3(nwork, groups), dim3(BS), 0, \
+            hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, NR_, BS, LAP>), dim3(nwork, groups), dim3(BS), 0, \
                                c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta, \
                                part);                                                                      \
         else                                                                                               \
-            hipLaunchKernelGGL((interbody_kernel<R, TPT, NR_, BS>), dim3(nwork, groups), dim3(BS), 0,      \
+            hipLaunchKernelGGL((interbody_kernel<R, TPT, NR_, BS, LAP>), dim3(nwork, groups), dim3(BS), 0, \
                                c.stream, work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, part);             \
     }
         if constexpr (sizeof(R) == 4 && BS == 128 && TPT <= 2) {
             if (nr == 32)
-                hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, 32, BS>), dim3(nwork, groups), dim3(BS), 0,
+                hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, 32, BS, LAP>), dim3(nwork, groups), dim3(BS), 0,
                                    c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta,
                                    part);
             if (nr == 16)
-                hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, 16, BS>), dim3(nwork, groups), dim3(BS), 0,
+                hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, 16, BS, LAP>), dim3(nwork, groups), dim3(BS), 0,
                                    c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta,
                                    part);
         } else {
@@ -954,7 +979,10 @@ static void dispatch_ib(Ctx &c, const IBShape &s, const IBWork *work, int nwork,
     }
 #define AXS_IB_CASE(T_, B_)                                                             \
     if (s.tpt == T_ && s.bs == B_) {                                                    \
-        launch_ib<R, T_, B_>(c, s.variant, work, nwork, geo, cs, rg, frame, q, nrhs, part); \
+        if (c.kappa > 0)                                                                \
+            launch_ib<R, T_, B_, false>(c, s.variant, work, nwork, geo, cs, rg, frame, q, nrhs, part); \
+        else                                                                            \
+            launch_ib<R, T_, B_, true>(c, s.variant, work, nwork, geo, cs, rg, frame, q, nrhs, part); \
         return;                                                                         \
     }
     AXS_IB_CASE(1, 256)
@@ -1010,16 +1038,16 @@ void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
     }
 }
 
-void interbody_reduce_to_c128(Ctx &c, void *y, int nrhs, int prec) {
+void interbody_reduce_to_c128(Ctx &c, void *y, int nrhs, int prec, bool add) {
     const int splits = interbody_splits(c, prec, nrhs);
     const int64_t total = (int64_t)nrhs * c.N;
     const int thr = 256;
     if (prec == AXS_FP32)
         hipLaunchKernelGGL(reduce_parts_kernel<float>, dim3(ceil_div(total, thr)), dim3(thr), 0, c.stream,
-                           (const float2 *)c.scratch(WS_PART, 0), splits, total, (double2 *)y);
+                           (const float2 *)c.scratch(WS_PART, 0), splits, total, add ? 1 : 0, (double2 *)y);
     else
         hipLaunchKernelGGL(reduce_parts_kernel<double>, dim3(ceil_div(total, thr)), dim3(thr), 0, c.stream,
-                           (const double2 *)c.scratch(WS_PART, 0), splits, total, (double2 *)y);
+                           (const double2 *)c.scratch(WS_PART, 0), splits, total, add ? 1 : 0, (double2 *)y);
     AXS_HIP(hipGetLastError());
 }
 
@@ -1059,7 +1087,7 @@ template <int BS>
 __global__ __launch_bounds__(BS) void eval_field_kernel(const double *__restrict__ g, int64_t N,
                                                         const double2 *__restrict__ sigma,
                                                         const double *__restrict__ tgt, int nt,
-                                                        double kappa, double eta,
+                                                        double kappa, double gam_re, double gam_im,
                                                         double2 *__restrict__ u) {
     const int t = blockIdx.x, c = blockIdx.y;
     const double tx = tgt[3 * t], ty = tgt[3 * t + 1], tz = tgt[3 * t + 2];
@@ -1072,9 +1100,10 @@ __global__ __launch_bounds__(BS) void eval_field_kernel(const double *__restrict
         const double nd = g[3 * N + j] * dx + g[4 * N + j] * dy + g[5 * N + j] * dz;
         double s, cs;
         sincos(kappa * R, &s, &cs);
-        const double a = nd / r2, bim = eta - a * kappa * R;
+        // 4 pi G = e^{ikR}/R [a (1 - i k R) + gamma], a = n.d / R^2
+        const double a = nd / r2, are = a + gam_re, bim = gam_im - a * kappa * R;
         const double er = cs / R, ei = s / R;
-        const double gr = er * a - ei * bim, gi = er * bim + ei * a;
+        const double gr = er * are - ei * bim, gi = er * bim + ei * are;
         const double w = g[6 * N + j] * (0.25 / M_PI);
         const double qr = sg[j].x * w, qi = sg[j].y * w;
         re += gr * qr - gi * qi;
@@ -1112,7 +1141,7 @@ __global__ __launch_bounds__(BS) void far_field_kernel(const double *__restrict_
 
 void eval_field_launch(Ctx &c, const void *sigma, int nrhs, const double *tgt_dev, int nt, void *u) {
     hipLaunchKernelGGL(eval_field_kernel<256>, dim3(nt, nrhs), dim3(256), 0, c.stream, c.g64, c.N,
-                       (const double2 *)sigma, tgt_dev, nt, c.kappa, c.eta, (double2 *)u);
+                       (const double2 *)sigma, tgt_dev, nt, c.kappa, c.gam_re, c.gam_im, (double2 *)u);
     AXS_HIP(hipGetLastError());
 }
 

@@ -348,15 +348,28 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
                       double tol, int max_iters, axs_solve_info *info) {
     const auto t0 = std::chrono::steady_clock::now();
     const bool certify = (mode & AXS_SOLVE_CERTIFY) != 0;
-    mode &= ~AXS_SOLVE_CERTIFY;
+    const bool unprec = (mode & AXS_SOLVE_UNPRECONDITIONED) != 0;
+    mode &= ~(AXS_SOLVE_CERTIFY | AXS_SOLVE_UNPRECONDITIONED);
+    // the operator of the solve: I + D^{-1} B (FP64), or D + B without the preconditioner
+    auto op64 = [&](const double2 *in, double2 *out) {
+        if (unprec) apply_unpreconditioned(c, in, out, nrhs);
+        else apply_operator(c, in, out, nrhs, AXS_FP64);
+    };
     const int64_t N = c.N, tot = N * nrhs;
     const size_t vb = (size_t)tot * sizeof(double2);
     double2 *x = (double2 *)sigma_out;
     double2 *b = (double2 *)c.dalloc(vb);
     double2 *r = (double2 *)c.dalloc(vb);
     double2 *tmp = (double2 *)c.dalloc(vb);
-    // b = -D^{-1} v
-    apply_precond(c, incident, b, nrhs, AXS_FP64, -1.0);
+    // b = -D^{-1} v, or -v without the preconditioner
+    if (unprec) {
+        AXS_HIP(hipMemsetAsync(tmp, 0, vb, c.stream));
+        hipLaunchKernelGGL(csub_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, tmp,
+                           (const double2 *)incident, b, tot);
+        AXS_HIP(hipGetLastError());
+    } else {
+        apply_precond(c, incident, b, nrhs, AXS_FP64, -1.0);
+    }
     std::vector<double> bn = norms(c, b, N, nrhs);
     for (double v : bn) AXS_REQUIRE(std::isfinite(v), AXS_ENONFINITE, "non-finite incident field");
     for (auto &v : bn)
@@ -366,7 +379,7 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
     AXS_HIP(hipMemsetAsync(x, 0, vb, c.stream));
     AXS_HIP(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, c.stream));
     if (sigma0) {
-        apply_operator(c, sigma0, tmp, nrhs, AXS_FP64);
+        op64((const double2 *)sigma0, tmp);
         hipLaunchKernelGGL(csub_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, b, tmp, tmp, tot);
         AXS_HIP(hipGetLastError());
         std::vector<double> rn = norms(c, tmp, N, nrhs);
@@ -385,14 +398,12 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
     std::vector<int> inner_total(nrhs, 0);
     double2 *V = (double2 *)c.dalloc((size_t)(max_iters + 1) * vb);
     if (mode == AXS_SOLVE_FP64) {
-        auto op = [&](const double2 *in, double2 *out) { apply_operator(c, in, out, nrhs, AXS_FP64); };
         auto none = [&](const double2 *, double2 *) {};
-        outer = gmres_core(c, N, nrhs, max_iters, tol, r, x, V, nullptr, bn, op, none, false, est);
+        outer = gmres_core(c, N, nrhs, max_iters, tol, r, x, V, nullptr, bn, op64, none, false, est);
     } else {
         const int max_inner = 60;
         double2 *Z = (double2 *)c.dalloc((size_t)max_iters * vb);
         double2 *Vi = (double2 *)c.dalloc((size_t)(max_inner + 1) * vb);
-        auto op64 = [&](const double2 *in, double2 *out) { apply_operator(c, in, out, nrhs, AXS_FP64); };
         auto prec = [&](const double2 *v, double2 *z) {
             // inner GMRES on the FP32 operator, zero initial guess, rhs v; it only
             // has to reduce the outer residual by the factor still missing
@@ -417,7 +428,7 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
     std::vector<double> relv = est;
     if (certify) {
         // explicit FP64 residual of the returned solution
-        apply_operator(c, x, tmp, nrhs, AXS_FP64);
+        op64(x, tmp);
         hipLaunchKernelGGL(csub_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, b, tmp, tmp, tot);
         AXS_HIP(hipGetLastError());
         std::vector<double> rn = norms(c, tmp, N, nrhs);

@@ -246,12 +246,13 @@ void dft_forward(Ctx &c, int prec, int from_vec, const void *vec, int nrhs, int 
     AXS_HIP(hipGetLastError());
 }
 
-void modal_gemm(Ctx &c, int prec, int nrhs) {
+void modal_gemm(Ctx &c, int prec, int nrhs, bool forward) {
     const int64_t total = (int64_t)nrhs * c.N;
     dim3 grid((unsigned)ceil_div(c.max_NG, 32), (unsigned)ceil_div((int64_t)c.gemm_max_cols * nrhs, 32),
               (unsigned)c.ngemm);
     // all shapes' matrices live in one planar allocation per precision (see precompute)
     const Shape &s0 = c.shapes[0];
+    if (forward && prec != AXS_FP64) throw Error{AXS_EINVAL, "the A~_m products exist in FP64 only"};
     if (prec == AXS_FP32) {
         float *Yr = (float *)c.scratch(WS_YR, total * sizeof(float));
         float *Yi = (float *)c.scratch(WS_YI, total * sizeof(float));
@@ -261,9 +262,9 @@ void modal_gemm(Ctx &c, int prec, int nrhs) {
     } else {
         double *Yr = (double *)c.scratch(WS_YR, total * sizeof(double));
         double *Yi = (double *)c.scratch(WS_YI, total * sizeof(double));
-        hipLaunchKernelGGL(modal_gemm_kernel<double>, grid, dim3(256), 0, c.stream, c.gemm, nrhs, s0.S64r,
-                           s0.S64i, (const double *)c.scratch(WS_XR, 0), (const double *)c.scratch(WS_XI, 0),
-                           Yr, Yi);
+        hipLaunchKernelGGL(modal_gemm_kernel<double>, grid, dim3(256), 0, c.stream, c.gemm, nrhs,
+                           forward ? s0.A64r : s0.S64r, forward ? s0.A64i : s0.S64i,
+                           (const double *)c.scratch(WS_XR, 0), (const double *)c.scratch(WS_XI, 0), Yr, Yi);
     }
     AXS_HIP(hipGetLastError());
 }

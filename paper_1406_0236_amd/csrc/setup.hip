@@ -16,7 +16,8 @@
 // form with the exact factor (s - s_i), so n'.(y' - y) keeps full relative
 // accuracy as y' -> y.
 //
-// The modal kernel k^G_m = (k^D_m + i eta k^S_m) / (4 pi) is evaluated exactly:
+// The modal kernel k^G_m = (k^D_m + gamma k^S_m) / (4 pi) is evaluated exactly
+// (gamma = i eta for kappa > 0; eta at kappa = 0, the Laplace equation of Sec. 6.1):
 //   k^S_m = sum_l c_l q_{m-l} + i s_m,  c_l, s_m: Fourier coefficients of the
 //   entire functions cos(kR(t)) and sin(kR)/R (sampled at Nt points),
 //   q_m = 2 Q_{|m|-1/2}(chi) / sqrt(r r') with Q the toroidal harmonic
@@ -243,7 +244,8 @@ template <int WPB>
 __global__ __launch_bounds__(64 * WPB) void modal_kernel(Pts pts, int64_t npts, int Nt, int M,
                                                          const double *__restrict__ qv,
                                                          const double *__restrict__ dqv, double kappa,
-                                                         double eta, double2 *__restrict__ kout) {
+                                                         double gam_re, double gam_im,
+                                                         double2 *__restrict__ kout) {
     extern __shared__ double sm[];
     const int Nh = Nt / 2 + 1, L = Nt / 2 - 1, nq = M + L + 1;
     const int per = 4 * Nh + 2 * (L + 1) + 2 * (M + 1) + 2 * nq;
@@ -337,8 +339,9 @@ __global__ __launch_bounds__(64 * WPB) void modal_kernel(Pts pts, int64_t npts, 
             dr_ = fma(dcl[al], ql[mm], fma(cl[al], dql[mm], dr_));
         }
         const double si = sm_[m], di = dsm[m];
-        // (kD + i eta kS) / (4 pi)
-        const double re = (dr_ - eta * si) * inv4pi, im = (di + eta * sr) * inv4pi;
+        // (kD + gamma kS) / (4 pi)
+        const double re = (dr_ + gam_re * sr - gam_im * si) * inv4pi;
+        const double im = (di + gam_re * si + gam_im * sr) * inv4pi;
         out[m] = make_double2(re * wj, im * wj);
     }
 }
@@ -477,8 +480,10 @@ __global__ void split_planar_kernel(const double2 *__restrict__ S, int M, int NG
     const double2 v = S[m * nn + (int64_t)i * NG + k];
     r64[t] = v.x;
     i64[t] = v.y;
-    r32[t] = (float)v.x;
-    i32[t] = (float)v.y;
+    if (r32) {
+        r32[t] = (float)v.x;
+        i32[t] = (float)v.y;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -681,7 +686,7 @@ void precompute_shape(Ctx &c, Shape &s) {
         const size_t shm = (Nt + WPB * per) * sizeof(double);
         AXS_REQUIRE(shm <= 160 * 1024, AXS_EINVAL, "mode count or wavenumber too large for the modal kernel");
         hipLaunchKernelGGL(modal_kernel<WPB>, dim3(ceil_div(P, WPB)), dim3(64 * WPB), shm, c.stream, pts, P, Nt,
-                           M, qv, dqv, s.kappa, s.eta, kv);
+                           M, qv, dqv, s.kappa, s.kappa > 0 ? 0.0 : s.eta, s.kappa > 0 ? s.eta : 0.0, kv);
         AXS_HIP(hipGetLastError());
         if (nfar) {
             hipLaunchKernelGGL(scatter_far_kernel, dim3(ceil_div(nfar * (M + 1), 256)), dim3(256), 0, c.stream,
@@ -712,10 +717,10 @@ void precompute_shape(Ctx &c, Shape &s) {
         c.dfree(ptr);
 }
 
-void split_planar(Ctx &c, Shape &s, double *r64, double *i64, float *r32, float *i32) {
+void split_planar(Ctx &c, Shape &s, const double *src, double *r64, double *i64, float *r32, float *i32) {
     const int64_t nmat = (int64_t)(s.M + 1) * s.NG * s.NG;
     hipLaunchKernelGGL(split_planar_kernel, dim3(ceil_div(nmat, 256)), dim3(256), 0, c.stream,
-                       (const double2 *)s.S64, s.M, s.NG, r64, i64, r32, i32);
+                       (const double2 *)src, s.M, s.NG, r64, i64, r32, i32);
     AXS_HIP(hipGetLastError());
 }
 

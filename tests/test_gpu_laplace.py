@@ -1,0 +1,100 @@
+"""Zero frequency (kappa = 0): the Laplace equation of Sec. 6.1, whose combined
+field adds the single layer with the real coefficient eta (= 1), through the C
+ABI against the FP64 reference on a sphere, a rotated spheroid and a rotated
+bowl (tests/conftest.py::laplace_system).
+
+Tolerances as in test_gpu_parity.py: modal matrices 1e-9, FP64 sums 1e-12, FP32
+sums 3e-5, solves to 1e-11 within 1e-8 of the dense reference; the exterior
+field of interior point sources within 1e-6 of the exact one (the reference
+itself reaches 9e-9 on this discretisation)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(np.asarray(b))), 1e-300))
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def lap(laplace_system):
+    from paper_1406_0236_amd import Context
+    wl, S = laplace_system
+    print(f"[gpu] Laplace context {wl.name} N={wl.N}", flush=True)
+    ctx = Context(0).add_workload(wl)
+    ctx.precompute_scattering()
+    return wl, S, ctx
+
+
+def test_laplace_modal_matrices(lap):
+    wl, S, ctx = lap
+    for b, body in enumerate(S.bodies):
+        sh = body.shape
+        eA = rel(ctx.modal_matrices(b, 0, sh.M, sh.NG).cpu().numpy(), sh.modal_matrices())
+        eS = rel(ctx.modal_matrices(b, 1, sh.M, sh.NG).cpu().numpy(), sh.inverses())
+        print(f"body {b} ({wl.bodies[b].contour.kind}): A~ {eA:.2e} S {eS:.2e}")
+        assert eA < 1e-9 and eS < 1e-9
+
+
+def test_laplace_interbody_sum_all_orders(lap):
+    """Point and ring orders (no phase: one rsq and a real kernel per pair), both
+    precisions, several launch shapes; the MFMA order needs kappa > 0."""
+    from paper_1406_0236_amd import FP32, FP64, AxsError
+    wl, S, ctx = lap
+    assert ctx.interbody_launch_shape(FP32)[0] == 2
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal((5, S.N)) + 1j * rng.standard_normal((5, S.N))
+    ref = S.apply_B(x.T).T
+    for prec, tol in ((FP64, 1e-12), (FP32, 3e-5)):
+        for variant in (1, 2):
+            for tpt, block, splits in ((1, 128, 1), (2, 256, 3), (4, 256, 0)):
+                ctx.set_interbody_config(prec, variant, tpt, block, splits)
+                e = rel(ctx.apply_interbody(_dev(x), prec).cpu().numpy(), ref)
+                assert e < tol, (prec, variant, tpt, block, splits, e)
+            print(f"prec {prec} variant {variant}: rel err {e:.2e}")
+        ctx.set_interbody_config(prec, 3, 2, 256, 0)
+        with pytest.raises(AxsError, match="EINVAL"):
+            ctx.apply_interbody(_dev(x), prec)
+        ctx.set_interbody_config(prec, 0, 0, 0, 0)
+
+
+def test_laplace_solves_with_and_without_preconditioner(lap):
+    """FP64 GMRES, mixed FGMRES and unpreconditioned FP64 GMRES on (D + B) sigma = -v
+    all return the dense reference solution."""
+    from paper_1406_0236_amd import SOLVE_FP64, SOLVE_MIXED
+    wl, S, ctx = lap
+    from workloads import configs
+    src = configs.point_sources(wl, seed=13)
+    amp = np.array([1.0, -0.7, 0.0])
+    v = S.point_source_field(src, amp, S.x)
+    xd = S.solve_dense(v)
+    vd = ctx.incident_point_sources(src, amp)
+    assert rel(vd.cpu().numpy()[0], v) < 1e-13
+    runs = ((SOLVE_FP64, True), (SOLVE_MIXED, True), (SOLVE_FP64, False))
+    for mode, pre in runs:
+        sol, info = ctx.solve(vd, mode=mode, tol=1e-11, max_iters=100, precondition=pre, certify=True)
+        err = np.linalg.norm(sol.cpu().numpy()[0] - xd) / np.linalg.norm(xd)
+        print(f"mode {mode} preconditioned {pre}: {info[0]['iterations']} iterations "
+              f"(inner {info[0]['inner_iterations']}), residual {info[0]['rel_residual']:.1e}, err {err:.1e}")
+        assert info[0]["converged"] and err < 1e-8, err
+    # exterior field of the interior point sources (the accuracy protocol of Sec. 6)
+    sol, _ = ctx.solve(vd, mode=SOLVE_MIXED, tol=1e-10)
+    xt = configs.exterior_targets(wl, 10, seed=14)
+    u = ctx.eval_field(sol, xt).cpu().numpy()[0]
+    e = rel(u, -S.point_source_field(src, amp, xt))
+    print(f"exterior field vs exact: {e:.2e}")
+    assert e < 1e-6, e
+
+
+def test_laplace_has_no_far_field(lap):
+    from paper_1406_0236_amd import AxsError
+    wl, S, ctx = lap
+    x = torch.zeros((1, S.N), dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(AxsError, match="EINVAL"):
+        ctx.far_field(x, np.array([[0.0, 0.0, 1.0]]))
