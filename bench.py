@@ -34,8 +34,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a calibration copy
 # (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
 # source they were taken on.
-TRAFFIC_BYTES = 80.14e6
-TRAFFIC_SOURCE_SHA = "61d3ea4c96348744"
+TRAFFIC_BYTES = 80.15e6
+TRAFFIC_SOURCE_SHA = "982a1944f26524c1"
 
 
 def log(msg):
@@ -214,6 +214,17 @@ def main():
             variants[f"{pname}_{vname}_ms"] = float(np.min(t))
         ctx.set_interbody_config(prec, 0, 0, 0, 0)
     log(f"inter-body sum by source order: {variants}")
+    # far-field pattern of the solution in 4096 Fibonacci directions (FP64)
+    from workloads import geometry as geo_
+    xh = geo_.fibonacci_directions(4096)
+    ctx.far_field(sol, xh)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ctx.far_field(sol, xh)
+    torch.cuda.synchronize()
+    t_ff = time.time() - t0
+    far = {"directions": 4096, "ms": t_ff * 1e3, "gevals_per_s": 4096 * wl.N / t_ff / 1e9}
+    log(f"far field: {far}")
     ctx.apply_matvec(x, FP32)
     stage32 = ctx.last_timing()
     ctx.apply_matvec(x, FP64)
@@ -263,6 +274,7 @@ def main():
         "pct_fp32_valu_peak": 100.0 * achieved / FP32_VECTOR_PEAK_TFLOPS,
         "interbody_ms_by_variant": variants,
         "interbody_launch_shape": {"fp32": list(shape32), "fp64": list(shape64)},
+        "far_field": far,
         "stage_ms_fp32": stage32,
         "stage_ms_fp64": stage64,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
