@@ -83,7 +83,7 @@ def cpu_baseline(wl, iters_fp64, seconds_budget=15.0):
         "kind": "oracle",
         "sample": (f"FP64 reference inter-body sum (C/OpenMP) on {rows} random rows of N={S.N}: "
                    f"{tt:.2f} s; x N/rows = {full:.1f} s per operator application, x {iters_fp64} "
-                   f"(FP64 GPU GMRES iterations + residual check); the per-body preconditioner "
+                   f"(the FP64 GPU GMRES iteration count, one operator application each); the per-body preconditioner "
                    f"(< 0.1% of the work) and Arnoldi are not included"),
     }
 
@@ -111,6 +111,10 @@ def main():
                     help="zero frequency: 125 spheroids 2 x 1 x 1 on a 5^3 lattice (tips 0.05 apart), "
                          "10,100 nodes each, interior point sources; FP64 GMRES with and without the "
                          "preconditioner, mixed FGMRES, error of the exterior field")
+    ap.add_argument("--modal-probe", action="store_true",
+                    help="time the per-mode scattering applies (MFMA GEMM) with HIP events: 27 spheres "
+                         "with 1 and 16 rhs, 8 mixed bodies with 64 rhs, FP32 and FP64; also the launches "
+                         "the matrix-core counter passes measure")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="launch only what the hardware-counter passes measure: a 512 MiB device copy "
                          "(calibration), then two FP32 and one FP64 inter-body sums on the 27 spheres")
@@ -129,6 +133,8 @@ def main():
         return learned(args)
     if args.pmc_probe:
         return pmc_probe()
+    if args.modal_probe:
+        return modal_probe()
     if args.batched:
         return batched(args)
     if args.many:
@@ -244,7 +250,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        iters = (fp64["iterations"] + 1) if fp64 else 30
+        iters = fp64["iterations"] if fp64 else 30
         cpu = cpu_baseline(wl, iters)
 
     out = {
@@ -491,6 +497,44 @@ def laplace(args):
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def modal_probe():
+    """Per-mode scattering applies alone (axs_apply_precond: forward DFT, the
+    S_m GEMMs on MFMA, inverse DFT), timed per stage with the library's HIP
+    events.  Algorithmic flops of the GEMM stage: 8 NG^2 per column (four real
+    products per complex one), columns = 2 modes (+-m, one for m = 0) x bodies
+    x rhs per shape and mode."""
+    import numpy as np
+    import torch
+    from paper_1406_0236_amd import FP32, FP64, Context
+    from workloads import configs
+    rows = []
+    for wl, nrs in ((configs.sphere_lattice(), (1, 16)), (configs.mixed_bodies(), (64,))):
+        ctx = Context(0).add_workload(wl)
+        ctx.precompute_scattering()
+        shapes = {}
+        for b in wl.bodies:
+            key = (id(b.contour), b.M)
+            shapes.setdefault(key, [b.contour.NG, b.M, 0])[2] += 1
+        for r in nrs:
+            flops = sum(8.0 * NG * NG * nb * (2 * M + 1) * r for NG, M, nb in shapes.values())
+            g = torch.Generator(device="cuda:0").manual_seed(3)
+            x = torch.randn((r, wl.N), dtype=torch.complex128, device="cuda:0", generator=g)
+            for prec, pname, peak in ((FP32, "fp32", 157.3), (FP64, "fp64", 78.6)):
+                ctx.set_timing(True)
+                ms = []
+                for _ in range(5):
+                    ctx.apply_precond(x, prec)
+                    ms.append(ctx.last_timing()["modal_apply"])
+                ctx.set_timing(False)
+                t = float(np.median(ms))
+                row = {"workload": wl.name, "nrhs": r, "precision": pname, "gemm_ms": t,
+                       "gemm_tflops": flops / t / 1e9, "mfma_frac": flops / t / 1e9 / peak}
+                rows.append(row)
+                log(f"modal GEMM {row}")
+        ctx.close()
+    print(json.dumps({"modal_gemm": rows}), flush=True)
 
 
 def batched(args):
