@@ -161,6 +161,7 @@ struct Ctx {
     float *mf_src = nullptr;
     double *mf_src64 = nullptr;          // the same in FP64
     int64_t *body_off = nullptr;         // [B + 1]: first node of each body, then N
+    double2 *sctab = nullptr;            // [256]: (cos, sin)(2 pi k / 256) for the FP64 sin/cos
     // every body's diameter is under 127 wavelengths, so the phase less the
     // per-(wavefront, source body) whole revolutions floor(min (|p| - r_b) k/2pi)
     // stays inside the hardware sin/cos input range (ring and MFMA orders rely on it)

@@ -80,6 +80,40 @@ __device__ __forceinline__ void sincos_rev(double t, double &s, double &c) {
 }
 __device__ __forceinline__ void sincos_rev_near(double t, double &s, double &c) { sincos_rev(t, s, c); }
 
+// The same in FP64 with a 256-entry table of (cos, sin)(2 pi k / 256) held in
+// LDS: t = j/256 + r with |r| <= 1/512 exactly, x = 2 pi r in [-pi/256, pi/256],
+// sin x to x^5 and cos x to x^6 (truncation below 1e-17), then the angle sum
+// with the table entry.  About 20 instructions instead of the 33 above.
+__device__ __forceinline__ void sincos_rev_tab(double t, const double2 *tab, double &s, double &c) {
+    const double f = t - rint(t);                 // exact, [-1/2, 1/2]
+    const double j = rint(256.0 * f);             // -128..128
+    const double r = fma(-1.0 / 256.0, j, f);     // exact
+    const double x = r * 6.283185307179586476925287;
+    const double x2 = x * x;
+    const double sx = fma(x * x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
+    const double cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    const double2 e = tab[((int)j) & 255];        // (cos, sin)(2 pi j / 256)
+    s = fma(e.y, cx, e.x * sx);
+    c = fma(e.x, cx, -e.y * sx);
+}
+// precision-generic entry points used by the kernels (the table is unused in FP32)
+__device__ __forceinline__ void sincos_any(float ph, const double2 *, float &s, float &c) { sincos_rev(ph, s, c); }
+__device__ __forceinline__ void sincos_any(double t, const double2 *tab, double &s, double &c) {
+    sincos_rev_tab(t, tab, s, c);
+}
+__device__ __forceinline__ void sincos_near_any(float ph, const double2 *, float &s, float &c) {
+    sincos_rev_near(ph, s, c);
+}
+__device__ __forceinline__ void sincos_near_any(double t, const double2 *tab, double &s, double &c) {
+    sincos_rev_tab(t, tab, s, c);
+}
+// copy the FP64 table to LDS (the kernels' first barrier publishes it)
+template <typename R, int BS>
+__device__ __forceinline__ void load_sctab(double2 *dst, const double2 *__restrict__ src) {
+    if constexpr (sizeof(R) == 8)
+        for (int i = threadIdx.x; i < 256; i += BS) dst[i] = src[i];
+}
+
 // floor(max(min over the wavefront of v, 0)), the same in every lane; in FP32
 // moved to a scalar register so that the phase FMA reads two VGPRs, not three
 __device__ __forceinline__ float wave_floor_min(float v) {
@@ -114,10 +148,13 @@ template <typename R, int NR> struct SrcStride {
 template <typename R, int TPT, int NR, int BS, bool LAP>
 __global__ __launch_bounds__(BS) void interbody_kernel(
     const IBWork *__restrict__ work, const R *__restrict__ geo, const typename C2T<R>::T *__restrict__ q,
-    int64_t N, int nrhs, int c0, R kappa, R k2pi, R eta, typename C2T<R>::T *__restrict__ part) {
+    int64_t N, int nrhs, int c0, R kappa, R k2pi, R eta, const double2 *__restrict__ sctab,
+    typename C2T<R>::T *__restrict__ part) {
     using R2 = typename C2T<R>::T;
     constexpr int ST = SrcStride<R, NR>::value;
     __shared__ __align__(16) R tile[BS * ST];
+    __shared__ double2 s_tab[sizeof(R) == 8 ? 256 : 1];
+    load_sctab<R, BS>(s_tab, sctab);
 
     const IBWork w = work[blockIdx.x];
     const int tid = threadIdx.x;
@@ -191,7 +228,7 @@ __global__ __launch_bounds__(BS) void interbody_kernel(
                     }
                     const R rr = r2 * ri;
                     R sn, cs;
-                    sincos_rev(rr * k2pi, sn, cs);
+                    sincos_any(rr * k2pi, s_tab, sn, cs);
                     const R a = nd * ri * ri;                 // (n.d)/R^2
                     const R bim = fma(-a * kappa, rr, eta);   // eta - a k R
                     const R er = cs * ri, ei = sn * ri;       // e^{ikR}/R
@@ -239,10 +276,13 @@ template <typename R, int TPT, int NR, int BS, bool LAP>
 __global__ __launch_bounds__(BS) void interbody_ring_kernel(
     const IBWork *__restrict__ work, const R *__restrict__ geo, const R *__restrict__ cs,
     const typename C2T<R>::T *__restrict__ q, RingTabs rt, const R *__restrict__ rg, int nrings,
-    const R *__restrict__ frame, int64_t N, int nrhs, int c0, R k2pi, R eta, typename C2T<R>::T *__restrict__ part) {
+    const R *__restrict__ frame, int64_t N, int nrhs, int c0, R k2pi, R eta, const double2 *__restrict__ sctab,
+    typename C2T<R>::T *__restrict__ part) {
     using R2 = typename C2T<R>::T;
     constexpr int ST = RingStride<R, NR>::value;
     __shared__ __align__(16) R tile[BS * ST];
+    __shared__ double2 s_tab[sizeof(R) == 8 ? 256 : 1];
+    load_sctab<R, BS>(s_tab, sctab);
 
     const IBWork w = work[blockIdx.x];
     const int tid = threadIdx.x;
@@ -364,7 +404,7 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                             continue;
                         }
                         R sn, cs_;
-                        sincos_rev_near(fma(r2, u, -n0), sn, cs_);   // phase R' = kR / 2pi revolutions
+                        sincos_near_any(fma(r2, u, -n0), s_tab, sn, cs_);   // phase R' = kR / 2pi revolutions
                         const R t = nd * (u * u);
                         const R P = t * u;                    // n.d / R^3
                         const R Q = fma(-twopi, t, etap * u);  // eta / R - k n.d / R^2
@@ -451,10 +491,10 @@ __device__ __forceinline__ f64x4 mfma_16x16x4(double a, double b, f64x4 c) {
 
 // 4 pi G from R'^2 and nd' (the same arithmetic as the ring order)
 template <typename R>
-__device__ __forceinline__ void kernel_value(R r2, R nd, R n0, R etap, R &gr, R &gi) {
+__device__ __forceinline__ void kernel_value(R r2, R nd, R n0, R etap, const double2 *tab, R &gr, R &gi) {
     const R u = rsq(r2);                   // 1 / R'
     R sn, cs_;
-    sincos_rev_near(fma(r2, u, -n0), sn, cs_);   // R' less whole revolutions n0
+    sincos_near_any(fma(r2, u, -n0), tab, sn, cs_);   // R' less whole revolutions n0
     const R t = nd * (u * u);
     const R P = t * u;                     // n.d / R^3
     const R Q = fma(R(-6.283185307179586476925287), t, etap * u);   // eta / R - k n.d / R^2
@@ -477,7 +517,8 @@ template <typename R, int G, int NR>
 __global__ __launch_bounds__(256) void interbody_mfma_kernel(
     const IBWork *__restrict__ work, const R *__restrict__ geo, const typename MfT<R>::V *__restrict__ sop,
     const typename C2T<R>::T *__restrict__ q, const int64_t *__restrict__ boff, int nbodies,
-    const R *__restrict__ frame, int64_t N, int nrhs, int c0, R s2, R etap, typename C2T<R>::T *__restrict__ part) {
+    const R *__restrict__ frame, int64_t N, int nrhs, int c0, R s2, R etap, const double2 *__restrict__ sctab,
+    typename C2T<R>::T *__restrict__ part) {
     using V = typename MfT<R>::V;
     using R2 = typename C2T<R>::T;
     constexpr int CH = MfT<R>::chunk;
@@ -486,6 +527,8 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
     __shared__ V s_sr[CH], s_sn[CH];
     // densities: NR < 16 as [src][c](re, im); NR = 16 as planes re[src][c], im[src][c]
     __shared__ R s_q[CH * 2 * NR];
+    __shared__ double2 s_tab[sizeof(R) == 8 ? 256 : 1];
+    load_sctab<R, 256>(s_tab, sctab);
 
     const IBWork w = work[blockIdx.x];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -585,7 +628,7 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             R gr, gi;
-                            kernel_value<R>(d1[v], d2[v], n0, etap, gr, gi);
+                            kernel_value<R>(d1[v], d2[v], n0, etap, s_tab, gr, gi);
 #pragma unroll
                             for (int c = 0; c < NR; ++c) {
                                 ar[g][c] = fma(gr, qr[v][c], fma(-gi, qi[v][c], ar[g][c]));
@@ -612,7 +655,7 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
                             R gr, gi;
-                            kernel_value<R>(d1[v], d2[v], n0, etap, gr, gi);
+                            kernel_value<R>(d1[v], d2[v], n0, etap, s_tab, gr, gi);
                             kr[g] = mfma_16x16x4(gr, bqr[v], kr[g]);
                             ki[g] = mfma_16x16x4(gi, bqi[v], ki[g]);
                             ks[g] = mfma_16x16x4(gr + gi, bqs[v], ks[g]);
@@ -705,17 +748,17 @@ static int ib_tile(const IBShape &s) { return s.variant == 3 ? 64 * s.tpt : s.tp
 static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
     const int pi = prec == AXS_FP32 ? 1 : 0;
     IBShape s;
-    // defaults from the launch-shape sweeps on MI355X (27-sphere lattice, one
-    // rhs; 8 mixed bodies, 64 rhs): FP32 rings x 2 targets per thread below 16
-    // rhs, the MFMA order with 2 groups of 16 targets per wavefront from 16 rhs
-    // on, FP64 points x 4 targets per thread
-    s.tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : (prec == AXS_FP32 ? 2 : 4);
+    // Defaults from the launch-shape sweeps on MI355X (27-sphere lattice, one
+    // rhs; 8 mixed bodies, 1-64 rhs): below 16 rhs the ring order (2 targets
+    // per thread), from 16 rhs on the MFMA order (2 groups of 16 targets per
+    // wavefront in FP32, 4 in FP64); the point order where neither applies.
     s.bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : 256;
     const bool ring_ok = c.max_nf <= s.bs && (c.kappa == 0 || c.near_phase_ok);
-    const bool mf_default = prec == AXS_FP32 && nrhs >= 16 && c.kappa > 0 && c.mf_src && c.near_phase_ok &&
-                            s.bs == 256 && s.tpt <= 4;
-    s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi]
-                                     : mf_default ? 3 : ((ring_ok && prec == AXS_FP32) ? 2 : 1);
+    const bool mf_ok = c.kappa > 0 && c.mf_src && c.near_phase_ok && s.bs == 256 &&
+                       (c.ib_tpt[pi] == 0 || c.ib_tpt[pi] <= 4);
+    s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi] : (nrhs >= 16 && mf_ok) ? 3 : ring_ok ? 2 : 1;
+    const int dflt = prec == AXS_FP32 ? 2 : s.variant == 2 ? 2 : 4;
+    s.tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : dflt;
     AXS_REQUIRE(s.variant != 2 || ring_ok, AXS_EINVAL,
                 "ring variant needs N_F <= threads per block and bodies under 127 wavelengths across");
     if (s.variant == 3) {
@@ -847,6 +890,15 @@ void build_ring_tables(Ctx &c) {
     up(fr, c.frame64, c.frame32);
     up(csv, c.cs64, c.cs32);
 
+    // (cos, sin)(2 pi k / 256) for the FP64 sin/cos of the inter-body kernels
+    std::vector<double> tab(512);
+    for (int k = 0; k < 256; ++k) {
+        tab[2 * k] = std::cos(2.0 * M_PI * k / 256.0);
+        tab[2 * k + 1] = std::sin(2.0 * M_PI * k / 256.0);
+    }
+    c.sctab = (double2 *)c.dalloc(tab.size() * sizeof(double));
+    AXS_HIP(hipMemcpy(c.sctab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+
     std::vector<int64_t> bo;
     for (auto &b : c.bodies) bo.push_back(b.offset);
     bo.push_back(N);
@@ -909,20 +961,20 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
         if (variant == 2)                                                                                  \
             hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, NR_, BS, LAP>), dim3(nwork, groups), dim3(BS), 0, \
                                c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta, \
-                               part);                                                                      \
+                               c.sctab, part);                                                             \
         else                                                                                               \
             hipLaunchKernelGGL((interbody_kernel<R, TPT, NR_, BS, LAP>), dim3(nwork, groups), dim3(BS), 0, \
-                               c.stream, work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, part);             \
+                               c.stream, work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, c.sctab, part);    \
     }
         if constexpr (sizeof(R) == 4 && BS == 128 && TPT <= 2) {
             if (nr == 32)
                 hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, 32, BS, LAP>), dim3(nwork, groups), dim3(BS), 0,
                                    c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta,
-                                   part);
+                                   c.sctab, part);
             if (nr == 16)
                 hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, 16, BS, LAP>), dim3(nwork, groups), dim3(BS), 0,
                                    c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta,
-                                   part);
+                                   c.sctab, part);
         } else {
             if (nr > 8) throw Error{AXS_EINVAL, "wide rhs groups need FP32 rings, 128 threads, <= 2 targets"};
         }
@@ -955,7 +1007,7 @@ static void launch_mf(Ctx &c, const IBWork *work, int nwork, const typename C2T<
 #define AXS_MF_NR(NR_)                                                                                      \
     if (nr == NR_)                                                                                         \
         hipLaunchKernelGGL((interbody_mfma_kernel<R, G, NR_>), dim3(nwork, groups), dim3(256), 0, c.stream, \
-                           work, geo, sop, q, c.body_off, nb, frame, c.N, nrhs, c0, s2, etap, part);
+                           work, geo, sop, q, c.body_off, nb, frame, c.N, nrhs, c0, s2, etap, c.sctab, part);
         AXS_MF_NR(16)
         AXS_MF_NR(8)
         AXS_MF_NR(4)
