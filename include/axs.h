@@ -215,6 +215,42 @@ axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant,
  * AXS_EINVAL if the configured shape does not fit the context. */
 axs_status axs_interbody_launch_shape(axs_ctx *ctx, int precision, int nrhs, int *out);
 
+/* ------------------------------------------------------------------------
+ * Skeletonization (Sec. 5, eqs. ip0-ip6): each off-diagonal block is factored
+ * as U_p A_pq(I_p, I_q) V_q^* by interpolative decompositions, and GMRES runs on
+ * the smaller system  s~ + S B~ s~ = -v~  with S_p = V_p^* A_pp^{-1} U_p,
+ * v~_p = V_p^* A_pp^{-1} v_p, B~ the inter-body sum over the skeleton nodes;
+ * the full density is s_p = -A_pp^{-1} (v_p + U_p (B~ s~)_p).  Skeletons are
+ * whole rings (contour nodes with all their azimuthal nodes): U_p = X (x) I,
+ * V_p^* = X^T (x) I with one X (NG x k) per shape from the row ID, over the
+ * contour index, of the fields of combined-field sources on a proxy sphere at
+ * the contour nodes and of the contour nodes' fields at two proxy spheres,
+ * all Fourier modes stacked; so S_p is k x k per mode and B~ a ring-order sum.
+ * ------------------------------------------------------------------------ */
+
+/* Build the skeleton system after axs_precompute_scattering.
+ *  eps          : relative tolerance of the IDs (pivoted Gram-Schmidt stops when
+ *                 the pivot norm falls below eps x the first one), e.g. 1e-8.
+ *  proxy_factor : proxy radius = min(proxy_factor x bounding radius, distance to
+ *                 the nearest other body's bounding ball) over the bodies of a
+ *                 shape; a shape whose proxy radius is below 1.05 x its bounding
+ *                 radius keeps all its rings.  2.0 is typical.
+ *  out_nskel    : host int64, number of skeleton nodes (may be NULL).
+ * FP64 on the device; replaces an earlier skeleton system of the context. */
+axs_status axs_skeletonize(axs_ctx *ctx, double eps, double proxy_factor, int64_t *out_nskel);
+
+/* Skeleton rings k and contour nodes NG of a body's shape (host ints). */
+axs_status axs_skeleton_rank(axs_ctx *ctx, int body_id, int *rings, int *contour_nodes);
+
+/* Solve through the skeleton system; incident and sigma as for axs_solve
+ * (device complex128 [nrhs][N], full-size).  mode: AXS_SOLVE_FP64 or
+ * AXS_SOLVE_MIXED for the GMRES on the compressed system, whose residual info
+ * reports; with | AXS_SOLVE_CERTIFY, info reports instead the residual of the
+ * lifted sigma in the full system (one FP64 application of I + D^{-1} B), which
+ * also includes the skeletonization error. */
+axs_status axs_solve_skeleton(axs_ctx *ctx, const void *incident, void *sigma, int nrhs, int mode,
+                              double tol, int max_iters, axs_solve_info *info);
+
 /* ------------------------------------------------------------------------ *
  * Learned warm start.  A multilayer perceptron maps (incident direction,
  * scaled wavenumber) to the low azimuthal modes of the density; it is

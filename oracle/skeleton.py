@@ -35,7 +35,7 @@ import math
 import numpy as np
 import scipy.linalg as sla
 
-from .modal import modal_kernels
+from .modal import default_nt, modal_kernels
 from .multibody import System, apply_B_c, gmres
 
 
@@ -51,7 +51,7 @@ def proxy_rings(R: float, n: int):
 def modal_blocks(shape, R_p: float, n_in: int, n_out: int):
     """IN (M+1, NG, n_in) and OUT (M+1, 2 n_out, NG) of the docstring."""
     sh = shape
-    Nt = sh.Nt
+    Nt = default_nt(sh.kappa, 1.25 * R_p)     # band limit of the azimuthal integrands out to the proxy
     r_, z_, nr_, nz_, w_ = proxy_rings(R_p, n_in)
     # incoming: target body node i, source proxy node j (its normal, its weight)
     ti, sj = np.meshgrid(np.arange(sh.NG), np.arange(n_in), indexing="ij")

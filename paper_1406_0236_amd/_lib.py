@@ -71,6 +71,12 @@ EXPORTS = {
                                        ctypes.c_int, ctypes.c_void_p]),
     "axs_set_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int]),
     "axs_last_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "axs_skeletonize": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_int64)]),
+    "axs_skeleton_rank": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int)]),
+    "axs_solve_skeleton": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.POINTER(SolveInfo)]),
     "axs_interbody_launch_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                                     ctypes.POINTER(ctypes.c_int)]),
     "axs_set_interbody_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -243,6 +249,31 @@ class Context:
         ps, _ = self._vec(sig)
         info = (SolveInfo * nrhs)()
         st = self.lib.axs_solve(self.h, pv, p0, ps, nrhs, int(mode), float(tol), int(max_iters), info)
+        self._check(st, soft_ok=True)
+        return sig, [i.as_dict() for i in info]
+
+    # -- skeletonization (Sec. 5) ----------------------------------------------------
+    def skeletonize(self, eps=1e-8, proxy_factor=2.0):
+        """axs_skeletonize; returns the number of skeleton nodes."""
+        n = ctypes.c_int64()
+        self._check(self.lib.axs_skeletonize(self.h, float(eps), float(proxy_factor), ctypes.byref(n)))
+        return n.value
+
+    def skeleton_rank(self, body_id):
+        """(skeleton rings, contour nodes) of a body's shape."""
+        k, ng = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.axs_skeleton_rank(self.h, int(body_id), ctypes.byref(k), ctypes.byref(ng)))
+        return k.value, ng.value
+
+    def solve_skeleton(self, incident, mode=SOLVE_FP64, tol=1e-7, max_iters=200, out=None, certify=False):
+        """axs_solve_skeleton; certify=True reports the full-system residual of the lifted sigma."""
+        if certify:
+            mode = int(mode) | SOLVE_CERTIFY
+        pv, nrhs = self._vec(incident)
+        sig = self._empty(nrhs) if out is None else out
+        ps, _ = self._vec(sig)
+        info = (SolveInfo * nrhs)()
+        st = self.lib.axs_solve_skeleton(self.h, pv, ps, nrhs, int(mode), float(tol), int(max_iters), info)
         self._check(st, soft_ok=True)
         return sig, [i.as_dict() for i in info]
 

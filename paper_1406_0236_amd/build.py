@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["api.hip", "interbody.hip", "modal.hip", "setup.hip", "krylov.hip", "mlp.hip"]
+SOURCES = ["api.hip", "interbody.hip", "modal.hip", "setup.hip", "krylov.hip", "mlp.hip", "skeleton.hip"]
 LIB = os.path.join(HERE, "libaxs.so")
 # MFMA results of the inter-body kernels feed VALU arithmetic at once: keep
 # them in ordinary VGPRs instead of accumulation registers (saves two

@@ -128,6 +128,12 @@ void apply_precond(Ctx &c, const void *x, void *y, int nrhs, int prec, double be
 static void precompute_all(Ctx &c) {
     AXS_REQUIRE(!c.bodies.empty(), AXS_ESTATE, "no bodies");
     for (auto &s : c.shapes) precompute_shape(c, s);
+    finish_precompute(c);
+}
+
+// everything after the per-shape matrices: GEMM operands, DFT layout, node
+// arrays, ring tables (also used for the skeleton context, whose S_m are given)
+void finish_precompute(Ctx &c) {
     // planar copies of all S_m in one allocation per precision (GEMM operands)
     int64_t total = 0;
     std::vector<int64_t> soff(c.shapes.size());
@@ -140,8 +146,10 @@ static void precompute_all(Ctx &c) {
     float *r32 = (float *)c.dalloc(total * sizeof(float));
     float *i32 = (float *)c.dalloc(total * sizeof(float));
     // the same layout for A~_m itself (FP64), used only by the unpreconditioned operator
-    double *ar64 = (double *)c.dalloc(total * sizeof(double));
-    double *ai64 = (double *)c.dalloc(total * sizeof(double));
+    bool have_A = true;
+    for (auto &s : c.shapes) have_A = have_A && s.A64 != nullptr;
+    double *ar64 = have_A ? (double *)c.dalloc(total * sizeof(double)) : nullptr;
+    double *ai64 = have_A ? (double *)c.dalloc(total * sizeof(double)) : nullptr;
     for (size_t k = 0; k < c.shapes.size(); ++k) {
         Shape &s = c.shapes[k];
         s.S64r = r64 + soff[k];
@@ -149,9 +157,11 @@ static void precompute_all(Ctx &c) {
         s.S32r = r32 + soff[k];
         s.S32i = i32 + soff[k];
         split_planar(c, s, s.S64, s.S64r, s.S64i, s.S32r, s.S32i);
-        s.A64r = ar64 + soff[k];
-        s.A64i = ai64 + soff[k];
-        split_planar(c, s, s.A64, s.A64r, s.A64i, nullptr, nullptr);
+        if (have_A) {
+            s.A64r = ar64 + soff[k];
+            s.A64i = ai64 + soff[k];
+            split_planar(c, s, s.A64, s.A64r, s.A64i, nullptr, nullptr);
+        }
     }
     // DFT workspace layout per shape and the batched GEMM table
     std::vector<GemmBatch> gb;
@@ -604,6 +614,77 @@ axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant, in
         c.ib_block[pi] = block;
         c.ib_splits[pi] = splits;
         return AXS_OK;
+    });
+}
+
+axs_status axs_skeletonize(axs_ctx *ctx, double eps, double proxy_factor, int64_t *out_nskel) {
+    return guarded(ctx, [&](Ctx &c) -> axs_status {
+        skeletonize(c, eps, proxy_factor);
+        if (out_nskel) *out_nskel = c.skel->Ns;
+        return AXS_OK;
+    });
+}
+
+axs_status axs_skeleton_rank(axs_ctx *ctx, int body_id, int *rings, int *contour_nodes) {
+    return guarded(ctx, [&](Ctx &c) -> axs_status {
+        AXS_REQUIRE(c.skel, AXS_ESTATE, "call axs_skeletonize first");
+        AXS_REQUIRE(rings && contour_nodes, AXS_EINVAL, "null output");
+        AXS_REQUIRE(body_id >= 0 && body_id < (int)c.bodies.size(), AXS_EINVAL, "bad body id");
+        const int sh = c.bodies[body_id].shape;
+        *rings = c.skel->rank[sh];
+        *contour_nodes = c.shapes[sh].NG;
+        return AXS_OK;
+    });
+}
+
+axs_status axs_solve_skeleton(axs_ctx *ctx, const void *incident, void *sigma, int nrhs, int mode, double tol,
+                              int max_iters, axs_solve_info *info) {
+    return guarded(ctx, [&](Ctx &c) -> axs_status {
+        AXS_REQUIRE(c.skel, AXS_ESTATE, "call axs_skeletonize first");
+        AXS_REQUIRE(incident && sigma && nrhs >= 1 && nrhs <= 4096 && max_iters >= 1 && max_iters <= 2000,
+                    AXS_EINVAL, "bad arguments");
+        AXS_REQUIRE(incident != sigma, AXS_EINVAL, "sigma must not alias the incident field");
+        const bool certify = (mode & AXS_SOLVE_CERTIFY) != 0;
+        const int base = mode & ~AXS_SOLVE_CERTIFY;
+        AXS_REQUIRE(base == AXS_SOLVE_FP64 || base == AXS_SOLVE_MIXED, AXS_EINVAL, "bad solve mode");
+        AXS_REQUIRE(tol > 0 && tol < 1, AXS_EINVAL, "tol must be in (0, 1)");
+        Ctx &ch = *c.skel->child;
+        const int64_t N = c.N, Ns = c.skel->Ns;
+        double2 *y = (double2 *)c.dalloc((size_t)N * nrhs * sizeof(double2));
+        double2 *u = (double2 *)c.dalloc((size_t)N * nrhs * sizeof(double2));
+        double2 *bs = (double2 *)c.dalloc((size_t)Ns * nrhs * sizeof(double2));
+        double2 *xs = (double2 *)c.dalloc((size_t)Ns * nrhs * sizeof(double2));
+        double2 *ws = (double2 *)c.dalloc((size_t)Ns * nrhs * sizeof(double2));
+        const auto t0 = std::chrono::steady_clock::now();
+        apply_precond(c, incident, y, nrhs, AXS_FP64, 1.0);           // D^{-1} v
+        skel_restrict(c, y, bs, nrhs, -1.0);                           // -v~ = -V^* D^{-1} v
+        axs_status st = solve_impl(ch, nullptr, nullptr, xs, nrhs, base, tol, max_iters, info, bs);
+        interbody_partials(ch, xs, nrhs, AXS_FP64);                    // B~ s~
+        interbody_reduce_to_c128(ch, ws, nrhs, AXS_FP64);
+        skel_prolong(c, ws, incident, u, nrhs);                         // v + U B~ s~
+        apply_precond(c, u, sigma, nrhs, AXS_FP64, -1.0);              // s = -D^{-1} (...)
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (info)
+            for (int cc = 0; cc < nrhs; ++cc) info[cc].seconds = secs;
+        if (certify) {
+            // residual of the lifted sigma in the full system: b - (I + D^{-1} B) sigma, b = -D^{-1} v
+            apply_operator(c, sigma, u, nrhs, AXS_FP64);
+            bool ok = true;
+            for (int cc = 0; cc < nrhs; ++cc) {
+                const double2 *uc = u + (int64_t)cc * N, *yc = y + (int64_t)cc * N;
+                const double num = skel_residual_sumsq(c, uc, yc, N), den = skel_sumsq(c, yc, N);
+                const double rel = std::sqrt(num / (den > 0 ? den : 1.0));
+                if (info) {
+                    info[cc].rel_residual = rel;
+                    info[cc].converged = rel <= tol ? 1 : 0;
+                }
+                ok = ok && rel <= tol;
+            }
+            if (st == AXS_OK && !ok) st = AXS_NOT_CONVERGED;
+        }
+        for (void *q : {(void *)y, (void *)u, (void *)bs, (void *)xs, (void *)ws}) c.dfree(q);
+        return st;
     });
 }
 

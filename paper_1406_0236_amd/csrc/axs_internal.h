@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "../../include/axs.h"
@@ -104,6 +105,14 @@ struct GemmBatch {
     int32_t NG, ncols;   // ncols for nrhs = 1
 };
 
+// skeleton descriptor of one body: its full and skeleton node offsets, contour
+// nodes, skeleton rings, azimuthal nodes, offset of its shape's X (NG x k)
+struct SkelBody {
+    int64_t o0, s0, xoff;
+    int32_t NG, k, NF, pad;
+};
+struct Skeleton;
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -167,6 +176,9 @@ struct Ctx {
     // stays inside the hardware sin/cos input range (ring and MFMA orders rely on it)
     bool near_phase_ok = false;
 
+    // ring skeletonization (Sec. 5): the compressed system and its factors
+    std::unique_ptr<Skeleton> skel;
+
     // timing
     bool timing = false;
     hipEvent_t ev[6] = {};
@@ -202,11 +214,28 @@ enum ScratchSlot {
     WS_EVAL = 15,
 };
 
+struct Skeleton {
+    std::unique_ptr<Ctx> child;          // skeleton rings of every body, S~_m = X^T S_m X
+    double2 *X = nullptr;                // per shape NG x k (row-major, columns by ascending ring)
+    SkelBody *desc = nullptr;            // [bodies]
+    std::vector<int> rank;               // skeleton rings per shape
+    int64_t Ns = 0;                      // skeleton nodes
+    double eps = 0;
+};
+
 // ---------------------------------------------------------------------------
 // launches (defined in the .hip files)
 // ---------------------------------------------------------------------------
 // setup.hip
 void precompute_shape(Ctx &c, Shape &s);
+void gauss_legendre_rule(int n, std::vector<double> &x, std::vector<double> &w);
+// k^G_m w (m = 0..M) for arbitrary (target ring, source ring) pairs: host arrays
+// pts[7][P] = (r_t, r_s, r_s - r_t, z_s - z_t, n_r, n_z of the source, weight);
+// result on the device, [P][M+1]
+void modal_values(Ctx &c, double kappa, double gam_re, double gam_im, int M, int Nt,
+                  const std::vector<double> &pts, int64_t P, double2 *kout);
+// api.hip
+void finish_precompute(Ctx &c);
 // interbody.hip
 void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec);   // -> WS_PART
 void interbody_reduce_to_c128(Ctx &c, void *y, int nrhs, int prec, bool add = false);  // WS_PART -> (+)y
@@ -225,9 +254,17 @@ void modal_gemm(Ctx &c, int prec, int nrhs, bool forward = false);
 // y = alpha * sigma + beta * inverse DFT
 void dft_inverse(Ctx &c, int prec, const void *sigma, double alpha, double beta, void *y,
                  int nrhs);
+// skeleton.hip
+void skeletonize(Ctx &c, double eps, double proxy_factor);
+void skel_restrict(Ctx &c, const void *y, void *out, int nrhs, double alpha);      // out = alpha (X^T (x) I) y
+void skel_prolong(Ctx &c, const void *w, const void *add, void *out, int nrhs);   // out = add + (X (x) I) w
+double skel_sumsq(Ctx &c, const double2 *a, int64_t n);
+double skel_residual_sumsq(Ctx &c, const double2 *a, const double2 *b, int64_t n);   // sum |a + b|^2
 // krylov.hip
+// b_given: the right-hand side b itself (instead of b = -D^{-1} incident)
 axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *sigma, int nrhs,
-                      int mode, double tol, int max_iters, axs_solve_info *info);
+                      int mode, double tol, int max_iters, axs_solve_info *info,
+                      const void *b_given = nullptr);
 // api-level helpers
 void apply_operator(Ctx &c, const void *sigma, void *y, int nrhs, int prec);  // y = sigma + D^-1 B sigma
 void apply_precond(Ctx &c, const void *x, void *y, int nrhs, int prec, double beta);  // y = beta D^-1 x

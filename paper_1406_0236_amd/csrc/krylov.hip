@@ -345,7 +345,7 @@ static std::vector<double> norms(Ctx &c, const double2 *v, int64_t N, int nrhs) 
 }
 
 axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *sigma_out, int nrhs, int mode,
-                      double tol, int max_iters, axs_solve_info *info) {
+                      double tol, int max_iters, axs_solve_info *info, const void *b_given) {
     const auto t0 = std::chrono::steady_clock::now();
     const bool certify = (mode & AXS_SOLVE_CERTIFY) != 0;
     const bool unprec = (mode & AXS_SOLVE_UNPRECONDITIONED) != 0;
@@ -361,8 +361,10 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
     double2 *b = (double2 *)c.dalloc(vb);
     double2 *r = (double2 *)c.dalloc(vb);
     double2 *tmp = (double2 *)c.dalloc(vb);
-    // b = -D^{-1} v, or -v without the preconditioner
-    if (unprec) {
+    // b = -D^{-1} v, or -v without the preconditioner, or given
+    if (b_given) {
+        AXS_HIP(hipMemcpyAsync(b, b_given, vb, hipMemcpyDeviceToDevice, c.stream));
+    } else if (unprec) {
         AXS_HIP(hipMemsetAsync(tmp, 0, vb, c.stream));
         hipLaunchKernelGGL(csub_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, tmp,
                            (const double2 *)incident, b, tot);

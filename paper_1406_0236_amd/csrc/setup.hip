@@ -489,7 +489,9 @@ __global__ void split_planar_kernel(const double2 *__restrict__ S, int M, int NG
 // ---------------------------------------------------------------------------
 // host: Gauss-Legendre rule by Newton's method on the three-term recurrence
 // ---------------------------------------------------------------------------
-static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+void gauss_legendre_rule(int n, std::vector<double> &x, std::vector<double> &w);
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) { gauss_legendre_rule(n, x, w); }
+void gauss_legendre_rule(int n, std::vector<double> &x, std::vector<double> &w) {
     x.assign(n, 0.0);
     w.assign(n, 0.0);
     for (int i = 0; i < n; ++i) {
@@ -715,6 +717,25 @@ void precompute_shape(Ctx &c, Shape &s) {
     for (void *ptr : {(void *)d_sn, (void *)d_lden, (void *)d_gu, (void *)d_gw, (void *)d_r, (void *)d_z,
                       (void *)d_nr, (void *)d_nz, (void *)d_aw})
         c.dfree(ptr);
+}
+
+void modal_values(Ctx &c, double kappa, double gam_re, double gam_im, int M, int Nt,
+                  const std::vector<double> &h, int64_t P, double2 *kout) {
+    const int L = Nt / 2 - 1, nq = M + L + 1;
+    double *pbuf = (double *)c.scratch(WS_MISC, (size_t)P * 7 * sizeof(double));
+    AXS_HIP(hipMemcpy(pbuf, h.data(), (size_t)P * 7 * sizeof(double), hipMemcpyHostToDevice));
+    Pts pts{pbuf, pbuf + P, pbuf + 2 * P, pbuf + 3 * P, pbuf + 4 * P, pbuf + 5 * P, pbuf + 6 * P, nullptr};
+    double *qv = (double *)c.scratch(WS_TMP, (size_t)P * nq * sizeof(double));
+    double *dqv = (double *)c.scratch(WS_TMP2, (size_t)P * nq * sizeof(double));
+    hipLaunchKernelGGL(toroidal_kernel, dim3(ceil_div(P, 64)), dim3(64), 0, c.stream, pts, P, nq - 1, qv, dqv);
+    AXS_HIP(hipGetLastError());
+    constexpr int WPB = 4;
+    const int per = 4 * (Nt / 2 + 1) + 2 * (L + 1) + 2 * (M + 1) + 2 * nq;
+    const size_t shm = (Nt + WPB * per) * sizeof(double);
+    AXS_REQUIRE(shm <= 160 * 1024, AXS_EINVAL, "mode count or wavenumber too large for the modal kernel");
+    hipLaunchKernelGGL(modal_kernel<WPB>, dim3(ceil_div(P, WPB)), dim3(64 * WPB), shm, c.stream, pts, P, Nt, M,
+                       qv, dqv, kappa, gam_re, gam_im, kout);
+    AXS_HIP(hipGetLastError());
 }
 
 void split_planar(Ctx &c, Shape &s, const double *src, double *r64, double *i64, float *r32, float *i32) {
