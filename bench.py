@@ -115,6 +115,9 @@ def main():
                     help="time the per-mode scattering applies (MFMA GEMM) with HIP events: 27 spheres "
                          "with 1 and 16 rhs, 8 mixed bodies with 64 rhs, FP32 and FP64; also the launches "
                          "the matrix-core counter passes measure")
+    ap.add_argument("--skeleton", action="store_true",
+                    help="the 27-sphere benchmark through the ring skeletonization of Sec. 5: ID time, "
+                         "ranks, compressed mixed and FP64 solves, full-system residual of the lifted density")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="launch only what the hardware-counter passes measure: a 512 MiB device copy "
                          "(calibration), then two FP32 and one FP64 inter-body sums on the 27 spheres")
@@ -141,6 +144,8 @@ def main():
         return many(args)
     if args.laplace:
         return laplace(args)
+    if args.skeleton:
+        return skeleton(args)
 
     wl = configs.two_spheres() if args.small else configs.sphere_lattice()
     log(f"workload {wl.name}: N={wl.N}, pairs={wl.pairs:.4g}")
@@ -535,6 +540,54 @@ def modal_probe():
                 log(f"modal GEMM {row}")
         ctx.close()
     print(json.dumps({"modal_gemm": rows}), flush=True)
+
+
+def skeleton(args, eps=1e-8):
+    """The benchmark problem solved through the compressed system of Sec. 5."""
+    import numpy as np
+    import torch
+    from paper_1406_0236_amd import FP32, FP64, SOLVE_FP64, SOLVE_MIXED, Context
+    from workloads import configs
+    wl = configs.sphere_lattice()
+    ctx = Context(0).add_workload(wl)
+    ctx.precompute_scattering()
+    v = ctx.incident_plane_waves(wl.dirs)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ns = ctx.skeletonize(eps, 2.0)
+    torch.cuda.synchronize()
+    t_id = time.time() - t0
+    k, ng = ctx.skeleton_rank(0)
+    log(f"skeletonize (eps {eps}): {t_id:.2f} s, rings {k} of {ng}, {ns} of {wl.N} unknowns")
+    runs = {}
+    for name, mode in (("mixed", SOLVE_MIXED), ("fp64", SOLVE_FP64)):
+        ctx.solve_skeleton(v, mode=mode, tol=args.tol)          # warm-up
+        ts = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            sol, info = ctx.solve_skeleton(v, mode=mode, tol=args.tol)
+            torch.cuda.synchronize()
+            ts.append(time.time() - t0)
+        b_ = ctx.apply_precond(v, FP64)
+        full_res = float(torch.linalg.norm(ctx.apply_matvec(sol, FP64) + b_) / torch.linalg.norm(b_))
+        runs[name] = {"s": float(np.median(ts)), "iterations": info[0]["iterations"],
+                      "inner": info[0]["inner_iterations"], "compressed_rel_residual": info[0]["rel_residual"],
+                      "full_rel_residual": full_res}
+        log(f"{name}: {runs[name]}")
+    ref, info_ref = ctx.solve(v, mode=SOLVE_MIXED, tol=args.tol)
+    diff = float(torch.linalg.norm(sol - ref) / torch.linalg.norm(ref))
+    out = {
+        "metric": "s to 1e-7 residual of the compressed system (Sec. 5 skeletonization), 27 spheres",
+        "value": runs["mixed"]["s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": runs["mixed"]["s"] * 1e3, "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": wl.name, "N": wl.N, "eps": eps, "proxy_factor": 2.0, "tol": args.tol},
+        "skeletonize_s": t_id, "rings": [k, ng], "skeleton_unknowns": ns, "solves": runs,
+        "rel_diff_vs_uncompressed_mixed": diff,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 def batched(args):

@@ -81,3 +81,30 @@ def test_fullsize_solve_residual_certified_on_one_body(lattice):
     e = np.linalg.norm(r) / np.linalg.norm(bfull)
     print(f"body {b_id}: reference residual {e:.2e} (library total {info[0]['rel_residual']:.2e})")
     assert e <= 1.2e-7
+
+
+def test_fullsize_skeleton_solve(lattice):
+    """The benchmark problem through the ring skeletonization (Sec. 5, eps = 1e-8):
+    the ring rank equals the reference's ID of the same shape and proxy sphere
+    (within 2), and the lifted density of a mixed solve to 1e-7 has a full-system
+    FP64 residual below 1e-7 and agrees with the uncompressed mixed solution to
+    the solve tolerance."""
+    from oracle.nystrom import Shape
+    from oracle.skeleton import ring_id
+    from paper_1406_0236_amd import SOLVE_MIXED
+    wl, S, ctx = lattice
+    ns = ctx.skeletonize(1e-8, 2.0)
+    k, ng = ctx.skeleton_rank(0)
+    c = wl.bodies[0].contour
+    sh = Shape(c.rz, c.drz, c.gw, c.n_panels, c.p, wl.kappa, wl.eta, wl.bodies[0].M)
+    kr = ring_id(sh, 2.0, 1e-8)[1].shape[1]
+    print(f"rings {k} of {ng} (reference {kr}), {ns} of {wl.N} unknowns", flush=True)
+    assert abs(k - kr) <= 2 and ns == 27 * k * sh.NF
+    v = ctx.incident_plane_waves(wl.dirs)
+    sol, info = ctx.solve_skeleton(v, mode=SOLVE_MIXED, tol=1e-7, certify=True)
+    ref, _ = ctx.solve(v, mode=SOLVE_MIXED, tol=1e-7)
+    d = float(torch.linalg.norm(sol - ref) / torch.linalg.norm(ref))
+    print(f"skeleton solve: {info[0]['iterations']} outer, {info[0]['inner_iterations']} inner, "
+          f"full residual {info[0]['rel_residual']:.2e}, vs uncompressed {d:.2e}")
+    assert info[0]["rel_residual"] < 1e-7
+    assert d < 1e-6
