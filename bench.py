@@ -418,6 +418,18 @@ def many(args):
     log(f"fp64 {t64:.1f} s (iterations {max(i['iterations'] for i in info64)})")
     b_ = ctx.apply_precond(v, FP64)
     res = (torch.linalg.norm(ctx.apply_matvec(sol, FP64) + b_, dim=1) / torch.linalg.norm(b_, dim=1)).max().item()
+    # the same solve through the ring skeletonization of Sec. 5
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ns = ctx.skeletonize(1e-8, 2.0)
+    torch.cuda.synchronize()
+    t_id = time.time() - t0
+    t0 = time.time()
+    sk, info_sk = ctx.solve_skeleton(v, mode=SOLVE_MIXED, tol=args.tol)
+    torch.cuda.synchronize()
+    t_sk = time.time() - t0
+    res_sk = (torch.linalg.norm(ctx.apply_matvec(sk, FP64) + b_, dim=1) / torch.linalg.norm(b_, dim=1)).max().item()
+    log(f"skeleton: {ns} of {wl.N} unknowns, ID {t_id:.1f} s, mixed solve {t_sk:.1f} s, full residual {res_sk:.2e}")
     flops = wl.pairs * (FLOP_PER_PAIR + FLOP_PER_EXTRA_RHS * (r - 1))
     out = {
         "metric": "s to 1e-7 residual, 16 rhs batched (mixed vs FP64 GMRES)",
@@ -438,6 +450,9 @@ def many(args):
         "interbody_launch_shape": {"fp32": list(ctx.interbody_launch_shape(FP32, r)),
                                    "fp64": list(ctx.interbody_launch_shape(FP64, r))},
         "tflops_fp32_algorithmic": flops / t_ib / 1e12,
+        "skeleton": {"unknowns": ns, "skeletonize_s": t_id, "mixed_s": t_sk,
+                     "outer": max(i["iterations"] for i in info_sk),
+                     "inner": max(i["inner_iterations"] for i in info_sk), "max_full_rel_residual": res_sk},
     }
     print(json.dumps(out), flush=True)
     ctx.close()
