@@ -34,8 +34,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a calibration copy
 # (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
 # source they were taken on.
-TRAFFIC_BYTES = 80.15e6
-TRAFFIC_SOURCE_SHA = "982a1944f26524c1"
+TRAFFIC_BYTES = 115.14e6
+TRAFFIC_SOURCE_SHA = "7f10ff8dc204ae61"
 
 
 def log(msg):
@@ -124,7 +124,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is described in DESIGN.md", file=sys.stderr)
+              "the decomposition over several GPUs is a design, not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -193,7 +193,8 @@ axs_status axs_last_timing(axs_ctx *ctx, double ms[5]);
 
 /* Inter-body sum launch shape, per precision; 0 = library default for each field.
  *  variant: 1 = sources streamed as points, 2 = sources streamed as azimuthal rings
- *           (per target and ring, R^2 and n.d become two FMAs each; needs kappa > 0),
+ *           in mirror pairs (azimuths l and N_F - l): per target and ring, R^2
+ *           of a pair costs 3 FMAs and n.d one each (needs N_F/2 + 1 <= block),
  *           3 = MFMA order, kappa > 0: R^2 and n.d of 16 x 16 (source,
  *           target) blocks from matrix-core products of 4-vectors in the source
  *           body's frame; with 16 right-hand sides per group the complex

@@ -157,8 +157,9 @@ struct Ctx {
     // ring tables (one ring = one contour node of one body = its N_F azimuthal nodes)
     int nrings = 0;
     std::vector<int64_t> ring_base;      // first ring id of each body
-    int32_t *ring_i = nullptr;           // [3][nrings]: node offset, N_F, body
-    double *ring_g64 = nullptr;          // [4][nrings]: r, z, n_r, n_z
+    int32_t *ring_i = nullptr;           // [3][nrings]: node offset, N_F, body; [nrings + 1]: first mirror-pair entry
+    int2 *ring_pair = nullptr;           // [entries]: node of azimuth e, node of N_F - e (-1: none)
+    double *ring_g64 = nullptr;          // [5][nrings]: r, z, n_r, n_z, -n_r / (2 r)
     float *ring_g32 = nullptr;
     double *frame64 = nullptr;           // [B][FRAME]: centre, rotation (row-major), bound radius
     float *frame32 = nullptr;

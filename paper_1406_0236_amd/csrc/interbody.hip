@@ -258,19 +258,78 @@ __global__ __launch_bounds__(BS) void interbody_kernel(
     }
 }
 
-// LDS stride of one staged ring node: cos, sin + NR complex q, 16-byte rounded.
-template <typename R, int NR> struct RingStride {
-    static constexpr int raw = 2 + 2 * NR;
+// LDS stride of one staged mirror pair: cos, sin + NR complex q of azimuth l
+// + NR complex q of azimuth N_F - l, 16-byte rounded.  With one right-hand
+// side (FOLD) each node carries the six density terms of ring_term1 instead.
+template <typename R, int NR, bool FOLD> struct RingStride {
+    static constexpr int raw = FOLD ? 14 : 2 + 4 * NR;
     static constexpr int per16 = 16 / sizeof(R);
     static constexpr int value = (raw + per16 - 1) / per16 * per16;
 };
 
 // Ring variant.  Work items hold ring-id ranges; rings are numbered in node
-// order, so a ring range is a contiguous node range.  Sources are staged in
-// LDS a tile of whole rings at a time (at most BS nodes).
+// order.  A ring's azimuths are theta_l = 2 pi l / N_F, so in the source
+// body's frame the nodes l and N_F - l are mirror images in y: same cos, sin
+// of opposite sign.  The ring is staged as N_F/2 + 1 entries e, each holding
+// node e and its mirror N_F - e (none for e = 0 and e = N_F/2), and R'^2,
+// nd' of both come from one shared partial sum: 3 FMAs per pair instead of 4
+// (an entry without a mirror carries zero density).  Sources are staged in
+// LDS a tile of whole rings at a time (at most BS entries).
 struct RingTabs {
     const int32_t *off, *nf, *body;   // [nrings]
+    const int32_t *eoff;              // [nrings + 1]: first entry of each ring
+    const int2 *pair;                 // [entries]: node of azimuth e, node of N_F - e (-1: none)
 };
+
+// One pair's contribution, accumulated into NR right-hand sides.
+// r2 = R'^2, nd = nd' (R' = R k/2pi, nd' = n.d (k/2pi)^3), n0 whole revolutions.
+template <typename R, int NR, bool LAP>
+__device__ __forceinline__ void ring_term(R r2, R nd, R n0, R eta, R etap, const double2 *s_tab,
+                                          const R *qr, const R *qi, R *ar, R *ai) {
+    const R u = rsq(r2);   // 1 / R'
+    if constexpr (LAP) {
+        // kappa = 0 (scale factor 1): 4 pi G = (n.d / R^2 + eta) / R, real
+        const R G = u * fma(nd, u * u, eta);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            ar[c] = fma(G, qr[c], ar[c]);
+            ai[c] = fma(G, qi[c], ai[c]);
+        }
+    } else {
+        const R twopi = R(6.283185307179586476925287);
+        R sn, cs_;
+        sincos_near_any(fma(r2, u, -n0), s_tab, sn, cs_);   // phase R' = kR / 2pi revolutions
+        const R t = nd * (u * u);
+        const R P = t * u;                     // n.d / R^3
+        const R Q = fma(-twopi, t, etap * u);  // eta / R - k n.d / R^2
+        const R gr = fma(cs_, P, -sn * Q);
+        const R gi = fma(cs_, Q, sn * P);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            ar[c] = fma(gr, qr[c], fma(-gi, qi[c], ar[c]));
+            ai[c] = fma(gr, qi[c], fma(gi, qr[c], ai[c]));
+        }
+    }
+}
+
+// One pair's contribution to a single right-hand side.  With u = 1/R',
+//   G q = e^{2 pi i R'} (P + iQ) q = e^{2 pi i R'} u z,
+//   z = i eta' q + (nd' u) (u - 2 pi i) q,
+// so the terms of q that do not depend on the pair are staged with the source,
+// qv = (q_r, q_i, 2 pi q_i, -2 pi q_r, -eta' q_i, eta' q_r), and the pair
+// costs 11 operations after sin/cos instead of 13.
+template <typename R>
+__device__ __forceinline__ void ring_term1(R r2, R nd, R n0, const double2 *s_tab, const R *qv, R &ar, R &ai) {
+    const R u = rsq(r2);
+    R sn, cs_;
+    sincos_near_any(fma(r2, u, -n0), s_tab, sn, cs_);   // phase R' less whole revolutions
+    const R w = nd * u;
+    const R zr = fma(w, fma(u, qv[0], qv[2]), qv[4]);
+    const R zi = fma(w, fma(u, qv[1], qv[3]), qv[5]);
+    const R er = cs_ * u, ei = sn * u;
+    ar = fma(er, zr, fma(-ei, zi, ar));
+    ai = fma(er, zi, fma(ei, zr, ai));
+}
 
 template <typename R, int TPT, int NR, int BS, bool LAP>
 __global__ __launch_bounds__(BS) void interbody_ring_kernel(
@@ -279,7 +338,9 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
     const R *__restrict__ frame, int64_t N, int nrhs, int c0, R k2pi, R eta, const double2 *__restrict__ sctab,
     typename C2T<R>::T *__restrict__ part) {
     using R2 = typename C2T<R>::T;
-    constexpr int ST = RingStride<R, NR>::value;
+    constexpr bool FOLD = NR == 1 && !LAP;
+    constexpr int ST = RingStride<R, NR, FOLD>::value;
+    constexpr int QB = FOLD ? 8 : 2 + 2 * NR;   // offset of the mirror's densities in an entry
     __shared__ __align__(16) R tile[BS * ST];
     __shared__ double2 s_tab[sizeof(R) == 8 ? 256 : 1];
     load_sctab<R, BS>(s_tab, sctab);
@@ -290,9 +351,9 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
     const R *gx = geo, *gy = geo + N, *gz = geo + 2 * N;
     const R *gc = cs, *gs = cs + N;
     const R *rr_ = rg, *rz_ = rg + nrings, *rnr = rg + 2 * nrings, *rnz = rg + 3 * nrings;
+    const R *rho_ = rg + 4 * nrings;
     const R s2 = k2pi * k2pi, c1 = k2pi * k2pi * k2pi;
     const R etap = eta * k2pi;
-    const R twopi = R(6.283185307179586476925287);
 
     R tx[TPT], ty[TPT], tz[TPT];
     R px[TPT], py[TPT], pz[TPT], n0 = R(0);
@@ -317,25 +378,35 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
         int r0 = lo;
 #pragma unroll 1
         while (r0 < hi) {
-            // a tile of whole rings [r0, r1) holding at most BS nodes
-            const int nb = rt.off[r0];
-            int r1 = r0, cnt = 0;
-            while (r1 < hi && cnt + rt.nf[r1] <= BS) {
-                cnt += rt.nf[r1];
-                ++r1;
-            }
+            // a tile of whole rings [r0, r1) holding at most BS entries
+            const int e0 = rt.eoff[r0];
+            int r1 = r0;
+            while (r1 < hi && rt.eoff[r1 + 1] - e0 <= BS) ++r1;
             if (r1 == r0) break;   // a ring wider than a tile: the host never launches this
+            const int cnt = rt.eoff[r1] - e0;
             __syncthreads();
             if (tid < cnt) {
-                const int64_t j = (int64_t)nb + tid;
+                const int2 pr = rt.pair[e0 + tid];
                 R *d = tile + tid * ST;
-                d[0] = gc[j];
-                d[1] = gs[j];
+                d[0] = gc[pr.x];
+                d[1] = gs[pr.x];
 #pragma unroll
                 for (int c = 0; c < NR; ++c) {
-                    R2 v = q[(int64_t)(cb + c) * N + j];
-                    d[2 + 2 * c] = v.x;
-                    d[3 + 2 * c] = v.y;
+                    const R2 v = q[(int64_t)(cb + c) * N + pr.x];
+                    R2 m;
+                    m.x = m.y = R(0);
+                    if (pr.y >= 0) m = q[(int64_t)(cb + c) * N + pr.y];
+                    if constexpr (FOLD) {
+                        const R tp = R(6.283185307179586476925287);
+                        d[2] = v.x, d[3] = v.y, d[4] = tp * v.y, d[5] = -tp * v.x, d[6] = -etap * v.y, d[7] = etap * v.x;
+                        d[8] = m.x, d[9] = m.y, d[10] = tp * m.y, d[11] = -tp * m.x, d[12] = -etap * m.y,
+                        d[13] = etap * m.x;
+                    } else {
+                        d[2 + 2 * c] = v.x;
+                        d[3 + 2 * c] = v.y;
+                        d[QB + 2 * c] = m.x;
+                        d[QB + 1 + 2 * c] = m.y;
+                    }
                 }
             }
             __syncthreads();
@@ -363,58 +434,64 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                     prev_body = b;
                 }
                 const R rj = rr_[ring], zj = rz_[ring], nrj = rnr[ring], nzj = rnz[ring];
-                const int nf = rt.nf[ring];
-                const R *src = tile + (rt.off[ring] - nb) * ST;
-                // per target: R'^2 = al + Ax cos + Ay sin, nd' = be + Bx cos + By sin
-                // (R' = R k/2pi, nd' = n.d (k/2pi)^3)
-                R al[TPT], Ax[TPT], Ay[TPT], Bx[TPT], By[TPT], be[TPT];
+                const int ne = rt.eoff[ring + 1] - rt.eoff[ring];
+                const R *src = tile + (rt.eoff[ring] - e0) * ST;
+                // per target: R'^2 = al + Ax cos + Ay sin and nd' = be + Bx cos + By sin
+                // with (Bx, By) = kap (Ax, Ay), kap = -(k/2pi) n_r / (2 r) the same for
+                // every target, so nd' = kap R'^2 + beta, beta = be - kap al (one FMA
+                // per pair).  kap stays bounded for contours that meet the axis at
+                // a right angle (n_r ~ r there).  The ring table holds
+                // rho = -n_r / (2 r), 0 for a ring of radius 0 (zero area weight,
+                // hence zero density).
+                const R kap = rho_[ring] * k2pi;
+                R al[TPT], Ax[TPT], Ay[TPT], beta[TPT];
 #pragma unroll
                 for (int k = 0; k < TPT; ++k) {
                     const R pzp = pz[k] - zj;
                     al[k] = fma(px[k], px[k], fma(py[k], py[k], fma(pzp, pzp, rj * rj))) * s2;
                     Ax[k] = (R(-2) * s2 * rj) * px[k];
                     Ay[k] = (R(-2) * s2 * rj) * py[k];
-                    Bx[k] = (c1 * nrj) * px[k];
-                    By[k] = (c1 * nrj) * py[k];
-                    be[k] = fma(nzj, pzp, -nrj * rj) * c1;
+                    beta[k] = fma(-kap, al[k], fma(nzj, pzp, -nrj * rj) * c1);
                 }
-#pragma unroll sizeof(R) == 4 ? 2 : 1
-                for (int l = 0; l < nf; ++l) {
+                if constexpr (FOLD) {
+#pragma unroll 1
+                    for (int l = 0; l < ne; ++l) {
+                        const R *s = src + l * ST;
+                        const R cl = s[0], sl = s[1];
+                        R qv[6], mv[6];
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) {
+                            qv[i] = s[2 + i];
+                            mv[i] = s[8 + i];
+                        }
+#pragma unroll
+                        for (int k = 0; k < TPT; ++k) {
+                            const R br = fma(Ax[k], cl, al[k]);
+                            const R ra = fma(Ay[k], sl, br), rb = fma(-Ay[k], sl, br);
+                            ring_term1<R>(ra, fma(kap, ra, beta[k]), n0, s_tab, qv, ar[k][0], ai[k][0]);
+                            ring_term1<R>(rb, fma(kap, rb, beta[k]), n0, s_tab, mv, ar[k][0], ai[k][0]);
+                        }
+                    }
+                    continue;
+                }
+#pragma unroll 1
+                for (int l = 0; l < ne; ++l) {
                     const R *s = src + l * ST;
                     const R cl = s[0], sl = s[1];
-                    R qr[NR], qi[NR];
+                    R qr[NR], qi[NR], mr[NR], mi[NR];
 #pragma unroll
                     for (int c = 0; c < NR; ++c) {
                         qr[c] = s[2 + 2 * c];
                         qi[c] = s[3 + 2 * c];
+                        mr[c] = s[QB + 2 * c];
+                        mi[c] = s[QB + 1 + 2 * c];
                     }
 #pragma unroll
                     for (int k = 0; k < TPT; ++k) {
-                        const R r2 = fma(Ax[k], cl, fma(Ay[k], sl, al[k]));
-                        const R nd = fma(Bx[k], cl, fma(By[k], sl, be[k]));
-                        const R u = rsq(r2);                  // 1 / R'
-                        if constexpr (LAP) {
-                            // kappa = 0 (scale factor 1): 4 pi G = (n.d / R^2 + eta) / R, real
-                            const R G = u * fma(nd, u * u, eta);
-#pragma unroll
-                            for (int c = 0; c < NR; ++c) {
-                                ar[k][c] = fma(G, qr[c], ar[k][c]);
-                                ai[k][c] = fma(G, qi[c], ai[k][c]);
-                            }
-                            continue;
-                        }
-                        R sn, cs_;
-                        sincos_near_any(fma(r2, u, -n0), s_tab, sn, cs_);   // phase R' = kR / 2pi revolutions
-                        const R t = nd * (u * u);
-                        const R P = t * u;                    // n.d / R^3
-                        const R Q = fma(-twopi, t, etap * u);  // eta / R - k n.d / R^2
-                        const R gr = fma(cs_, P, -sn * Q);
-                        const R gi = fma(cs_, Q, sn * P);
-#pragma unroll
-                        for (int c = 0; c < NR; ++c) {
-                            ar[k][c] = fma(gr, qr[c], fma(-gi, qi[c], ar[k][c]));
-                            ai[k][c] = fma(gr, qi[c], fma(gi, qr[c], ai[k][c]));
-                        }
+                        const R br = fma(Ax[k], cl, al[k]);
+                        const R ra = fma(Ay[k], sl, br), rb = fma(-Ay[k], sl, br);
+                        ring_term<R, NR, LAP>(ra, fma(kap, ra, beta[k]), n0, eta, etap, s_tab, qr, qi, ar[k], ai[k]);
+                        ring_term<R, NR, LAP>(rb, fma(kap, rb, beta[k]), n0, eta, etap, s_tab, mr, mi, ar[k], ai[k]);
                     }
                 }
             }
@@ -749,18 +826,19 @@ static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
     const int pi = prec == AXS_FP32 ? 1 : 0;
     IBShape s;
     // Defaults from the launch-shape sweeps on MI355X (27-sphere lattice, one
-    // rhs; 8 mixed bodies, 1-64 rhs): below 16 rhs the ring order (2 targets
-    // per thread), from 16 rhs on the MFMA order (2 groups of 16 targets per
-    // wavefront in FP32, 4 in FP64); the point order where neither applies.
+    // rhs; 8 mixed bodies, 1-64 rhs): below 16 rhs the ring order (1 target
+    // per thread in FP32, 4 in FP64), from 16 rhs on the MFMA order (2 groups
+    // of 16 targets per wavefront in FP32, 4 in FP64); the point order where
+    // neither applies.
     s.bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : 256;
-    const bool ring_ok = c.max_nf <= s.bs && (c.kappa == 0 || c.near_phase_ok);
+    const bool ring_ok = c.max_nf / 2 + 1 <= s.bs && (c.kappa == 0 || c.near_phase_ok);
     const bool mf_ok = c.kappa > 0 && c.mf_src && c.near_phase_ok && s.bs == 256 &&
                        (c.ib_tpt[pi] == 0 || c.ib_tpt[pi] <= 4);
     s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi] : (nrhs >= 16 && mf_ok) ? 3 : ring_ok ? 2 : 1;
-    const int dflt = prec == AXS_FP32 ? 2 : s.variant == 2 ? 2 : 4;
+    const int dflt = prec == AXS_FP32 ? (s.variant == 2 ? 1 : 2) : 4;
     s.tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : dflt;
     AXS_REQUIRE(s.variant != 2 || ring_ok, AXS_EINVAL,
-                "ring variant needs N_F <= threads per block and bodies under 127 wavelengths across");
+                "ring variant needs N_F/2 + 1 <= threads per block and bodies under 127 wavelengths across");
     if (s.variant == 3) {
         AXS_REQUIRE(c.kappa > 0 && c.mf_src && c.near_phase_ok, AXS_EINVAL,
                     "MFMA variant needs kappa > 0 and bodies under 127 wavelengths across");
@@ -771,11 +849,14 @@ static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
     if (c.ib_splits[pi] > 0) {
         s.splits = c.ib_splits[pi];
     } else {
-        // enough blocks to fill 256 CUs several times over
+        // enough blocks to fill 256 CUs several times over; the FP32 ring order
+        // (8 resident blocks per CU) takes 16K so that the last, partly filled
+        // round of blocks is a small share of the launch
         int64_t tiles = 0;
         for (auto &b : c.bodies) tiles += ceil_div(b.n, (int64_t)ib_tile(s));
+        const int64_t want = (prec == AXS_FP32 && s.variant == 2) ? 16384 : 4096;
         s.splits = 1;
-        while (tiles * s.splits < 4096 && s.splits < 64) s.splits *= 2;
+        while (tiles * s.splits < want && s.splits < 64) s.splits *= 2;
     }
     return s;
 }
@@ -857,8 +938,10 @@ void build_ring_tables(Ctx &c) {
     double rmax = 0;
     for (auto &b : c.bodies) rmax = std::max(rmax, b.bound_radius);
     c.near_phase_ok = 4.0 * rmax * c.kappa / (2.0 * M_PI) + 2.0 < 256.0;
-    std::vector<int32_t> off(nr), nf(nr), body(nr);
-    std::vector<double> g(4 * (size_t)nr);
+    std::vector<int32_t> off(nr), nf(nr), body(nr), eoff(nr + 1, 0);
+    std::vector<int2> pairs;
+    std::vector<double> g(5 * (size_t)nr);
+    AXS_REQUIRE(N < (int64_t)INT32_MAX, AXS_EINVAL, "node count beyond 32-bit ring tables");
     for (size_t bi = 0; bi < c.bodies.size(); ++bi) {
         const auto &b = c.bodies[bi];
         const Shape &s = c.shapes[b.shape];
@@ -867,18 +950,29 @@ void build_ring_tables(Ctx &c) {
             off[id] = (int32_t)(b.offset + (int64_t)i * s.NF);
             nf[id] = s.NF;
             body[id] = (int32_t)bi;
+            // mirror-pair entries e = 0 .. N_F/2: azimuth e and N_F - e
+            eoff[id] = (int32_t)pairs.size();
+            for (int e = 0; e <= s.NF / 2; ++e) {
+                const int mir = (e == 0 || 2 * e == s.NF) ? -1 : off[id] + s.NF - e;
+                pairs.push_back(make_int2(off[id] + e, mir));
+            }
             const double sp = std::hypot(s.dr[i], s.dz[i]);
             g[id] = s.r[i];
             g[nr + id] = s.z[i];
             g[2 * nr + id] = -s.dz[i] / sp;
             g[3 * nr + id] = s.dr[i] / sp;
+            g[4 * nr + id] = s.r[i] > 0 ? -0.5 * g[2 * nr + id] / s.r[i] : 0.0;
         }
     }
     ri.insert(ri.end(), off.begin(), off.end());
     ri.insert(ri.end(), nf.begin(), nf.end());
     ri.insert(ri.end(), body.begin(), body.end());
+    eoff[nr] = (int32_t)pairs.size();
+    ri.insert(ri.end(), eoff.begin(), eoff.end());
     c.ring_i = (int32_t *)c.dalloc(ri.size() * sizeof(int32_t));
     AXS_HIP(hipMemcpy(c.ring_i, ri.data(), ri.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    c.ring_pair = (int2 *)c.dalloc(pairs.size() * sizeof(int2));
+    AXS_HIP(hipMemcpy(c.ring_pair, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice));
     auto up = [&](const std::vector<double> &h, double *&d64, float *&d32) {
         std::vector<float> f(h.begin(), h.end());
         d64 = (double *)c.dalloc(h.size() * sizeof(double));
@@ -944,11 +1038,12 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
                       typename C2T<R>::T *part) {
     // at kappa = 0 the ring order runs unscaled (k/2pi replaced by 1, no phase)
     const R kappa = (R)c.kappa, k2pi = LAP ? R(1) : (R)(c.kappa / (2.0 * M_PI)), eta = (R)c.eta;
-    const RingTabs rt{c.ring_i, c.ring_i + c.nrings, c.ring_i + 2 * c.nrings};
+    const RingTabs rt{c.ring_i, c.ring_i + c.nrings, c.ring_i + 2 * c.nrings, c.ring_i + 3 * c.nrings,
+                      c.ring_pair};
     // one launch covers every body and every full group of NR right-hand sides
     // (grid.y = groups); a remainder group gets one more launch.  Wide groups
     // (16, 32) share one kernel evaluation among more complex MACs; they exist
-    // for the FP32 ring order with 128-thread blocks (LDS tile <= 35 KB).
+    // for the FP32 ring order with 128-thread blocks (LDS tile <= 68 KB).
     const bool wide = sizeof(R) == 4 && variant == 2 && BS == 128 && TPT <= 2;
     int c0 = 0;
     while (c0 < nrhs) {
