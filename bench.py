@@ -11,7 +11,10 @@ matrices (FP64, on the GPU) is timed separately and is not part of a step.
 
 Prints one JSON line.  The roofline object is for the dominant kernel, the
 FP32 inter-body sum: 39 flop per (target, source) pair on different bodies,
-timed with HIP events on the library's stream.
+timed with HIP events on the library's stream.  Beside the step, the line
+reports the same problem solved through the ring skeletonization of Sec. 5
+(`skeleton`: ID time, kept unknowns, compressed mixed solve, residual of the
+lifted density in the full system).
 """
 from __future__ import annotations
 
@@ -120,7 +123,8 @@ def main():
                          "ranks, compressed mixed and FP64 solves, full-system residual of the lifted density")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="launch only what the hardware-counter passes measure: a 512 MiB device copy "
-                         "(calibration), then two FP32 and one FP64 inter-body sums on the 27 spheres")
+                         "(calibration), then two FP32 and one FP64 inter-body sums on the 27 spheres, "
+                         "and two FP32 64-rhs sums (MFMA order) on the 8 mixed bodies")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -253,6 +257,28 @@ def main():
     log(f"interbody fp32 {t_ib*1e3:.2f} ms ({pairs / t_ib / 1e9:.1f} Gpairs/s, {achieved:.2f} TFLOP/s); "
         f"fp64 {t_ib64*1e3:.2f} ms; stages fp32 {stage32} fp64 {stage64}")
 
+    # the same problem through the ring skeletonization of Sec. 5 (reported
+    # beside the step; the step itself is the uncompressed solve)
+    skel = None
+    if not args.small:
+        torch.cuda.synchronize()
+        t0 = time.time()
+        ns = ctx.skeletonize(1e-8, 2.0)
+        torch.cuda.synchronize()
+        t_id = time.time() - t0
+        ctx.solve_skeleton(v, mode=SOLVE_MIXED, tol=args.tol)     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.time()
+        sk, info_sk = ctx.solve_skeleton(v, mode=SOLVE_MIXED, tol=args.tol)
+        torch.cuda.synchronize()
+        t_sk = time.time() - t0
+        b_ = ctx.apply_precond(v, FP64)
+        res_sk = float(torch.linalg.norm(ctx.apply_matvec(sk, FP64) + b_) / torch.linalg.norm(b_))
+        skel = {"eps": 1e-8, "rings": list(ctx.skeleton_rank(0)), "unknowns": ns, "skeletonize_s": t_id,
+                "mixed_s": t_sk, "outer": info_sk[0]["iterations"], "inner": info_sk[0]["inner_iterations"],
+                "full_rel_residual": res_sk}
+        log(f"skeleton: {skel}")
+
     cpu = None
     if not args.no_cpu_baseline:
         iters = fp64["iterations"] if fp64 else 30
@@ -292,6 +318,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": f"{kname} (FP32 inter-body sum), launch shape {list(shape32)}",
                      "flop_per_launch": flops, "launch_ms": t_ib * 1e3},
+        "skeleton": skel,
         "cpu_baseline": cpu,
         "autotuned": tuned,
     }
@@ -375,6 +402,16 @@ def pmc_probe():
         ctx.apply_interbody(v, prec)
         torch.cuda.synchronize()
     log("inter-body sums done")
+    ctx.close()
+    # the MFMA order with 16-rhs groups: 8 mixed bodies, 64 plane waves
+    wl = configs.mixed_bodies()
+    ctx = Context(0).add_workload(wl)
+    ctx.precompute_scattering()
+    v = ctx.incident_plane_waves(wl.dirs)
+    for prec in (FP32, FP32):
+        ctx.apply_interbody(v, prec)
+        torch.cuda.synchronize()
+    log(f"64-rhs inter-body sums done ({ctx.interbody_launch_shape(FP32, len(wl.dirs))})")
     ctx.close()
 
 

@@ -138,6 +138,34 @@ def test_interbody_launch_shapes_agree(small):
         ctx.set_interbody_config(prec, 0, 0, 0, 0)
 
 
+@pytest.mark.parametrize("M, fits128", [(127, True), (128, False)])
+def test_ring_order_at_the_tile_limit(M, fits128):
+    """A ring of N_F = 2M + 1 azimuths is staged as N_F/2 + 1 mirror-pair entries
+    (azimuth 0 alone, then l with N_F - l); 128-thread blocks hold rings of up to
+    128 entries (M = 127) and refuse wider ones, 256-thread blocks take both."""
+    from oracle.multibody import System
+    from paper_1406_0236_amd import FP32, FP64, AxsError, Context
+    from workloads import configs
+    wl = configs.two_spheres(n_panels=2, p=4, M=M)
+    S = System.from_workload(wl)
+    print(f"[gpu] ring tile limit M={M} N={S.N}", flush=True)
+    ctx = Context(0).add_workload(wl)
+    ctx.precompute_scattering()
+    x = _dev(_rand(S.N, 2, 47))
+    ref = S.apply_B(x.cpu().numpy().T).T
+    for prec, tol in ((FP64, 1e-12), (FP32, 3e-5)):
+        for block in (128, 256):
+            ctx.set_interbody_config(prec, 2, 1, block, 0)
+            if block == 128 and not fits128:
+                with pytest.raises(AxsError, match="EINVAL"):
+                    ctx.apply_interbody(x, prec)
+                continue
+            e = rel(ctx.apply_interbody(x, prec).cpu().numpy(), ref)
+            print(f"prec {prec} block {block}: rel err {e:.2e}")
+            assert e < tol, (prec, block, e)
+    ctx.close()
+
+
 def test_fp64_interbody_is_accurate_to_rounding(small):
     """The FP64 sum (own octant-reduced sin/cos, Newton-refined 1/sqrt) agrees with
     the reference to a few ulps of the largest term, for both source orders."""
