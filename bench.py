@@ -38,7 +38,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
 # source they were taken on.
 TRAFFIC_BYTES = 115.14e6
-TRAFFIC_SOURCE_SHA = "7f10ff8dc204ae61"
+TRAFFIC_SOURCE_SHA = "6b35f10030a29fa2"
 
 
 def log(msg):

@@ -20,9 +20,9 @@ from ._lib import FP32, FP64
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 CANDIDATES = [
-    # (variant, targets per thread, block); FP32 rings with 128 threads and
-    # <= 2 targets per thread also get 16- and 32-wide right-hand-side groups;
-    # the MFMA order takes 1, 2 or 4 groups of 16 targets per wavefront
+    # (variant, targets per thread, block); the point and ring orders take the
+    # right-hand sides in groups of up to 8, the MFMA order in groups of 16 and
+    # 1, 2 or 4 groups of 16 targets per wavefront
     (3, 2, 256), (3, 1, 256), (3, 4, 256),
     (2, 4, 256), (2, 2, 256), (2, 8, 256), (2, 4, 128), (2, 2, 128), (2, 1, 128), (2, 1, 256),
     (1, 4, 256), (1, 2, 256), (1, 8, 256),

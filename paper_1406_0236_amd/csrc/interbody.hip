@@ -96,6 +96,20 @@ __device__ __forceinline__ void sincos_rev_tab(double t, const double2 *tab, dou
     s = fma(e.y, cx, e.x * sx);
     c = fma(e.x, cx, -e.y * sx);
 }
+// The same for phases t in [0, 2^20) revolutions (the whole-revolution offset
+// already taken off): j = rint(256 t) indexes the table modulo 256 and
+// r = t - j/256 is exact, so the fraction t - rint(t) is not needed.
+__device__ __forceinline__ void sincos_rev_tab_near(double t, const double2 *tab, double &s, double &c) {
+    const double j = rint(256.0 * t);
+    const double r = fma(-1.0 / 256.0, j, t);     // exact, |r| <= 1/512
+    const double x = r * 6.283185307179586476925287;
+    const double x2 = x * x;
+    const double sx = fma(x * x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
+    const double cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    const double2 e = tab[((int)j) & 255];        // (cos, sin)(2 pi j / 256)
+    s = fma(e.y, cx, e.x * sx);
+    c = fma(e.x, cx, -e.y * sx);
+}
 // precision-generic entry points used by the kernels (the table is unused in FP32)
 __device__ __forceinline__ void sincos_any(float ph, const double2 *, float &s, float &c) { sincos_rev(ph, s, c); }
 __device__ __forceinline__ void sincos_any(double t, const double2 *tab, double &s, double &c) {
@@ -105,7 +119,7 @@ __device__ __forceinline__ void sincos_near_any(float ph, const double2 *, float
     sincos_rev_near(ph, s, c);
 }
 __device__ __forceinline__ void sincos_near_any(double t, const double2 *tab, double &s, double &c) {
-    sincos_rev_tab(t, tab, s, c);
+    sincos_rev_tab_near(t, tab, s, c);
 }
 // copy the FP64 table to LDS (the kernels' first barrier publishes it)
 template <typename R, int BS>
@@ -128,13 +142,13 @@ __device__ __forceinline__ double wave_floor_min(double v) {
     return floor(fmax(v, 0.0));
 }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-// 1/sqrt(x) for finite x > 0: hardware estimate refined by two Newton steps
+// 1/sqrt(x) for finite x > 0: hardware estimate refined by two Newton steps,
+// y <- y + y (1/2 - (x/2) y^2)
 __device__ __forceinline__ double rsq(double x) {
+    const double h = 0.5 * x;
     double y = __builtin_amdgcn_rsq(x);
-    double e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-x * y, y, 1.0);
-    return fma(0.5 * y, e, y);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return fma(y, fma(-h * y, y, 0.5), y);
 }
 
 // LDS stride (in elements) of one staged source: x y z nx ny nz + NR complex q,
@@ -288,7 +302,8 @@ __device__ __forceinline__ void ring_term(R r2, R nd, R n0, R eta, R etap, const
                                           const R *qr, const R *qi, R *ar, R *ai) {
     const R u = rsq(r2);   // 1 / R'
     if constexpr (LAP) {
-        // kappa = 0 (scale factor 1): 4 pi G = (n.d / R^2 + eta) / R, real
+        // kappa = 0 (scale factor 1): 4 pi G = (n.d / R^2 + eta) / R, real; the
+        // caller passes nd = beta and eta + kap, since n.d / R^2 = kap + beta / R^2
         const R G = u * fma(nd, u * u, eta);
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
@@ -444,6 +459,7 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                 // rho = -n_r / (2 r), 0 for a ring of radius 0 (zero area weight,
                 // hence zero density).
                 const R kap = rho_[ring] * k2pi;
+                const R etak = eta + kap;   // zero frequency: n.d/R^2 + eta = beta/R^2 + (kap + eta)
                 R al[TPT], Ax[TPT], Ay[TPT], beta[TPT];
 #pragma unroll
                 for (int k = 0; k < TPT; ++k) {
@@ -490,8 +506,15 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                     for (int k = 0; k < TPT; ++k) {
                         const R br = fma(Ax[k], cl, al[k]);
                         const R ra = fma(Ay[k], sl, br), rb = fma(-Ay[k], sl, br);
-                        ring_term<R, NR, LAP>(ra, fma(kap, ra, beta[k]), n0, eta, etap, s_tab, qr, qi, ar[k], ai[k]);
-                        ring_term<R, NR, LAP>(rb, fma(kap, rb, beta[k]), n0, eta, etap, s_tab, mr, mi, ar[k], ai[k]);
+                        if constexpr (LAP) {
+                            ring_term<R, NR, true>(ra, beta[k], n0, etak, etap, s_tab, qr, qi, ar[k], ai[k]);
+                            ring_term<R, NR, true>(rb, beta[k], n0, etak, etap, s_tab, mr, mi, ar[k], ai[k]);
+                        } else {
+                            ring_term<R, NR, false>(ra, fma(kap, ra, beta[k]), n0, eta, etap, s_tab, qr, qi, ar[k],
+                                                    ai[k]);
+                            ring_term<R, NR, false>(rb, fma(kap, rb, beta[k]), n0, eta, etap, s_tab, mr, mi, ar[k],
+                                                    ai[k]);
+                        }
                     }
                 }
             }
@@ -1041,15 +1064,14 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
     const RingTabs rt{c.ring_i, c.ring_i + c.nrings, c.ring_i + 2 * c.nrings, c.ring_i + 3 * c.nrings,
                       c.ring_pair};
     // one launch covers every body and every full group of NR right-hand sides
-    // (grid.y = groups); a remainder group gets one more launch.  Wide groups
-    // (16, 32) share one kernel evaluation among more complex MACs; they exist
-    // for the FP32 ring order with 128-thread blocks (LDS tile <= 68 KB).
-    const bool wide = sizeof(R) == 4 && variant == 2 && BS == 128 && TPT <= 2;
+    // (grid.y = groups); a remainder group gets one more launch.  Groups stop
+    // at 8: with mirror pairs a 16- or 32-wide group doubles the LDS tile and
+    // the registers of the densities, and ran slower than groups of 8 (64 rhs
+    // beyond 16 take the MFMA order anyway).
     int c0 = 0;
     while (c0 < nrhs) {
         const int left = nrhs - c0;
-        const int nr = (wide && left >= 32) ? 32 : (wide && left >= 16) ? 16 : left >= 8 ? 8 : left >= 4 ? 4
-                                                                                      : left >= 2 ? 2 : 1;
+        const int nr = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
         const int groups = left / nr;
 #define AXS_IB_NR(NR_)                                                                                     \
     if (nr == NR_) {                                                                                       \
@@ -1061,18 +1083,6 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
             hipLaunchKernelGGL((interbody_kernel<R, TPT, NR_, BS, LAP>), dim3(nwork, groups), dim3(BS), 0, \
                                c.stream, work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, c.sctab, part);    \
     }
-        if constexpr (sizeof(R) == 4 && BS == 128 && TPT <= 2) {
-            if (nr == 32)
-                hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, 32, BS, LAP>), dim3(nwork, groups), dim3(BS), 0,
-                                   c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta,
-                                   c.sctab, part);
-            if (nr == 16)
-                hipLaunchKernelGGL((interbody_ring_kernel<R, TPT, 16, BS, LAP>), dim3(nwork, groups), dim3(BS), 0,
-                                   c.stream, work, geo, cs, q, rt, rg, c.nrings, frame, c.N, nrhs, c0, k2pi, eta,
-                                   c.sctab, part);
-        } else {
-            if (nr > 8) throw Error{AXS_EINVAL, "wide rhs groups need FP32 rings, 128 threads, <= 2 targets"};
-        }
         AXS_IB_NR(8)
         AXS_IB_NR(4)
         AXS_IB_NR(2)

@@ -414,8 +414,8 @@ def test_autotuner_choice_is_valid(small, tmp_path):
     ctx.set_interbody_config(FP32, 0, 0, 0, 0)
 
 
-def test_wide_rhs_groups_fp32_rings(small):
-    """37 right-hand sides through 32-, 4- and 1-wide groups (FP32 rings, 128 threads)."""
+def test_rhs_groups_fp32_rings(small):
+    """37 right-hand sides through 8-, 4- and 1-wide groups (FP32 rings, 128 threads)."""
     from paper_1406_0236_amd import FP32
     wl, S, ctx = small
     sig = _rand(S.N, 37, 81)
