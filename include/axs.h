@@ -198,9 +198,16 @@ axs_status axs_last_timing(axs_ctx *ctx, double ms[5]);
  *           3 = MFMA order, kappa > 0: R^2 and n.d of 16 x 16 (source,
  *           target) blocks from matrix-core products of 4-vectors in the source
  *           body's frame; with 16 right-hand sides per group the complex
- *           multiply-accumulate is a matrix-core product too
- *  targets_per_thread: 1, 2, 4 or 8 (variant 3: 1, 2 or 4 groups of 16 targets
- *           per wavefront);  block: 128 or 256 threads (variant 3: 256);
+ *           multiply-accumulate is a matrix-core product too,
+ *           4 = the MFMA order with the complex multiply-accumulate of each
+ *           group of 16 right-hand sides on the FP16 matrix cores: kernel
+ *           values and densities split into high and low FP16 parts (three
+ *           of the four part products kept), scaled by powers of two into
+ *           FP16 range, results in FP32 (FP32 only; needs kappa > 0 and
+ *           bodies whose bounding balls are disjoint, from which the scale of
+ *           the kernel values is bounded)
+ *  targets_per_thread: 1, 2, 4 or 8 (variants 3 and 4: 1, 2 or 4 groups of 16
+ *           targets per wavefront);  block: 128 or 256 threads (variants 3 and 4: 256);
  *  splits: number of source chunks per target tile (partial sums reduced in order).
  * Every shape computes the same sum; used by the launch-shape autotuner.
  * Shapes that do not fit the context are rejected (AXS_EINVAL) at the next
@@ -210,9 +217,11 @@ axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant,
 
 /* The launch shape an inter-body application in `precision` on nrhs right-hand
  * sides will use, defaults resolved: out[0..3] = variant, targets per thread
- * (variant 3: groups of 16 targets per wavefront), block, splits.  out: host
- * int[4].  The FP32 default is the ring order below 16 right-hand sides and the
- * MFMA order from 16 on.  AXS_ESTATE before axs_precompute_scattering;
+ * (variants 3 and 4: groups of 16 targets per wavefront), block, splits.  out:
+ * host int[4].  The FP32 default is the ring order below 16 right-hand sides and
+ * from 16 on the MFMA order with the FP16 multiply-accumulate (the FP32 MFMA
+ * order where bounding balls overlap); the FP64 default is the ring order below
+ * 16 and the MFMA order from 16 on.  AXS_ESTATE before axs_precompute_scattering;
  * AXS_EINVAL if the configured shape does not fit the context. */
 axs_status axs_interbody_launch_shape(axs_ctx *ctx, int precision, int nrhs, int *out);
 

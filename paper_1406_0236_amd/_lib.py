@@ -319,7 +319,8 @@ class Context:
 
     def set_interbody_config(self, precision, variant=0, targets_per_thread=0, block=0, splits=0):
         """Launch shape of the inter-body sum (0 = default): variant 1 = points, 2 = rings,
-        3 = MFMA order (targets_per_thread = groups of 16 targets per wavefront)."""
+        3 = MFMA order, 4 = MFMA order with the FP16 multiply-accumulate (FP32 only; for both,
+        targets_per_thread = groups of 16 targets per wavefront)."""
         self._check(self.lib.axs_set_interbody_config(self.h, int(precision), int(variant), int(targets_per_thread),
                                                       int(block), int(splits)))
 

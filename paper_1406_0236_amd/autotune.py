@@ -15,14 +15,17 @@ import json
 import math
 import os
 
-from ._lib import FP32, FP64
+from ._lib import FP32, FP64, AxsError
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 CANDIDATES = [
     # (variant, targets per thread, block); the point and ring orders take the
-    # right-hand sides in groups of up to 8, the MFMA order in groups of 16 and
-    # 1, 2 or 4 groups of 16 targets per wavefront
+    # right-hand sides in groups of up to 8, the MFMA orders in groups of 16 and
+    # 1, 2 or 4 groups of 16 targets per wavefront (variant 4, the FP16
+    # multiply-accumulate, is FP32 only and needs bodies whose bounding balls
+    # do not overlap)
+    (4, 2, 256), (4, 1, 256), (4, 4, 256),
     (3, 2, 256), (3, 1, 256), (3, 4, 256),
     (2, 4, 256), (2, 2, 256), (2, 8, 256), (2, 4, 128), (2, 2, 128), (2, 1, 128), (2, 1, 256),
     (1, 4, 256), (1, 2, 256), (1, 8, 256),
@@ -77,12 +80,18 @@ def tune(ctx, precision, nrhs, max_nf, x=None, reps=2, cache_path=DEFAULT_CACHE,
         for variant, tpt, block in CANDIDATES:
             if variant == 2 and max_nf > block:
                 continue
-            if variant == 3 and not (ctx.kappa or 0) > 0:
+            if variant >= 3 and not (ctx.kappa or 0) > 0:
+                continue
+            if variant == 4 and (precision != FP32 or nrhs < 16):
                 continue
             for splits in SPLITS:
                 cfg = (variant, tpt, block, splits)
                 ctx.set_interbody_config(precision, *cfg)
-                ms = _time_candidate(ctx, x, precision, reps)
+                try:
+                    ms = _time_candidate(ctx, x, precision, reps)
+                except AxsError:
+                    # a shape this context cannot run (the library says why)
+                    break
                 timings[",".join(map(str, cfg))] = ms
                 spent += ms * (reps + 1)
                 if verbose:

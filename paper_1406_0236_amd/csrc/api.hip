@@ -601,8 +601,8 @@ axs_status axs_last_timing(axs_ctx *ctx, double ms[5]) {
 axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant, int tpt, int block, int splits) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         AXS_REQUIRE(precision == AXS_FP64 || precision == AXS_FP32, AXS_EINVAL, "bad precision");
-        AXS_REQUIRE(variant >= 0 && variant <= 3, AXS_EINVAL,
-                    "variant must be 0, 1 (points), 2 (rings) or 3 (MFMA)");
+        AXS_REQUIRE(variant >= 0 && variant <= 4, AXS_EINVAL,
+                    "variant must be 0, 1 (points), 2 (rings), 3 (MFMA) or 4 (MFMA, FP16 multiply-accumulate)");
         AXS_REQUIRE(tpt == 0 || tpt == 1 || tpt == 2 || tpt == 4 || tpt == 8, AXS_EINVAL,
                     "targets per thread must be 0, 1, 2, 4 or 8");
         AXS_REQUIRE(block == 0 || block == 128 || block == 256, AXS_EINVAL, "block must be 0, 128 or 256");

@@ -142,14 +142,15 @@ struct Ctx {
     int ngemm = 0, gemm_max_cols = 0, max_NG = 0;
 
     // cached inter-body work tables, per precision (0 = fp64, 1 = fp32)
-    // [precision][0: point / ring orders, 1: MFMA order], so that alternating
-    // single and batched calls do not rebuild them
-    IBWork *ib_work[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-    int ib_nwork[2][2] = {{0, 0}, {0, 0}};
-    int ib_key[2][2][4] = {};
+    // [precision][0: point / ring orders, 1: MFMA order (node units),
+    // 2: MFMA order with the FP16 multiply-accumulate (32-node block units)],
+    // so that alternating single and batched calls do not rebuild them
+    IBWork *ib_work[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int ib_nwork[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    int ib_key[2][3][4] = {};
 
     // launch configuration of the inter-body sum (0 = library default)
-    int ib_variant[2] = {0, 0};   // 1 = point sources, 2 = azimuthal rings, 3 = MFMA (FP32)
+    int ib_variant[2] = {0, 0};   // 1 = point sources, 2 = azimuthal rings, 3 = MFMA, 4 = MFMA + FP16 MAC (FP32)
     int ib_tpt[2] = {0, 0};       // targets per thread [fp64, fp32]
     int ib_block[2] = {0, 0};
     int ib_splits[2] = {0, 0};
@@ -171,6 +172,14 @@ struct Ctx {
     float *mf_src = nullptr;
     double *mf_src64 = nullptr;          // the same in FP64
     int64_t *body_off = nullptr;         // [B + 1]: first node of each body, then N
+    // 32-node source blocks of the FP16 multiply-accumulate: first block of each
+    // body (the last block of a body padded), and the power of two that scales
+    // the kernel values into FP16 range (mf16_gexp; mf16_ok is false where no
+    // bound applies, i.e. where bounding balls of two bodies overlap)
+    int32_t *blk_off = nullptr;          // [B + 1]
+    int64_t nblk = 0;
+    int mf16_gexp = 0;
+    bool mf16_ok = false;
     double2 *sctab = nullptr;            // [256]: (cos, sin)(2 pi k / 256) for the FP64 sin/cos
     // every body's diameter is under 127 wavelengths, so the phase less the
     // per-(wavefront, source body) whole revolutions floor(min (|p| - r_b) k/2pi)
@@ -188,7 +197,7 @@ struct Ctx {
     // device allocations owned by the context
     std::vector<void *> owned;
     // named scratch buffers (grow-only)
-    Buffer ws[16];
+    Buffer ws[18];
 
     void *dalloc(size_t bytes);
     void dfree(void *p);
@@ -213,6 +222,8 @@ enum ScratchSlot {
     WS_TMP3 = 13,
     WS_KRYLOV2 = 14,
     WS_EVAL = 15,
+    WS_Q16 = 16,     // FP16 density planes of the FP16 multiply-accumulate
+    WS_QMAX = 17,    // per-rhs max |q| (float bits)
 };
 
 struct Skeleton {

@@ -803,6 +803,261 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// MFMA order with the complex multiply-accumulate on the FP16 matrix cores
+// (FP32 results, 16 right-hand sides per group).  The geometry and the kernel
+// values are those of the MFMA order above (FP32); each kernel value g and
+// each density q is split into two FP16 numbers, g ~ g_hi + g_lo with g_hi =
+// g rounded toward zero and g_lo the rounded remainder, and
+//   g q ~ g_hi q_hi + g_hi q_lo + g_lo q_hi
+// (the dropped g_lo q_lo and the rounding of the low parts are ~2^-20 of
+// |g q|, below the FP32 rounding of the phase).  Four real products make the
+// complex product (Re = Gr qr + Gi (-qi), Im = Gr qi + Gi qr), 12 MFMAs
+// v_mfma_f32_16x16x32_f16 per 32 sources x 16 targets x 16 rhs, 16 cycles
+// each, against 12 FP32 16x16x4 MFMAs of 32 cycles per 16 sources in the
+// FP32 version.  FP16 has 5 exponent bits, so both factors are scaled by
+// powers of two: G by S_G, chosen on the host from the bound
+// |G| <= 1/d^2 + (|eta| + kappa)/d over pairs at least d apart (d = the
+// smallest gap between the bodies' bounding balls), so that |G S_G| <= 8192;
+// each rhs by S_q = 2^(13 - e) with 2^e <= max |q| (max over all nodes), so
+// that |q S_q| < 16384.  The results are scaled back in FP32.
+// Sources come in blocks of 32 nodes of one body (the last block of a body is
+// padded with zero densities); lane (kq, col) computes the kernel values of
+// target col for sources 4kq+v (v = 0..3) of each 16-source half of a block,
+// which are exactly the eight k = 8kq + t entries of its A operand (t = v and
+// 4 + v), so the MFMA operands need no exchange between lanes.  The densities
+// are split once per application into six FP16 planes (q_r, q_i, -q_i, high
+// and low) already in the B-operand order: [group][block][plane][rhs][k].
+// ---------------------------------------------------------------------------
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+constexpr int MF16_CB = 4;           // 32-source blocks per LDS chunk
+constexpr int MF16_BLK = 6 * 16 * 4; // h8 per block: 6 planes x 16 rhs x 4 k-slices
+
+__device__ __forceinline__ f32x4 mfma_16x16x32h(h8 a, h8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+// high and low FP16 parts of eight values
+__device__ __forceinline__ void split8(const float *g, h8 &hi, h8 &lo) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const h2 h = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(g[2 * p], g[2 * p + 1]));
+        const h2 l = __builtin_bit_cast(
+            h2, __builtin_amdgcn_cvt_pkrtz(g[2 * p] - (float)h.x, g[2 * p + 1] - (float)h.y));
+        hi[2 * p] = h.x;
+        hi[2 * p + 1] = h.y;
+        lo[2 * p] = l.x;
+        lo[2 * p + 1] = l.y;
+    }
+}
+// 2^(13 - e) for the largest |q| of a rhs (bits of a non-negative float), 1 for 0
+__device__ __forceinline__ int qscale_exp(unsigned bits) {
+    if (bits == 0u) return 0;
+    const int e = (int)(bits >> 23) - 127;       // floor(log2 max), normal numbers
+    return 13 - (e < -100 ? -100 : e);
+}
+
+// per-rhs max of max(|re|, |im|) of the staged densities, as float bits
+__global__ __launch_bounds__(256) void qmax_kernel(const float2 *__restrict__ q, int64_t N, unsigned *qmax) {
+    const int c = blockIdx.y;
+    float m = 0.f;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (int64_t)gridDim.x * 256) {
+        const float2 v = q[(int64_t)c * N + j];
+        m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(qmax + c, __float_as_uint(m));
+}
+__global__ void zero_u32_kernel(unsigned *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// six FP16 planes per 32-source block and rhs group (B-operand order)
+__global__ __launch_bounds__(256) void q16_kernel(const float2 *__restrict__ q, const unsigned *__restrict__ qmax,
+                                                  const int64_t *__restrict__ boff, const int32_t *__restrict__ bblk,
+                                                  int nbodies, int64_t N, int64_t nblk, int groups,
+                                                  _Float16 *__restrict__ q16) {
+    const int64_t item = (int64_t)blockIdx.x * 256 + threadIdx.x;   // ((grp * nblk + B) * 16 + c) * 32 + k
+    if (item >= (int64_t)groups * nblk * 512) return;
+    const int k = (int)(item & 31), c = (int)((item >> 5) & 15);
+    const int64_t gb = item >> 9, B = gb % nblk;
+    const int grp = (int)(gb / nblk);
+    int lo = 0, hi = nbodies - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bblk[mid] <= B) lo = mid;
+        else hi = mid - 1;
+    }
+    const int b = lo;
+    const int t = k & 7, kq = k >> 3;
+    const int r = (t < 4 ? 0 : 16) + 4 * kq + (t & 3);            // source of A-operand entry k
+    const int64_t node = boff[b] + 32 * (B - bblk[b]) + r;
+    const int rhs = grp * 16 + c;
+    float2 v = make_float2(0.f, 0.f);
+    if (node < boff[b + 1]) {
+        v = q[(int64_t)rhs * N + node];
+        const float s = ldexpf(1.f, qscale_exp(qmax[rhs]));
+        v.x *= s;
+        v.y *= s;
+    }
+    const h2 h = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(v.x, v.y));
+    const h2 l = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(v.x - (float)h.x, v.y - (float)h.y));
+    _Float16 *o = q16 + gb * (6 * 512) + c * 32 + k;
+    o[0 * 512] = h.x;    // q_r high
+    o[1 * 512] = l.x;    // q_r low
+    o[2 * 512] = h.y;    // q_i high
+    o[3 * 512] = l.y;    // q_i low
+    o[4 * 512] = -h.y;   // -q_i high
+    o[5 * 512] = -l.y;   // -q_i low
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void interbody_mfma16_kernel(
+    const IBWork *__restrict__ work, const float *__restrict__ geo, const f32x4 *__restrict__ sop,
+    const h8 *__restrict__ q16, const int64_t *__restrict__ boff, const int32_t *__restrict__ bblk, int nbodies,
+    const float *__restrict__ frame, int64_t N, int nrhs, int64_t nblk, float s2, float etap_s, float gscale,
+    int gexp, const unsigned *__restrict__ qmax, float2 *__restrict__ part) {
+    __shared__ f32x4 s_sr[MF16_CB * 32], s_sn[MF16_CB * 32];
+    __shared__ h8 s_q[MF16_CB * MF16_BLK];
+    const IBWork w = work[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int grp = blockIdx.y, cb = grp * 16;
+    const float *gx = geo, *gy = geo + N, *gz = geo + 2 * N;
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+
+    float tx[G], ty[G], tz[G], bT[G], n0 = 0.f;
+    f32x4 cR[G], sumR[G], sumI[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int t = (wv * G + g) * 16 + col;
+        const int64_t gi = w.t0 + (t < w.tn ? t : 0);
+        tx[g] = gx[gi];
+        ty[g] = gy[gi];
+        tz[g] = gz[gi];
+        bT[g] = 0.f;
+        cR[g] = zero4;
+        sumR[g] = sumI[g] = zero4;
+    }
+    int prev = -1;
+
+#pragma unroll 1
+    for (int rng = 0; rng < 2; ++rng) {
+        const int64_t lo = rng == 0 ? w.s0 : w.s2;
+        const int64_t hi = rng == 0 ? w.s1 : w.s3;
+        int64_t B = lo;
+#pragma unroll 1
+        while (B < hi) {
+            int b = 0;
+            {
+                int l2 = 0, h2_ = nbodies - 1;
+                while (l2 < h2_) {
+                    const int mid = (l2 + h2_ + 1) >> 1;
+                    if (bblk[mid] <= B) l2 = mid;
+                    else h2_ = mid - 1;
+                }
+                b = l2;
+            }
+            const int64_t e = min(hi, min((int64_t)bblk[b + 1], B + (int64_t)MF16_CB));
+            const int nb = (int)(e - B);
+            if (b != prev) {
+                const float *f = frame + FRAME * b;
+                const float k2pi = sqrtf(s2);
+                float m = 1e30f;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const float dx = tx[g] - f[0], dy = ty[g] - f[1], dz = tz[g] - f[2];
+                    const float px = fmaf(f[3], dx, fmaf(f[6], dy, f[9] * dz));
+                    const float py = fmaf(f[4], dx, fmaf(f[7], dy, f[10] * dz));
+                    const float pz = fmaf(f[5], dx, fmaf(f[8], dy, f[11] * dz));
+                    bT[g] = kq == 0 ? px : kq == 1 ? py : kq == 2 ? pz : 1.f;
+                    const float p2 = fmaf(px, px, fmaf(py, py, pz * pz));
+                    const float c2 = s2 * p2;
+                    cR[g] = (f32x4){c2, c2, c2, c2};
+                    m = fminf(m, (sqrtf(p2) - f[12]) * k2pi);
+                }
+                n0 = wave_floor_min(m);
+                prev = b;
+            }
+            __syncthreads();
+            const int64_t first = boff[b] + 32 * (B - bblk[b]);
+            for (int i = tid; i < nb * 32; i += 256) {
+                const int64_t node = first + i;
+                const bool ok = node < boff[b + 1];
+                s_sr[i] = ok ? sop[node] : zero4;
+                s_sn[i] = ok ? sop[N + node] * gscale : zero4;   // nd' scaled by S_G
+            }
+            const h8 *src = q16 + ((int64_t)grp * nblk + B) * MF16_BLK;
+            for (int i = tid; i < nb * MF16_BLK; i += 256) s_q[i] = src[i];
+            __syncthreads();
+            // the matrix cores accumulate one chunk (at most 128 sources) from
+            // zero; the chunk sums are added on the VALU, rounded to nearest
+            f32x4 accR[G], accI[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) accR[g] = accI[g] = zero4;
+#pragma unroll 1
+            for (int jb = 0; jb < nb; ++jb) {
+                const h8 *qb = s_q + jb * MF16_BLK;
+                const h8 qrh = qb[(0 * 16 + col) * 4 + kq], qrl = qb[(1 * 16 + col) * 4 + kq];
+                const h8 qih = qb[(2 * 16 + col) * 4 + kq], qil = qb[(3 * 16 + col) * 4 + kq];
+                const h8 nqh = qb[(4 * 16 + col) * 4 + kq], nql = qb[(5 * 16 + col) * 4 + kq];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    float gr[8], gi[8];
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+                        const int j = jb * 32 + half * 16 + col;
+                        const float a1 = ((const float *)s_sr)[j * 4 + kq];
+                        const float a2 = ((const float *)s_sn)[j * 4 + kq];
+                        const f32x4 d1 = mfma_16x16x4(a1, bT[g], cR[g]);
+                        const f32x4 d2 = mfma_16x16x4(a2, bT[g], zero4);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            kernel_value<float>(d1[v], d2[v], n0, etap_s, nullptr, gr[half * 4 + v], gi[half * 4 + v]);
+                    }
+                    h8 grh, grl, gih, gil;
+                    split8(gr, grh, grl);
+                    split8(gi, gih, gil);
+                    accR[g] = mfma_16x16x32h(grh, qrh, accR[g]);
+                    accI[g] = mfma_16x16x32h(grh, qih, accI[g]);
+                    accR[g] = mfma_16x16x32h(grh, qrl, accR[g]);
+                    accI[g] = mfma_16x16x32h(grh, qil, accI[g]);
+                    accR[g] = mfma_16x16x32h(grl, qrh, accR[g]);
+                    accI[g] = mfma_16x16x32h(grl, qih, accI[g]);
+                    accR[g] = mfma_16x16x32h(gih, nqh, accR[g]);
+                    accI[g] = mfma_16x16x32h(gih, qrh, accI[g]);
+                    accR[g] = mfma_16x16x32h(gih, nql, accR[g]);
+                    accI[g] = mfma_16x16x32h(gih, qrl, accI[g]);
+                    accR[g] = mfma_16x16x32h(gil, nqh, accR[g]);
+                    accI[g] = mfma_16x16x32h(gil, qrh, accI[g]);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                sumR[g] += accR[g];
+                sumI[g] += accI[g];
+            }
+            B = e;
+        }
+    }
+    // lane (kq, col) holds targets 4kq + v of each group for rhs cb + col
+    const float inv = ldexpf(1.f, -(gexp + qscale_exp(qmax[cb + col])));
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int t = (wv * G + g) * 16 + 4 * kq + v;
+            if (t < w.tn) {
+                float2 o;
+                o.x = sumR[g][v] * inv;
+                o.y = sumI[g][v] * inv;
+                part[((int64_t)w.slot * nrhs + cb + col) * N + w.t0 + t] = o;
+            }
+        }
+}
+
 // q[c][j] = w_j sigma[c][j] / (4 pi) in precision R
 template <typename R>
 __global__ void stage_density_kernel(const double2 *__restrict__ sigma, const double *__restrict__ w,
@@ -842,8 +1097,8 @@ struct IBShape {
     int variant, tpt, bs, splits;
 };
 
-// targets per work item: TPT x block, or for the MFMA order 16 x G x 4 waves
-static int ib_tile(const IBShape &s) { return s.variant == 3 ? 64 * s.tpt : s.tpt * s.bs; }
+// targets per work item: TPT x block, or for the MFMA orders 16 x G x 4 waves
+static int ib_tile(const IBShape &s) { return s.variant >= 3 ? 64 * s.tpt : s.tpt * s.bs; }
 
 static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
     const int pi = prec == AXS_FP32 ? 1 : 0;
@@ -857,12 +1112,17 @@ static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
     const bool ring_ok = c.max_nf / 2 + 1 <= s.bs && (c.kappa == 0 || c.near_phase_ok);
     const bool mf_ok = c.kappa > 0 && c.mf_src && c.near_phase_ok && s.bs == 256 &&
                        (c.ib_tpt[pi] == 0 || c.ib_tpt[pi] <= 4);
-    s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi] : (nrhs >= 16 && mf_ok) ? 3 : ring_ok ? 2 : 1;
+    const bool mf16_ok = mf_ok && prec == AXS_FP32 && c.mf16_ok;
+    s.variant = c.ib_variant[pi] > 0 ? c.ib_variant[pi]
+                : (nrhs >= 16 && mf16_ok) ? 4 : (nrhs >= 16 && mf_ok) ? 3 : ring_ok ? 2 : 1;
     const int dflt = prec == AXS_FP32 ? (s.variant == 2 ? 1 : 2) : 4;
     s.tpt = c.ib_tpt[pi] > 0 ? c.ib_tpt[pi] : dflt;
     AXS_REQUIRE(s.variant != 2 || ring_ok, AXS_EINVAL,
                 "ring variant needs N_F/2 + 1 <= threads per block and bodies under 127 wavelengths across");
-    if (s.variant == 3) {
+    if (s.variant == 4)
+        AXS_REQUIRE(prec == AXS_FP32 && c.mf16_ok, AXS_EINVAL,
+                    "FP16 multiply-accumulate: FP32 only, and bodies whose bounding balls do not overlap");
+    if (s.variant >= 3) {
         AXS_REQUIRE(c.kappa > 0 && c.mf_src && c.near_phase_ok, AXS_EINVAL,
                     "MFMA variant needs kappa > 0 and bodies under 127 wavelengths across");
         AXS_REQUIRE(s.tpt == 1 || s.tpt == 2 || s.tpt == 4, AXS_EINVAL,
@@ -895,14 +1155,19 @@ void interbody_shape(Ctx &c, int prec, int nrhs, int out[4]) {
 }
 
 // Work items: every body-aligned tile of `tile` targets against `splits`
-// chunks of the source units (nodes or rings) outside the target's body.
-static std::vector<IBWork> build_work(Ctx &c, int tile, int splits, bool rings) {
+// chunks of the source units (nodes, rings or 32-node blocks) outside the
+// target's body.
+enum class Units { nodes, rings, blocks };
+static std::vector<IBWork> build_work(Ctx &c, int tile, int splits, Units units) {
     std::vector<IBWork> out;
-    const int64_t U = rings ? c.nrings : c.N;
+    const int64_t U = units == Units::rings ? c.nrings : units == Units::blocks ? c.nblk : c.N;
+    int64_t boff = 0;
     for (size_t bi = 0; bi < c.bodies.size(); ++bi) {
         const auto &b = c.bodies[bi];
-        const int64_t uoff = rings ? c.ring_base[bi] : b.offset;
-        const int64_t un = rings ? c.shapes[b.shape].NG : b.n;
+        const int64_t nbk = ceil_div(b.n, (int64_t)32);
+        const int64_t uoff = units == Units::rings ? c.ring_base[bi] : units == Units::blocks ? boff : b.offset;
+        const int64_t un = units == Units::rings ? c.shapes[b.shape].NG : units == Units::blocks ? nbk : b.n;
+        boff += nbk;
         const int64_t others = U - un;
         const int64_t chunk = ceil_div(std::max<int64_t>(others, 1), splits);
         for (int64_t t0 = 0; t0 < b.n; t0 += tile) {
@@ -1021,6 +1286,28 @@ void build_ring_tables(Ctx &c) {
     bo.push_back(N);
     c.body_off = (int64_t *)c.dalloc(bo.size() * sizeof(int64_t));
     AXS_HIP(hipMemcpy(c.body_off, bo.data(), bo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    std::vector<int32_t> bk(1, 0);
+    for (auto &b : c.bodies) bk.push_back(bk.back() + (int32_t)ceil_div(b.n, (int64_t)32));
+    c.nblk = bk.back();
+    c.blk_off = (int32_t *)c.dalloc(bk.size() * sizeof(int32_t));
+    AXS_HIP(hipMemcpy(c.blk_off, bk.data(), bk.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    // FP16 multiply-accumulate: every inter-body pair is at least dmin apart
+    // (the smallest gap between bounding balls), so |4 pi G| <= 1/dmin^2 +
+    // (|eta| + kappa)/dmin; S_G = 2^gexp brings that bound to at most 8192
+    double dmin = 1e300;
+    for (size_t a = 0; a < c.bodies.size(); ++a)
+        for (size_t b2 = a + 1; b2 < c.bodies.size(); ++b2) {
+            const auto &A = c.bodies[a], &Bb = c.bodies[b2];
+            const double dx = A.centre[0] - Bb.centre[0], dy = A.centre[1] - Bb.centre[1],
+                         dz = A.centre[2] - Bb.centre[2];
+            dmin = std::min(dmin, std::sqrt(dx * dx + dy * dy + dz * dz) - A.bound_radius - Bb.bound_radius);
+        }
+    c.mf16_ok = false;
+    if (c.bodies.size() > 1 && dmin > 1e-3) {
+        const double gb = 1.0 / (dmin * dmin) + (std::fabs(c.eta) + c.kappa) / dmin;
+        c.mf16_gexp = (int)std::floor(std::log2(8192.0 / gb));
+        c.mf16_ok = c.mf16_gexp > -60 && c.mf16_gexp < 60;
+    }
     if (c.kappa > 0) {
         // MFMA source operands in each body's frame, scaled so that the
         // products give R'^2 and nd' of the ring order directly
@@ -1097,14 +1384,14 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
 // remainder groups of 8, 4, 2, 1 the VALU one.
 template <typename R, int G>
 static void launch_mf(Ctx &c, const IBWork *work, int nwork, const typename C2T<R>::T *q, int nrhs,
-                      typename C2T<R>::T *part) {
+                      typename C2T<R>::T *part, int c_begin = 0) {
     const R k2pi = (R)(c.kappa / (2.0 * M_PI));
     const R s2 = k2pi * k2pi, etap = (R)c.eta * k2pi;
     const R *geo = sizeof(R) == 4 ? (const R *)c.g32 : (const R *)c.g64;
     const R *frame = sizeof(R) == 4 ? (const R *)c.frame32 : (const R *)c.frame64;
     const auto *sop = (const typename MfT<R>::V *)(sizeof(R) == 4 ? (const void *)c.mf_src : (const void *)c.mf_src64);
     const int nb = (int)c.bodies.size();
-    int c0 = 0;
+    int c0 = c_begin;
     while (c0 < nrhs) {
         const int left = nrhs - c0;
         const int nr = left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
@@ -1153,15 +1440,12 @@ static void dispatch_ib(Ctx &c, const IBShape &s, const IBWork *work, int nwork,
     throw Error{AXS_EINVAL, "unsupported inter-body launch shape (targets/thread, block)"};
 }
 
-void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
-    const int pi = prec == AXS_FP32 ? 1 : 0;
-    const IBShape s = launch_shape(c, prec, nrhs);
-    const bool rings = s.variant == 2;
-    const int wi = s.variant == 3 ? 1 : 0;
+// cached work table [precision][wi] for a launch shape
+static const IBWork *get_work(Ctx &c, int pi, int wi, const IBShape &s, Units units, int &nwork) {
     int *key = c.ib_key[pi][wi];
     if (!c.ib_work[pi][wi] || key[0] != s.tpt || key[1] != s.bs || key[2] != s.splits || key[3] != s.variant) {
         // work tables are cached per launch shape; rebuilt only when it changes
-        std::vector<IBWork> work = build_work(c, ib_tile(s), s.splits, rings);
+        std::vector<IBWork> work = build_work(c, ib_tile(s), s.splits, units);
         if (c.ib_work[pi][wi]) {
             AXS_HIP(hipStreamSynchronize(c.stream));
             c.dfree(c.ib_work[pi][wi]);
@@ -1174,10 +1458,72 @@ void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
         key[2] = s.splits;
         key[3] = s.variant;
     }
-    const IBWork *dwork = c.ib_work[pi][wi];
-    const int nwork = c.ib_nwork[pi][wi];
+    nwork = c.ib_nwork[pi][wi];
+    return c.ib_work[pi][wi];
+}
+
+// MFMA order with the FP16 multiply-accumulate: full groups of 16 rhs over
+// 32-node source blocks; a remainder of fewer than 16 rhs takes the FP32 MFMA
+// order (node units).  Both write the same [splits][nrhs][N] partial sums.
+static void launch_mf16(Ctx &c, const IBShape &s, const float2 *q, int nrhs, float2 *part) {
+    const int groups = nrhs / 16;
+    if (groups > 0) {
+        int nwork = 0;
+        const IBWork *work = get_work(c, 1, 2, s, Units::blocks, nwork);
+        unsigned *qmax = (unsigned *)c.scratch(WS_QMAX, (size_t)nrhs * sizeof(unsigned));
+        hipLaunchKernelGGL(zero_u32_kernel, dim3(ceil_div(nrhs, 256)), dim3(256), 0, c.stream, qmax, nrhs);
+        const int gx = (int)std::min<int64_t>(ceil_div(c.N, (int64_t)256), 1024);
+        hipLaunchKernelGGL(qmax_kernel, dim3(gx, nrhs), dim3(256), 0, c.stream, q, c.N, qmax);
+        const int64_t items = (int64_t)groups * c.nblk * 512;
+        _Float16 *q16 = (_Float16 *)c.scratch(WS_Q16, (size_t)items * 6 * sizeof(_Float16));
+        hipLaunchKernelGGL(q16_kernel, dim3(ceil_div(items, (int64_t)256)), dim3(256), 0, c.stream, q, qmax,
+                           c.body_off, c.blk_off, (int)c.bodies.size(), c.N, c.nblk, groups, q16);
+        AXS_HIP(hipGetLastError());
+        const float k2pi = (float)(c.kappa / (2.0 * M_PI));
+        const float s2 = k2pi * k2pi;
+        const float gscale = std::ldexp(1.0f, c.mf16_gexp);
+        const float etap_s = (float)(c.eta * c.kappa / (2.0 * M_PI)) * gscale;
+        const auto *sop = (const f32x4 *)c.mf_src;
+        const auto *q16v = (const h8 *)q16;
+#define AXS_MF16(G_)                                                                                         \
+    if (s.tpt == G_)                                                                                        \
+        hipLaunchKernelGGL((interbody_mfma16_kernel<G_>), dim3(nwork, groups), dim3(256), 0, c.stream, work, \
+                           c.g32, sop, q16v, c.body_off, c.blk_off, (int)c.bodies.size(), c.frame32, c.N,    \
+                           nrhs, c.nblk, s2, etap_s, gscale, c.mf16_gexp, qmax, part);
+        AXS_MF16(1)
+        AXS_MF16(2)
+        AXS_MF16(4)
+#undef AXS_MF16
+        AXS_HIP(hipGetLastError());
+    }
+    if (16 * groups < nrhs) {
+        int nwork = 0;
+        IBShape s3 = s;
+        s3.variant = 3;
+        const IBWork *work = get_work(c, 1, 1, s3, Units::nodes, nwork);
+        if (s.tpt == 1) launch_mf<float, 1>(c, work, nwork, q, nrhs, part, 16 * groups);
+        else if (s.tpt == 2) launch_mf<float, 2>(c, work, nwork, q, nrhs, part, 16 * groups);
+        else launch_mf<float, 4>(c, work, nwork, q, nrhs, part, 16 * groups);
+    }
+}
+
+void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
+    const int pi = prec == AXS_FP32 ? 1 : 0;
+    const IBShape s = launch_shape(c, prec, nrhs);
     const int64_t total = (int64_t)nrhs * c.N;
     const int thr = 256;
+    if (s.variant == 4) {
+        float2 *q = (float2 *)c.scratch(WS_Q, total * sizeof(float2));
+        float2 *part = (float2 *)c.scratch(WS_PART, (size_t)s.splits * total * sizeof(float2));
+        hipLaunchKernelGGL(stage_density_kernel<float>, dim3(ceil_div(total, thr)), dim3(thr), 0,
+                           c.stream, (const double2 *)sigma, c.g64 + 6 * c.N, c.N, total, q);
+        AXS_HIP(hipGetLastError());
+        launch_mf16(c, s, q, nrhs, part);
+        return;
+    }
+    int nwork = 0;
+    const IBWork *dwork = get_work(c, pi, s.variant == 3 ? 1 : 0, s,
+                                   s.variant == 2 ? Units::rings : Units::nodes, nwork);
     if (prec == AXS_FP32) {
         float2 *q = (float2 *)c.scratch(WS_Q, total * sizeof(float2));
         float2 *part = (float2 *)c.scratch(WS_PART, (size_t)s.splits * total * sizeof(float2));

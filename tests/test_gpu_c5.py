@@ -3,7 +3,8 @@ U[1, 3], bowls) in a 24^3 box, kappa = 4 pi, N = 1,351,890, 16 plane waves.
 
 At this size the FP64 reference computes sampled outputs one by one: rows of the
 inter-body sum over all 1.35 million sources for 16 right-hand sides (FP32 in
-the launch shape the library picks for 16 rhs -- the MFMA order -- and FP64),
+the launch shape the library picks for 16 rhs -- the MFMA order with the
+FP16 multiply-accumulate -- and FP64),
 and rows of the modal matrices of the bowl and of the most elongated spheroid.
 Tolerances as in test_gpu_fullsize.py."""
 import numpy as np
@@ -34,7 +35,7 @@ def test_c5_interbody_sampled_rows_16_rhs(many):
     from oracle.multibody import apply_B_c
     from paper_1406_0236_amd import FP32, FP64
     wl, S, ctx = many
-    assert ctx.interbody_launch_shape(FP32, 16)[0] == 3      # MFMA order for 16 rhs
+    assert ctx.interbody_launch_shape(FP32, 16)[0] == 4      # MFMA order, FP16 multiply-accumulate
     rng = np.random.default_rng(201)
     sig = rng.standard_normal((16, S.N)) + 1j * rng.standard_normal((16, S.N))
     rows = np.sort(rng.choice(S.N, 96, replace=False))

@@ -300,7 +300,7 @@ def test_error_paths():
     with pytest.raises(AxsError, match="EINVAL"):   # output overlaps input
         ctx.apply_matvec(y, FP64, out=y)
     with pytest.raises(AxsError, match="EINVAL"):   # no such source order
-        ctx.set_interbody_config(FP64, 4, 2, 256, 0)
+        ctx.set_interbody_config(FP64, 5, 2, 256, 0)
     # a single body: no inter-body terms, the operator is the identity
     z = torch.from_numpy(_rand(ctx.N, 1, 3)).to("cuda:0")
     assert torch.equal(ctx.apply_matvec(z, FP64), z)
@@ -467,6 +467,54 @@ def test_mfma_accumulation_16_wide(small):
         ctx.set_interbody_config(prec, 0, 0, 0, 0)
 
 
+def test_fp16_multiply_accumulate_matches_reference(small):
+    """MFMA order with the complex multiply-accumulate on the FP16 matrix cores
+    (kernel values and densities split into scaled high and low FP16 parts):
+    37 right-hand sides = two groups of 16 in 32-node source blocks (the last
+    block of each body padded) and a remainder of 5 through the FP32 MFMA
+    order; 1, 2 or 4 groups of 16 targets per wavefront, several splits; every
+    column against the reference to the FP32 tolerance, bit for bit again on a
+    second call, and within 2e-6 of the FP32 MFMA order.  It is the library
+    default for FP32 from 16 rhs, and refused in FP64."""
+    from paper_1406_0236_amd import FP32, FP64, AxsError
+    wl, S, ctx = small
+    assert ctx.interbody_launch_shape(FP32, 16)[0] == 4
+    assert ctx.interbody_launch_shape(FP32, 15)[0] != 4
+    x = _rand(S.N, 37, 94)
+    ref = S.apply_B(x.T).T
+    ctx.set_interbody_config(FP32, 3, 2, 256, 0)
+    y3 = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
+    for g, splits in ((1, 0), (2, 3), (4, 16)):
+        ctx.set_interbody_config(FP32, 4, g, 256, splits)
+        y = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
+        e, e3 = rel(y, ref), rel(y, y3)
+        print(f"G {g} splits {splits}: rel err {e:.2e}, vs FP32 MFMA order {e3:.2e}")
+        assert e < 3e-5 and e3 < 2e-6, (g, splits, e, e3)
+        assert np.array_equal(y, ctx.apply_interbody(_dev(x), FP32).cpu().numpy())
+    ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+    ctx.set_interbody_config(FP64, 4, 2, 256, 0)
+    with pytest.raises(AxsError, match="EINVAL"):
+        ctx.apply_interbody(_dev(x[:16]), FP64)
+    ctx.set_interbody_config(FP64, 0, 0, 0, 0)
+
+
+def test_fp16_multiply_accumulate_scales_each_rhs(small):
+    """Per-rhs density scales: 16 columns whose magnitudes run from 1e-30 to 1e+30
+    and one zero column; each column relative to its own largest value."""
+    from paper_1406_0236_amd import FP32
+    wl, S, ctx = small
+    x = _rand(S.N, 16, 95) * (10.0 ** np.linspace(-30, 30, 16))[:, None]
+    x[7] = 0.0
+    ref = S.apply_B(x.T).T
+    ctx.set_interbody_config(FP32, 4, 2, 256, 0)
+    y = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
+    ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+    assert np.all(y[7] == 0)
+    worst = max(rel(y[c], ref[c]) for c in range(16) if c != 7)
+    print(f"worst column rel err {worst:.2e}")
+    assert worst < 3e-5, worst
+
+
 def test_mfma_source_order_mixed_bodies_64_rhs(mixed):
     """Rotated spheroids and bowls, 8 bodies of three shapes, 64 right-hand sides
     (four MFMA-accumulated groups of 16); three columns against the reference."""
@@ -475,9 +523,10 @@ def test_mfma_source_order_mixed_bodies_64_rhs(mixed):
     sig = _rand(S.N, 64, 93)
     picks = [0, 17, 63]
     ref = S.apply_B(sig[picks].T).T
-    ctx.set_interbody_config(FP32, 3, 2, 256, 0)
-    y = ctx.apply_interbody(_dev(sig), FP32).cpu().numpy()[picks]
+    for variant in (3, 4):
+        ctx.set_interbody_config(FP32, variant, 2, 256, 0)
+        y = ctx.apply_interbody(_dev(sig), FP32).cpu().numpy()[picks]
+        e = rel(y, ref)
+        print(f"mixed bodies, MFMA order (variant {variant}), 64 rhs: rel err {e:.2e}")
+        assert e < 3e-5, (variant, e)
     ctx.set_interbody_config(FP32, 0, 0, 0, 0)
-    e = rel(y, ref)
-    print(f"mixed bodies, MFMA order, 64 rhs: rel err {e:.2e}")
-    assert e < 3e-5, e
