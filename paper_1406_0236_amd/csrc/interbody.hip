@@ -837,18 +837,25 @@ constexpr int MF16_BLK = 6 * 16 * 4; // h8 per block: 6 planes x 16 rhs x 4 k-sl
 __device__ __forceinline__ f32x4 mfma_16x16x32h(h8 a, h8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
-// high and low FP16 parts of eight values
+// high and low FP16 parts of eight values: the high part rounded toward zero
+// (v_cvt_pkrtz, two values per instruction), the low part the exact FP32
+// remainder g - f32(high) rounded to nearest by the mixed-precision FMA, which
+// reads the FP16 high part directly and writes one half of the packed result
+// (v_fma_mixlo_f16 the low half, v_fma_mixhi_f16 the high half; each leaves
+// the other half of its destination as it was)
+__device__ __forceinline__ void split2(float a, float b, unsigned &hi, unsigned &lo) {
+    hi = __builtin_bit_cast(unsigned, __builtin_amdgcn_cvt_pkrtz(a, b));
+    unsigned l;
+    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(l) : "v"(hi), "v"(a));
+    asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(l) : "v"(hi), "v"(b));
+    lo = l;
+}
 __device__ __forceinline__ void split8(const float *g, h8 &hi, h8 &lo) {
+    unsigned h[4], l[4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const h2 h = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(g[2 * p], g[2 * p + 1]));
-        const h2 l = __builtin_bit_cast(
-            h2, __builtin_amdgcn_cvt_pkrtz(g[2 * p] - (float)h.x, g[2 * p + 1] - (float)h.y));
-        hi[2 * p] = h.x;
-        hi[2 * p + 1] = h.y;
-        lo[2 * p] = l.x;
-        lo[2 * p + 1] = l.y;
-    }
+    for (int p = 0; p < 4; ++p) split2(g[2 * p], g[2 * p + 1], h[p], l[p]);
+    hi = __builtin_bit_cast(h8, (uint4){h[0], h[1], h[2], h[3]});
+    lo = __builtin_bit_cast(h8, (uint4){l[0], l[1], l[2], l[3]});
 }
 // 2^(13 - e) for the largest |q| of a rhs (bits of a non-negative float), 1 for 0
 __device__ __forceinline__ int qscale_exp(unsigned bits) {
