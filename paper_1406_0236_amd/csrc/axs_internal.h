@@ -223,7 +223,7 @@ enum ScratchSlot {
     WS_KRYLOV2 = 14,
     WS_EVAL = 15,
     WS_Q16 = 16,     // FP16 density planes of the FP16 multiply-accumulate
-    WS_QMAX = 17,    // per-rhs max |q| (float bits)
+    WS_QMAX = 17,    // per-rhs max |q| (float bits), then the per-slice partial maxima
 };
 
 struct Skeleton {

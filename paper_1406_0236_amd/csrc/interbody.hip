@@ -864,21 +864,38 @@ __device__ __forceinline__ int qscale_exp(unsigned bits) {
     return 13 - (e < -100 ? -100 : e);
 }
 
-// per-rhs max of max(|re|, |im|) of the staged densities, as float bits
-__global__ __launch_bounds__(256) void qmax_kernel(const float2 *__restrict__ q, int64_t N, unsigned *qmax) {
-    const int c = blockIdx.y;
+// Per-rhs max of max(|re|, |im|) of the staged densities, as the bits of a
+// non-negative float (their integer order is the float order).  Two steps and
+// no atomics (device-wide atomics on one address serialise across the chip):
+// blocks (P, nrhs) reduce contiguous slices of a rhs into part[rhs][P], then
+// one wavefront per rhs reduces the P partial maxima.
+constexpr int QMAX_SLICES = 64;
+__global__ __launch_bounds__(256) void qmax_part_kernel(const float2 *__restrict__ q, int64_t N,
+                                                        unsigned *__restrict__ part) {
+    __shared__ float s_m[4];
+    const int c = blockIdx.y, P = gridDim.x;
+    const int64_t per = (N + P - 1) / P;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = min(N, lo + per);
     float m = 0.f;
-    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (int64_t)gridDim.x * 256) {
+    for (int64_t j = lo + threadIdx.x; j < hi; j += 256) {
         const float2 v = q[(int64_t)c * N + j];
         m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(qmax + c, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[(int64_t)c * P + blockIdx.x] = __float_as_uint(fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3])));
 }
-__global__ void zero_u32_kernel(unsigned *p, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0u;
+__global__ __launch_bounds__(64) void qmax_final_kernel(const unsigned *__restrict__ part, int P,
+                                                        unsigned *__restrict__ qmax) {
+    const int c = blockIdx.x;
+    unsigned m = 0u;
+    for (int i = threadIdx.x; i < P; i += 64) m = max(m, part[(int64_t)c * P + i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
+    if (threadIdx.x == 0) qmax[c] = m;
 }
 
 // six FP16 planes per 32-source block and rhs group (B-operand order)
@@ -1477,10 +1494,12 @@ static void launch_mf16(Ctx &c, const IBShape &s, const float2 *q, int nrhs, flo
     if (groups > 0) {
         int nwork = 0;
         const IBWork *work = get_work(c, 1, 2, s, Units::blocks, nwork);
-        unsigned *qmax = (unsigned *)c.scratch(WS_QMAX, (size_t)nrhs * sizeof(unsigned));
-        hipLaunchKernelGGL(zero_u32_kernel, dim3(ceil_div(nrhs, 256)), dim3(256), 0, c.stream, qmax, nrhs);
-        const int gx = (int)std::min<int64_t>(ceil_div(c.N, (int64_t)256), 1024);
-        hipLaunchKernelGGL(qmax_kernel, dim3(gx, nrhs), dim3(256), 0, c.stream, q, c.N, qmax);
+        // slices of at least 16K nodes per block, at most QMAX_SLICES per rhs
+        const int P = (int)std::min<int64_t>(QMAX_SLICES, std::max<int64_t>(1, c.N / 16384));
+        unsigned *qmax = (unsigned *)c.scratch(WS_QMAX, (size_t)nrhs * (P + 1) * sizeof(unsigned));
+        unsigned *qpart = qmax + nrhs;
+        hipLaunchKernelGGL(qmax_part_kernel, dim3(P, nrhs), dim3(256), 0, c.stream, q, c.N, qpart);
+        hipLaunchKernelGGL(qmax_final_kernel, dim3(nrhs), dim3(64), 0, c.stream, qpart, P, qmax);
         const int64_t items = (int64_t)groups * c.nblk * 512;
         _Float16 *q16 = (_Float16 *)c.scratch(WS_Q16, (size_t)items * 6 * sizeof(_Float16));
         hipLaunchKernelGGL(q16_kernel, dim3(ceil_div(items, (int64_t)256)), dim3(256), 0, c.stream, q, qmax,
