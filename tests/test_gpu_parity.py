@@ -515,6 +515,81 @@ def test_fp16_multiply_accumulate_scales_each_rhs(small):
     assert worst < 3e-5, worst
 
 
+def _edge_workload(tip_gap):
+    """A sphere of 144 nodes (four full 32-node blocks and a ragged one), a
+    spheroid of 84 nodes lying along x with its tip `tip_gap` from the sphere,
+    and a small sphere of 15 nodes (one padded block)."""
+    from workloads import configs, geometry as geo
+    to_x = np.array([[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [-1.0, 0.0, 0.0]])   # body z axis -> x
+    return configs.Workload(f"fp16_edges_gap{tip_gap}", 3.0, 3.0, [
+        configs.BodySpec(geo.sphere(1.0, 4, 4), np.zeros(3), np.eye(3), 4),
+        configs.BodySpec(geo.prolate(0.5, 1.0, 3, 4), np.array([2.0 + tip_gap, 0.0, 0.0]), to_x, 3),
+        configs.BodySpec(geo.sphere(0.3, 1, 3), np.array([0.0, 2.5, 0.0]), np.eye(3), 2)],
+        np.array([[0.0, 0.0, 1.0]]))
+
+
+def test_fp16_multiply_accumulate_ragged_blocks():
+    """Ragged and padded 32-node source blocks (bodies of 144, 84 and 15
+    nodes; the spheroid's tip 0.3 from the sphere) with 16, 17 and 33 rhs (one
+    or two full groups; remainders through the FP32 MFMA order), 1, 2 and 4
+    target groups per wavefront: every column against the reference to the
+    FP32 tolerance and within 2e-6 of the FP32 MFMA order."""
+    from oracle.multibody import System
+    from paper_1406_0236_amd import FP32
+    wl = _edge_workload(0.3)
+    assert [b.n_nodes for b in wl.bodies] == [144, 84, 15]
+    S = System.from_workload(wl)
+    ctx = _ctx_for(wl)
+    try:
+        assert ctx.interbody_launch_shape(FP32, 16)[0] == 4
+        for nrhs, seed in ((16, 96), (17, 97), (33, 98)):
+            x = _rand(S.N, nrhs, seed)
+            ref = S.apply_B(x.T).T
+            ctx.set_interbody_config(FP32, 3, 2, 256, 0)
+            y3 = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
+            for g in (1, 2, 4):
+                ctx.set_interbody_config(FP32, 4, g, 256, 0)
+                y = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
+                e = max(rel(y[c], ref[c]) for c in range(nrhs))
+                e3 = max(rel(y[c], y3[c]) for c in range(nrhs))
+                print(f"{nrhs} rhs, G {g}: worst column rel err {e:.2e}, vs FP32 MFMA order {e3:.2e}")
+                assert e < 3e-5 and e3 < 2e-6, (nrhs, g, e, e3)
+    finally:
+        ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+        ctx.close()
+
+
+def test_fp16_multiply_accumulate_negative_scale_exponent():
+    """The spheroid's tip 0.01 from the sphere: kernel values up to ~1e4, so
+    the power of two that brings them into FP16 range is below 1.  The FP16
+    multiply-accumulate must agree with the FP32 MFMA order, which shares its
+    kernel values.  Both differ from the FP64 reference by more than at wider
+    gaps: the MFMA and ring orders form R^2 as |p|^2 - 2 y.p + |y|^2 in the
+    source body's frame, which loses about eps32 |p|^2 / R^2 in relative terms
+    for pairs this close (the FP64 outer iteration of the mixed solver
+    absorbs it); that error is printed and bounded loosely."""
+    from oracle.multibody import System
+    from paper_1406_0236_amd import FP32
+    wl = _edge_workload(0.01)
+    S = System.from_workload(wl)
+    ctx = _ctx_for(wl)
+    try:
+        x = _rand(S.N, 17, 99)
+        ref = S.apply_B(x.T).T
+        ctx.set_interbody_config(FP32, 3, 2, 256, 0)
+        y3 = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
+        ctx.set_interbody_config(FP32, 4, 2, 256, 0)
+        y = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
+        e3 = max(rel(y[c], y3[c]) for c in range(17))
+        e = max(rel(y[c], ref[c]) for c in range(17))
+        print(f"gap 0.01: FP16 vs FP32 MFMA order {e3:.2e}; vs FP64 reference {e:.2e}")
+        assert e3 < 2e-6, e3
+        assert e < 1e-2, e
+    finally:
+        ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+        ctx.close()
+
+
 def test_mfma_source_order_mixed_bodies_64_rhs(mixed):
     """Rotated spheroids and bowls, 8 bodies of three shapes, 64 right-hand sides
     (four MFMA-accumulated groups of 16); three columns against the reference."""
