@@ -114,6 +114,12 @@ def main():
                     help="zero frequency: 125 spheroids 2 x 1 x 1 on a 5^3 lattice (tips 0.05 apart), "
                          "10,100 nodes each, interior point sources; FP64 GMRES with and without the "
                          "preconditioner, mixed FGMRES, error of the exterior field")
+    ap.add_argument("--laplace-table", action="store_true",
+                    help="the rows of the paper's 125-ellipsoid Laplace table (Sec. 6.1; tests/golden/"
+                         "laplace_125_spheroids_table.txt): FP64 GMRES to 1e-9 with and without the "
+                         "preconditioner at each (N_G, N_F), field error at 10 exterior targets")
+    ap.add_argument("--uniform-sources", action="store_true",
+                    help="with --laplace-table: interior point sources uniform in each body's volume")
     ap.add_argument("--modal-probe", action="store_true",
                     help="time the per-mode scattering applies (MFMA GEMM) with HIP events: 27 spheres "
                          "with 1 and 16 rhs, 8 mixed bodies with 64 rhs, FP32 and FP64; also the launches "
@@ -148,6 +154,8 @@ def main():
         return many(args)
     if args.laplace:
         return laplace(args)
+    if args.laplace_table:
+        return laplace_table(args)
     if args.skeleton:
         return skeleton(args)
 
@@ -559,6 +567,63 @@ def laplace(args):
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def laplace_table(args):
+    """The paper's 125-ellipsoid Laplace table, row by row, on the lattice
+    reading of its geometry: FP64 GMRES to 1e-9 with and without the
+    block-diagonal preconditioner, and the relative l-infinity error of the
+    exterior field at 10 targets against the exact field of the interior point
+    sources, printed next to the paper's values (its times are other hardware's
+    and not compared)."""
+    import numpy as np
+    import torch
+    from paper_1406_0236_amd import SOLVE_FP64, Context
+    from workloads import configs
+    rows = np.loadtxt(os.path.join(ROOT, "tests", "golden", "laplace_125_spheroids_table.txt"))
+    out_rows = []
+    for N, NG, NF, i_pre, i_no, e_paper in rows:
+        NG, NF = int(NG), int(NF)
+        wl = configs.laplace_ellipsoids(n_panels=NG // 10, p=10, M=(NF - 1) // 2)
+        assert wl.N == int(N), (wl.N, N)
+        ctx = Context(0).add_workload(wl)
+        ctx.precompute_scattering()
+        # sources near each centre (the default reading), or anywhere in the
+        # body's volume (--uniform-sources), whose fields on the surface need
+        # more Fourier modes and panels
+        src = configs.point_sources(wl, seed=11, uniform=args.uniform_sources)
+        amp = np.random.default_rng(12).standard_normal(len(src))
+        v = ctx.incident_point_sources(src, amp)
+        res = {}
+        for name, pre in (("pre", True), ("nopre", False)):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            sol, info = ctx.solve(v, mode=SOLVE_FP64, tol=1e-9, precondition=pre)
+            torch.cuda.synchronize()
+            res[name] = {"s": time.time() - t0, "iterations": info[0]["iterations"]}
+            if pre:
+                xt = configs.exterior_targets(wl, 10, seed=12)
+                u = ctx.eval_field(sol, xt).cpu().numpy()[0]
+                d = xt[:, None, :] - src[None, :, :]
+                exact = -(1.0 / (4.0 * math.pi * np.linalg.norm(d, axis=-1))) @ amp
+                res["e_inf"] = float(np.max(np.abs(u - exact)) / np.max(np.abs(exact)))
+        ctx.close()
+        row = {"workload": wl.name, "N": wl.N, "N_G": NG, "N_F": NF,
+               "iterations_pre": res["pre"]["iterations"], "iterations_nopre": res["nopre"]["iterations"],
+               "e_inf": res["e_inf"], "s_pre": res["pre"]["s"], "s_nopre": res["nopre"]["s"],
+               "paper": {"iterations_pre": int(i_pre), "iterations_nopre": int(i_no), "e_inf": e_paper}}
+        log(f"{wl.name} {NG} x {NF}: N = {wl.N}, iterations {row['iterations_pre']} / {row['iterations_nopre']} "
+            f"(paper {int(i_pre)} / {int(i_no)}), E_inf {res['e_inf']:.3e} (paper {e_paper:.3e}), "
+            f"FP64 solves {res['pre']['s']:.1f} / {res['nopre']['s']:.1f} s")
+        out_rows.append(row)
+    out = {"metric": "the paper's 125-ellipsoid Laplace table: iterations to 1e-9 with / without the "
+                     "preconditioner and field error", "unit": "rows", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "laplace_ellipsoids_125", "kappa": 0.0, "eta": 1.0, "tol": 1e-9,
+                      "sources": "one per body, " + ("uniform in its volume" if args.uniform_sources
+                                                     else "within half the inradius of its centre")
+                                 + " (seed 11)"},
+           "rows": out_rows}
+    print(json.dumps(out), flush=True)
 
 
 def modal_probe():

@@ -98,3 +98,48 @@ def test_laplace_has_no_far_field(lap):
     x = torch.zeros((1, S.N), dtype=torch.complex128, device="cuda:0")
     with pytest.raises(AxsError, match="EINVAL"):
         ctx.far_field(x, np.array([[0.0, 0.0, 1.0]]))
+
+
+def test_laplace_125_spheroids_first_table_row():
+    """The first row of the paper's 125-ellipsoid table (Sec. 6.1, fixture
+    tests/golden/laplace_125_spheroids_table.txt): N_G = 50, N_F = 25, N =
+    156,250 on the lattice reading of the geometry, FP64 GMRES to 1e-9.  The
+    paper's observation at zero frequency -- the block-diagonal preconditioner
+    makes no real difference (31 vs 33 iterations) -- must hold: the two
+    iteration counts within 3 of each other and each within 5 of the printed
+    one.  The field error depends on where the interior sources sit, which the
+    paper does not state; with sources near the centres it is far below the
+    printed 9.7e-5 and is only checked against 1e-6."""
+    import math
+    import os
+    from paper_1406_0236_amd import SOLVE_FP64, Context
+    from workloads import configs
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "laplace_125_spheroids_table.txt"))
+    N, NG, NF, i_pre, i_no, e_paper = rows[0]
+    wl = configs.laplace_ellipsoids(n_panels=int(NG) // 10, p=10, M=(int(NF) - 1) // 2)
+    assert wl.N == int(N)
+    print(f"[gpu] Laplace 125 spheroids N={wl.N}", flush=True)
+    ctx = Context(0).add_workload(wl)
+    try:
+        ctx.precompute_scattering()
+        src = configs.point_sources(wl, seed=11)
+        amp = np.random.default_rng(12).standard_normal(len(src))
+        v = ctx.incident_point_sources(src, amp)
+        its = {}
+        for pre in (True, False):
+            sol, info = ctx.solve(v, mode=SOLVE_FP64, tol=1e-9, precondition=pre)
+            assert info[0]["converged"]
+            its[pre] = info[0]["iterations"]
+            if pre:
+                xt = configs.exterior_targets(wl, 10, seed=12)
+                u = ctx.eval_field(sol, xt).cpu().numpy()[0]
+                d = xt[:, None, :] - src[None, :, :]
+                exact = -(1.0 / (4.0 * math.pi * np.linalg.norm(d, axis=-1))) @ amp
+                err = float(np.max(np.abs(u - exact)) / np.max(np.abs(exact)))
+        print(f"iterations {its[True]} / {its[False]} (paper {int(i_pre)} / {int(i_no)}), "
+              f"E_inf {err:.2e} (paper {e_paper:.2e})")
+        assert abs(its[True] - its[False]) <= 3
+        assert abs(its[True] - i_pre) <= 5 and abs(its[False] - i_no) <= 5
+        assert err < 1e-6
+    finally:
+        ctx.close()

@@ -136,16 +136,23 @@ def laplace_small() -> Workload:
                     "kappa = 0: sphere, spheroid, bowl")
 
 
-def laplace_ellipsoids(per_side=5, spacing=2.05, n_panels=10, p=10, M=50) -> Workload:
-    """125 prolate spheroids (axes 2 x 1 x 1) on a 5^3 lattice of spacing 2.05, all along z,
-    so that neighbouring tips are 0.05 apart inside [0, 10.2]^3; kappa = 0, eta = 1;
-    10 x 10 contour nodes x 101 azimuthal nodes = 10,100 nodes per body."""
+def laplace_ellipsoids(per_side=5, spacing=2.05, n_panels=10, p=10, M=50, orient_seed=None) -> Workload:
+    """125 prolate spheroids (axes 2 x 1 x 1) on a 5^3 lattice of spacing 2.05 inside
+    [0, 10.2]^3; kappa = 0, eta = 1; 10 x 10 contour nodes x 101 azimuthal nodes =
+    10,100 nodes per body.  By default all long axes lie along z, so neighbouring
+    tips are 0.05 apart on their common axis; with orient_seed every body gets a
+    seeded uniform random orientation (bounding balls stay 0.05 apart, so no two
+    bodies come closer than 0.05, and close approaches are off the axes)."""
     c = geo.prolate(0.5, 1.0, n_panels, p)
     offs = 1.0 + spacing * np.arange(per_side)
-    bodies = [BodySpec(c, np.array(xyz, dtype=np.float64), np.eye(3), M)
+    rng = np.random.default_rng(orient_seed) if orient_seed is not None else None
+    bodies = [BodySpec(c, np.array(xyz, dtype=np.float64),
+                       geo.random_rotation(rng) if rng is not None else np.eye(3), M)
               for xyz in itertools.product(offs, offs, offs)]
-    return Workload("laplace_ellipsoids_125", 0.0, 1.0, bodies, np.zeros((1, 3)),
-                    "125 spheroids 2 x 1 x 1, 5^3 lattice, spacing 2.05, kappa = 0")
+    tag = "" if orient_seed is None else f"_rot{orient_seed}"
+    return Workload("laplace_ellipsoids_125" + tag, 0.0, 1.0, bodies, np.zeros((1, 3)),
+                    "125 spheroids 2 x 1 x 1, 5^3 lattice, spacing 2.05, kappa = 0"
+                    + ("" if orient_seed is None else ", random orientations"))
 
 
 def single_sphere(a=1.0, n_panels=10, p=10, M=20, kappa=math.pi) -> Workload:
@@ -154,10 +161,14 @@ def single_sphere(a=1.0, n_panels=10, p=10, M=20, kappa=math.pi) -> Workload:
                     np.array([[0.0, 0.0, 1.0]]))
 
 
-def point_sources(wl: Workload, seed: int = 11):
-    """One seeded point source strictly inside each body (global frame)."""
+def point_sources(wl: Workload, seed: int = 11, uniform: bool = False):
+    """One seeded point source strictly inside each body (global frame): within
+    half the inradius of the centre (bowls: inside the wall), or with
+    uniform=True uniformly distributed in the body's volume (spheres and
+    spheroids)."""
     rng = np.random.default_rng(seed)
-    return np.array([b.centre + b.rot @ geo.interior_point(b.contour, rng) for b in wl.bodies])
+    pick = geo.uniform_interior_point if uniform else geo.interior_point
+    return np.array([b.centre + b.rot @ pick(b.contour, rng) for b in wl.bodies])
 
 
 def exterior_targets(wl: Workload, n: int = 10, seed: int = 12) -> np.ndarray:

@@ -219,5 +219,18 @@ def interior_point(contour: Contour, rng: np.random.Generator) -> np.ndarray:
     return v * rng.uniform(0.0, 0.5 * inr)
 
 
+def uniform_interior_point(contour: Contour, rng: np.random.Generator) -> np.ndarray:
+    """A seeded point uniformly distributed in the volume of a sphere or spheroid
+    (body frame), by rejection from the bounding box."""
+    if contour.kind not in ("sphere", "prolate"):
+        raise ValueError("uniform interior points are defined for spheres and spheroids")
+    a = contour.params["a"]
+    c = contour.params.get("c", a)
+    while True:
+        x = rng.uniform(-1.0, 1.0, 3)
+        if x @ x < 1.0:
+            return x * np.array([a, a, c])
+
+
 def sphere_targets(n: int, radius: float, centre, rng: np.random.Generator) -> np.ndarray:
     return np.asarray(centre) + radius * uniform_directions(n, rng)
