@@ -130,7 +130,8 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="launch only what the hardware-counter passes measure: a 512 MiB device copy "
                          "(calibration), then two FP32 and one FP64 inter-body sums on the 27 spheres, "
-                         "and two FP32 64-rhs sums (MFMA order) on the 8 mixed bodies")
+                         "and FP32 64-rhs sums on the 8 mixed bodies: two with FP32 MFMAs, two with the FP16 "
+                         "multiply-accumulate")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -430,7 +431,8 @@ def pmc_probe():
 
 def many(args):
     """One mixed and one FP64 solve of 16 plane waves on the 64-body workload,
-    library default launch shapes (MFMA order for FP32 at 16 rhs)."""
+    library default launch shapes (for 16 rhs: in FP32 the MFMA order with the FP16
+    multiply-accumulate, in FP64 the MFMA order)."""
     import numpy as np
     import torch
     os.environ.setdefault("AXS_VERBOSE", "1")     # one progress line per iteration
