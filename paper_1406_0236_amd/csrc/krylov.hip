@@ -101,6 +101,16 @@ __global__ void cscale_kernel(const double2 *__restrict__ in, const double *__re
     out[t] = make_double2(v.x * f, v.y * f);
 }
 
+// w[c][n] /= sqrt(nrm[c].x), or 0 where that norm is 0 (the new Arnoldi vector)
+__global__ void cnormalize_kernel(double2 *__restrict__ w, const double2 *__restrict__ nrm, int64_t N, int nrhs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * nrhs) return;
+    const double n2 = nrm[t / N].x;
+    const double f = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+    const double2 v = w[t];
+    w[t] = make_double2(v.x * f, v.y * f);
+}
+
 // out = a - b
 __global__ void csub_kernel(const double2 *__restrict__ a, const double2 *__restrict__ b, double2 *__restrict__ out,
                             int64_t n) {
@@ -129,14 +139,18 @@ struct Dots {
         c.dfree(partial);
         c.dfree(dev);
     }
-    // h[c][i] = V_i^H w (device + host copies)
-    void run(const double2 *V, int64_t ldv, int nvec, const double2 *w) {
+    // out[c][i] = V_i^H w on the device (stream-ordered, no host copy)
+    void launch(const double2 *V, int64_t ldv, int nvec, const double2 *w, double2 *out) {
         hipLaunchKernelGGL(cdot_many_kernel, dim3(nblk, nrhs), dim3(KR_BS), 0, c.stream, V, ldv, nvec, w, N,
                            partial);
         AXS_HIP(hipGetLastError());
         hipLaunchKernelGGL(reduce_dots_kernel, dim3(ceil_div(nvec * nrhs, 128)), dim3(128), 0, c.stream, partial,
-                           nblk, nvec, nrhs, dev);
+                           nblk, nvec, nrhs, out);
         AXS_HIP(hipGetLastError());
+    }
+    // h[c][i] = V_i^H w (device + host copies)
+    void run(const double2 *V, int64_t ldv, int nvec, const double2 *w) {
+        launch(V, ldv, nvec, w, dev);
         AXS_HIP(hipMemcpyAsync(host.data(), dev, (size_t)nvec * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
                                c.stream));
         AXS_HIP(hipStreamSynchronize(c.stream));
@@ -241,6 +255,10 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
     Dots D(c, N, nrhs, maxit + 1);
     double2 *hdev = (double2 *)c.dalloc((size_t)nrhs * (maxit + 1) * sizeof(double2));
     double *sdev = (double *)c.dalloc(nrhs * sizeof(double));
+    // per Arnoldi step: both Gram-Schmidt passes' coefficients [nrhs][j+1] and
+    // the squared norm of the new vector [nrhs], read back in one copy
+    double2 *cdev = (double2 *)c.dalloc((size_t)nrhs * (2 * maxit + 1) * sizeof(double2));
+    std::vector<double2> chost((size_t)nrhs * (2 * maxit + 1));
     // beta = ||r0||
     D.run(r0, ldv, 1, r0);
     std::vector<double> beta(nrhs), inv(nrhs);
@@ -259,6 +277,7 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
     if (all_done) {
         c.dfree(hdev);
         c.dfree(sdev);
+        c.dfree(cdev);
         return iters;
     }
     scale(c, r0, inv, V, N, nrhs, sdev);
@@ -273,27 +292,34 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
         } else {
             op(vj, w);
         }
-        // classical Gram-Schmidt, twice
-        std::vector<cd> hsum((size_t)nrhs * (j + 1), 0.0);
+        // classical Gram-Schmidt, twice, then the norm and the normalisation of
+        // the new vector, all stream-ordered on the device; the coefficients
+        // come to the host in one copy, the only synchronisation of the step
+        const int nv = j + 1;
+        const int64_t nh = (int64_t)nrhs * nv;
         for (int pass = 0; pass < 2; ++pass) {
-            D.run(V, ldv, j + 1, w);
-            std::vector<cd> hcur((size_t)nrhs * (j + 1));
-            for (int cc = 0; cc < nrhs; ++cc)
-                for (int i = 0; i <= j; ++i) {
-                    hcur[(size_t)cc * (j + 1) + i] = D.get(cc, i, j + 1);
-                    hsum[(size_t)cc * (j + 1) + i] += hcur[(size_t)cc * (j + 1) + i];
-                }
-            axpy_many(c, V, ldv, j + 1, hcur, nrhs, -1.0, w, N, hdev);
+            double2 *hc = cdev + pass * nh;
+            D.launch(V, ldv, nv, w, hc);
+            hipLaunchKernelGGL(caxpy_many_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, V, ldv,
+                               nv, hc, -1.0, w, N, nrhs);
+            AXS_HIP(hipGetLastError());
         }
-        D.run(w, ldv, 1, w);
-        std::vector<double> sc(nrhs);
+        D.launch(w, ldv, 1, w, cdev + 2 * nh);
+        hipLaunchKernelGGL(cnormalize_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, w,
+                           cdev + 2 * nh, N, nrhs);
+        AXS_HIP(hipGetLastError());
+        AXS_HIP(hipMemcpyAsync(chost.data(), cdev, (size_t)(2 * nh + nrhs) * sizeof(double2),
+                               hipMemcpyDeviceToHost, c.stream));
+        AXS_HIP(hipStreamSynchronize(c.stream));
         all_done = true;
         for (int cc = 0; cc < nrhs; ++cc) {
-            const double hn = std::sqrt(std::max(0.0, D.get(cc, 0, 1).real()));
+            const double hn = std::sqrt(std::max(0.0, chost[2 * nh + cc].x));
             AXS_REQUIRE(std::isfinite(hn), AXS_ENONFINITE, "non-finite Arnoldi vector");
-            for (int i = 0; i <= j; ++i) G.h(cc, i, j) = hsum[(size_t)cc * (j + 1) + i];
+            for (int i = 0; i < nv; ++i) {
+                const double2 a = chost[(size_t)cc * nv + i], b = chost[nh + (size_t)cc * nv + i];
+                G.h(cc, i, j) = cd(a.x + b.x, a.y + b.y);
+            }
             G.h(cc, j + 1, j) = hn;
-            sc[cc] = hn > 0 ? 1.0 / hn : 0.0;
             if (G.done_at[cc] < 0) {
                 const double res = G.rotate(cc, j);
                 rel_est[cc] = res / bnorm[cc];
@@ -307,7 +333,6 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
             std::fprintf(stderr, "[axs] %s iteration %d: max relative residual %.3e\n",
                          flexible ? "outer" : "gmres", j + 1, worst);
         }
-        scale(c, w, sc, w, N, nrhs, sdev);
         if (all_done) {
             ++j;
             break;
@@ -333,6 +358,7 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
     }
     c.dfree(hdev);
     c.dfree(sdev);
+    c.dfree(cdev);
     return iters;
 }
 
