@@ -123,6 +123,25 @@ def mixed_many(seed=5, kappa=4 * math.pi, n_bodies=64, box=24.0, gap=0.5, n_dirs
                     geo.fibonacci_directions(n_dirs), "64 mixed bodies in 24^3, gap 0.5")
 
 
+def cavities_8(kappa=2 * math.pi, panels_per_unit=20.0 / math.pi, M=25, seed=4, p=10) -> Workload:
+    """8 bowl cavities (outer radius 1, so 2 wavelengths across at kappa = 2 pi)
+    on a 2 x 2 x 2 lattice whose bounding balls are 0.5 apart, each opening in a
+    seeded uniform random direction; one point source inside each wall."""
+    rng = np.random.default_rng(seed)
+
+    def npan(length, lo=1):
+        return max(lo, int(math.ceil(length * panels_per_unit - 1e-9)))
+
+    al = 2.0 * math.pi / 3.0
+    bw = geo.bowl(npan(0.8 * al), npan(0.1 * math.pi, 2), npan(al), p)
+    step = 2.0 * bw.bound_radius + 0.5
+    offs = bw.bound_radius + step * np.arange(2)
+    bodies = [BodySpec(bw, np.array(xyz, dtype=np.float64), geo.random_rotation(rng), M)
+              for xyz in itertools.product(offs, offs, offs)]
+    return Workload(f"cavities8_k{kappa / math.pi:g}pi", kappa, kappa, bodies, np.array([[0.0, 0.0, 1.0]]),
+                    "8 bowls, 2 x 2 x 2 lattice, bounding balls 0.5 apart, random orientations")
+
+
 def laplace_small() -> Workload:
     """kappa = 0, eta = 1: unit sphere, spheroid 0.8 x 1.3 and a bowl, rotated, gaps > 0.5."""
     rng = np.random.default_rng(21)
