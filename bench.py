@@ -38,7 +38,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
 # source they were taken on.
 TRAFFIC_BYTES = 115.16e6
-TRAFFIC_SOURCE_SHA = "b73345308b65f7f0"
+TRAFFIC_SOURCE_SHA = "e94fac8b01beec23"
 
 
 def log(msg):

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/axs.h"
+#include "worktable.h"
 
 namespace axs {
 
@@ -78,11 +79,6 @@ struct Body {
 // Inter-body work item: one body-aligned target tile against up to two
 // contiguous source ranges (everything outside the target's body, cut into
 // `splits` chunks).  slot = chunk index; partial sums go to part[slot].
-struct IBWork {
-    int32_t t0, tn;
-    int32_t s0, s1, s2, s3;
-    int32_t slot, pad;
-};
 
 // Body descriptor used by the DFT kernels.  The DFT workspace holds, per
 // shape, a mode-major block of columns (column-major, leading dimension NG):

@@ -1178,13 +1178,10 @@ void interbody_shape(Ctx &c, int prec, int nrhs, int out[4]) {
     out[3] = s.splits;
 }
 
-// Work items: every body-aligned tile of `tile` targets against `splits`
-// chunks of the source units (nodes, rings or 32-node blocks) outside the
-// target's body.
+// Work items (worktable.h) in units of nodes, rings or 32-node blocks
 enum class Units { nodes, rings, blocks };
 static std::vector<IBWork> build_work(Ctx &c, int tile, int splits, Units units) {
-    std::vector<IBWork> out;
-    const int64_t U = units == Units::rings ? c.nrings : units == Units::blocks ? c.nblk : c.N;
+    std::vector<WorkBody> wb;
     int64_t boff = 0;
     for (size_t bi = 0; bi < c.bodies.size(); ++bi) {
         const auto &b = c.bodies[bi];
@@ -1192,30 +1189,10 @@ static std::vector<IBWork> build_work(Ctx &c, int tile, int splits, Units units)
         const int64_t uoff = units == Units::rings ? c.ring_base[bi] : units == Units::blocks ? boff : b.offset;
         const int64_t un = units == Units::rings ? c.shapes[b.shape].NG : units == Units::blocks ? nbk : b.n;
         boff += nbk;
-        const int64_t others = U - un;
-        const int64_t chunk = ceil_div(std::max<int64_t>(others, 1), splits);
-        for (int64_t t0 = 0; t0 < b.n; t0 += tile) {
-            for (int s = 0; s < splits; ++s) {
-                IBWork w{};
-                w.t0 = (int32_t)(b.offset + t0);
-                w.tn = (int32_t)std::min<int64_t>(tile, b.n - t0);
-                const int64_t v0 = std::min<int64_t>(others, (int64_t)s * chunk);
-                const int64_t v1 = std::min<int64_t>(others, v0 + chunk);
-                // virtual unit v < uoff -> v ; v >= uoff -> v + un (skips the own body)
-                int64_t a0 = v0, a1 = std::min<int64_t>(v1, uoff);
-                if (a1 < a0) a1 = a0;
-                int64_t b0 = std::max<int64_t>(v0, uoff), b1 = v1;
-                if (b1 < b0) b1 = b0;
-                w.s0 = (int32_t)a0;
-                w.s1 = (int32_t)a1;
-                w.s2 = (int32_t)(b0 + un);
-                w.s3 = (int32_t)(b1 + un);
-                w.slot = s;
-                out.push_back(w);
-            }
-        }
+        wb.push_back(WorkBody{b.offset, b.n, uoff, un});
     }
-    return out;
+    const int64_t U = units == Units::rings ? c.nrings : units == Units::blocks ? c.nblk : c.N;
+    return build_work_table(wb, U, tile, splits);
 }
 
 // ring tables, body frames and per-node azimuth cos/sin (built once)
