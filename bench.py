@@ -36,9 +36,23 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of the default FP32 inter-body kernel on this workload,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled by a calibration copy
 # (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
-# source they were taken on.
+# source they were taken on (source_fingerprint: code, not comments).
 TRAFFIC_BYTES = 115.16e6
-TRAFFIC_SOURCE_SHA = "e94fac8b01beec23"
+TRAFFIC_SOURCE_SHA = "739de903d62b60d3"
+
+
+def source_fingerprint(path):
+    """First 16 hex digits of the sha256 of a C/HIP source with its comments
+    removed and its whitespace collapsed: any change of code changes it, an
+    edit of comments or layout does not."""
+    import hashlib
+    import re
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def log(msg):
@@ -264,9 +278,7 @@ def main():
     t_ib64 = float(np.median(ms64)) * 1e-3
     pairs = wl.pairs
     flops = FLOP_PER_PAIR * pairs
-    import hashlib
-    with open(os.path.join(ROOT, "paper_1406_0236_amd", "csrc", "interbody.hip"), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    sha = source_fingerprint(os.path.join(ROOT, "paper_1406_0236_amd", "csrc", "interbody.hip"))
     traffic = TRAFFIC_BYTES if (sha == TRAFFIC_SOURCE_SHA and not args.small and tuned is None) else None
     achieved = flops / t_ib / 1e12
     log(f"interbody fp32 {t_ib*1e3:.2f} ms ({pairs / t_ib / 1e9:.1f} Gpairs/s, {achieved:.2f} TFLOP/s); "

@@ -1128,10 +1128,11 @@ static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
     const int pi = prec == AXS_FP32 ? 1 : 0;
     IBShape s;
     // Defaults from the launch-shape sweeps on MI355X (27-sphere lattice, one
-    // rhs; 8 mixed bodies, 1-64 rhs): below 16 rhs the ring order (1 target
-    // per thread in FP32, 4 in FP64), from 16 rhs on the MFMA order (2 groups
-    // of 16 targets per wavefront in FP32, 4 in FP64); the point order where
-    // neither applies.
+    // rhs; 8 mixed bodies, 1-64 rhs; 64 mixed bodies, 16 rhs): below 16 rhs
+    // the ring order (1 target per thread in FP32, 4 in FP64), from 16 rhs on
+    // the MFMA order (2 groups of 16 targets per wavefront in FP32, with the
+    // FP16 multiply-accumulate where the kernel values have a bound; 4 groups
+    // in FP64); the point order where neither applies.
     s.bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : 256;
     const bool ring_ok = c.max_nf / 2 + 1 <= s.bs && (c.kappa == 0 || c.near_phase_ok);
     const bool mf_ok = c.kappa > 0 && c.mf_src && c.near_phase_ok && s.bs == 256 &&
