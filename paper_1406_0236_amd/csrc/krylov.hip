@@ -240,14 +240,44 @@ struct Gmres {
     }
 };
 
-// Run GMRES for nrhs systems: op(x, y) computes y = A x.  V must hold
+// A Krylov basis: up to `maxvec` vectors of `vb` bytes in one allocation that
+// grows on demand (to at least 16 vectors, doubling), so that the memory of a
+// solve follows the iterations it takes rather than its iteration limit.  The
+// base pointer changes when the basis grows.
+struct Basis {
+    Ctx &c;
+    size_t vb;
+    int maxvec, cap = 0;
+    double2 *p = nullptr;
+    Basis(Ctx &c_, size_t vb_, int maxvec_) : c(c_), vb(vb_), maxvec(maxvec_) {}
+    Basis(const Basis &) = delete;
+    Basis &operator=(const Basis &) = delete;
+    ~Basis() { c.dfree(p); }
+    double2 *vec(int i) const { return p + (size_t)i * (vb / sizeof(double2)); }
+    // room for n vectors; the first `keep` are carried over
+    void reserve(int n, int keep) {
+        if (n <= cap) return;
+        AXS_REQUIRE(n <= maxvec, AXS_EINVAL, "Krylov basis beyond its iteration limit");
+        const int nc = std::min(maxvec, std::max(n, std::max(16, 2 * cap)));
+        double2 *q = (double2 *)c.dalloc((size_t)nc * vb);
+        if (keep > 0) {
+            AXS_HIP(hipMemcpyAsync(q, p, (size_t)keep * vb, hipMemcpyDeviceToDevice, c.stream));
+            AXS_HIP(hipStreamSynchronize(c.stream));   // the old block is released after the copy
+        }
+        c.dfree(p);
+        p = q;
+        cap = nc;
+    }
+};
+
+// Run GMRES for nrhs systems: op(x, y) computes y = A x.  V grows to at most
 // (maxit+1) vectors of nrhs*N.  Optional flexible mode: prec(v, z) gives
-// z_j ~ A^{-1} v_j stored in Z (maxit vectors), and the solution update uses Z.
-// On entry r0 holds the initial residual. On exit x += (V or Z) y.
+// z_j ~ A^{-1} v_j stored in Z (at most maxit vectors), and the solution update
+// uses Z.  On entry r0 holds the initial residual. On exit x += (V or Z) y.
 // Returns the iteration counts per rhs.
 template <class Op, class Prec>
 static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, double tol, const double2 *r0,
-                                   double2 *x, double2 *V, double2 *Z, const std::vector<double> &bnorm, Op op,
+                                   double2 *x, Basis &V, Basis *Z, const std::vector<double> &bnorm, Op op,
                                    Prec prec, bool flexible, std::vector<double> &rel_est) {
     const int64_t ldv = N * nrhs;
     Gmres G(nrhs, maxit);
@@ -280,13 +310,16 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
         c.dfree(cdev);
         return iters;
     }
-    scale(c, r0, inv, V, N, nrhs, sdev);
+    V.reserve(2, 0);
+    scale(c, r0, inv, V.vec(0), N, nrhs, sdev);
     int j = 0;
     for (; j < maxit; ++j) {
-        double2 *vj = V + (int64_t)j * ldv;
-        double2 *w = V + (int64_t)(j + 1) * ldv;
+        V.reserve(j + 2, j + 1);
+        double2 *vj = V.vec(j);
+        double2 *w = V.vec(j + 1);
         if (flexible) {
-            double2 *zj = Z + (int64_t)j * ldv;
+            Z->reserve(j + 1, j);
+            double2 *zj = Z->vec(j);
             prec(vj, zj);
             op(zj, w);
         } else {
@@ -299,8 +332,8 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
         const int64_t nh = (int64_t)nrhs * nv;
         for (int pass = 0; pass < 2; ++pass) {
             double2 *hc = cdev + pass * nh;
-            D.launch(V, ldv, nv, w, hc);
-            hipLaunchKernelGGL(caxpy_many_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, V, ldv,
+            D.launch(V.p, ldv, nv, w, hc);
+            hipLaunchKernelGGL(caxpy_many_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, V.p, ldv,
                                nv, hc, -1.0, w, N, nrhs);
             AXS_HIP(hipGetLastError());
         }
@@ -339,7 +372,7 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
         }
     }
     // x += basis * y, per rhs with its own k
-    const double2 *basis = flexible ? Z : V;
+    const double2 *basis = flexible ? Z->p : V.p;
     int kmax = 0;
     for (int cc = 0; cc < nrhs; ++cc) {
         iters[cc] = G.done_at[cc] < 0 ? j : G.done_at[cc];
@@ -424,14 +457,13 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
     std::vector<double> est;
     std::vector<int> outer;
     std::vector<int> inner_total(nrhs, 0);
-    double2 *V = (double2 *)c.dalloc((size_t)(max_iters + 1) * vb);
+    Basis V(c, vb, max_iters + 1);
     if (mode == AXS_SOLVE_FP64) {
         auto none = [&](const double2 *, double2 *) {};
         outer = gmres_core(c, N, nrhs, max_iters, tol, r, x, V, nullptr, bn, op64, none, false, est);
     } else {
         const int max_inner = 60;
-        double2 *Z = (double2 *)c.dalloc((size_t)max_iters * vb);
-        double2 *Vi = (double2 *)c.dalloc((size_t)(max_inner + 1) * vb);
+        Basis Z(c, vb, max_iters), Vi(c, vb, max_inner + 1);
         auto prec = [&](const double2 *v, double2 *z) {
             // inner GMRES on the FP32 operator, zero initial guess, rhs v; it only
             // has to reduce the outer residual by the factor still missing
@@ -448,11 +480,8 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
             std::vector<int> it = gmres_core(c, N, nrhs, max_inner, tin, v, z, Vi, nullptr, vn, op32, none, false, ie);
             for (int cc = 0; cc < nrhs; ++cc) inner_total[cc] += it[cc];
         };
-        outer = gmres_core(c, N, nrhs, max_iters, tol, r, x, V, Z, bn, op64, prec, true, est);
-        c.dfree(Z);
-        c.dfree(Vi);
+        outer = gmres_core(c, N, nrhs, max_iters, tol, r, x, V, &Z, bn, op64, prec, true, est);
     }
-    c.dfree(V);
     std::vector<double> relv = est;
     if (certify) {
         // explicit FP64 residual of the returned solution
