@@ -136,6 +136,10 @@ def main():
                     help="the paper's cavity experiment (Sec. 6.2, Example 4) on 8 bowls 2 and 5 wavelengths "
                          "across: FP64 GMRES to 1e-9 with and without the preconditioner (at most 300 "
                          "iterations), field error at 10 exterior targets")
+    ap.add_argument("--shard", action="store_true",
+                    help="one GPU's share of the 64-body inter-body sum (16 rhs): the bodies split into 8 "
+                         "contiguous groups, equal in body count or balanced by pair count; each group's rows "
+                         "against all sources, FP32 and FP64, next to the full sum")
     ap.add_argument("--uniform-sources", action="store_true",
                     help="with --laplace-table: interior point sources uniform in each body's volume")
     ap.add_argument("--modal-probe", action="store_true",
@@ -177,6 +181,8 @@ def main():
         return laplace_table(args)
     if args.cavities:
         return cavities(args)
+    if args.shard:
+        return shard(args)
     if args.skeleton:
         return skeleton(args)
 
@@ -692,6 +698,83 @@ def cavities(args):
            "unit": "rows", "n_gpus": 1, "data": "synthetic",
            "config": {"workload": "cavities8", "sources": "one inside each wall (seed 11)", "tol": 1e-9},
            "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def shard(args, n_gpus=8):
+    """The inter-body sum of the 64-body workload (16 rhs) cut by block rows as
+    it would be over n_gpus GPUs: each share is a contiguous group of bodies
+    whose targets meet every source (axs_set_target_bodies).  Two cuts: equal
+    body counts, and contiguous groups balanced by pairs n_b (N - n_b).  Each
+    share is timed on this GPU with HIP events; the largest share bounds the
+    sharded sum (before the all-gather of the staged densities)."""
+    import numpy as np
+    import torch
+    from paper_1406_0236_amd import FP32, FP64, Context
+    from workloads import configs
+    wl = configs.mixed_many()
+    ctx = Context(0).add_workload(wl)
+    ctx.precompute_scattering()
+    n = np.array([b.n_nodes for b in wl.bodies], dtype=np.int64)
+    N = int(n.sum())
+    pairs = n * (N - n)
+    B = len(n)
+    equal = [(i * B // n_gpus, (i + 1) * B // n_gpus) for i in range(n_gpus)]
+    # contiguous groups with the smallest largest pair count: bisection on the
+    # bound L, greedy filling decides whether n_gpus groups suffice
+
+    def greedy(L):
+        cuts, acc = [0], 0
+        for i, p_ in enumerate(pairs):
+            if acc + p_ > L and acc > 0:
+                cuts.append(i)
+                acc = 0
+            acc += p_
+        return cuts + [B]
+
+    lo_, hi_ = float(pairs.max()), float(pairs.sum())
+    for _ in range(60):
+        mid = 0.5 * (lo_ + hi_)
+        if len(greedy(mid)) - 1 <= n_gpus:
+            hi_ = mid
+        else:
+            lo_ = mid
+    cuts = greedy(hi_)
+    while len(cuts) - 1 < n_gpus:   # split the largest group until there are n_gpus
+        k = max(range(len(cuts) - 1), key=lambda g: cuts[g + 1] - cuts[g])
+        cuts.insert(k + 1, (cuts[k] + cuts[k + 1]) // 2)
+    balanced = [(cuts[i], cuts[i + 1]) for i in range(n_gpus)]
+    rng = np.random.default_rng(1)
+    x = torch.from_numpy(rng.standard_normal((16, N)) + 1j * rng.standard_normal((16, N))).to("cuda:0")
+    ctx.set_timing(True)
+
+    def timed():
+        ctx.apply_interbody(x, prec)
+        return ctx.last_timing()["interbody"]
+
+    out_prec = {}
+    for prec, name in ((FP32, "fp32"), (FP64, "fp64")):
+        full = timed()
+        res = {"full_ms": full, "launch_shape": list(ctx.interbody_launch_shape(prec, 16))}
+        for cut_name, cut in (("equal_bodies", equal), ("balanced_pairs", balanced)):
+            ms = []
+            for b0, b1 in cut:
+                ctx.set_target_bodies(b0, b1 - b0)
+                ms.append(timed())
+            ctx.set_target_bodies(0, 0)
+            share = [float(pairs[b0:b1].sum() / pairs.sum()) for b0, b1 in cut]
+            res[cut_name] = {"bodies": cut, "ms": ms, "pair_share": share, "max_ms": max(ms),
+                             "ideal_ms": full / n_gpus, "efficiency": full / n_gpus / max(ms)}
+            log(f"{name} {cut_name}: full {full:.1f} ms, shares {[round(v, 1) for v in ms]} ms, "
+                f"largest {max(ms):.1f} ms vs ideal {full / n_gpus:.1f} ms")
+        out_prec[name] = res
+    ctx.set_timing(False)
+    ctx.close()
+    q_bytes = 16 * N * 8
+    out = {"metric": f"inter-body sum of one GPU's share of the block rows ({n_gpus} shares), 16 rhs",
+           "unit": "ms", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": wl.name, "N": N, "bodies": B, "nrhs": 16, "shares": n_gpus},
+           "allgather_bytes_per_application_fp32": q_bytes, "results": out_prec}
     print(json.dumps(out), flush=True)
 
 

@@ -225,6 +225,20 @@ axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant,
  * AXS_EINVAL if the configured shape does not fit the context. */
 axs_status axs_interbody_launch_shape(axs_ctx *ctx, int precision, int nrhs, int *out);
 
+/* One GPU's share of the block rows (Sec. 3.3: the rows of A_pq for the bodies
+ * p a GPU owns, against the sources of every other body q).  After
+ * axs_set_target_bodies(ctx, first, count), axs_apply_interbody computes the
+ * inter-body sum only for the targets of bodies [first, first + count), with
+ * all sources as before (every other body, own body excluded); the rows of the
+ * other bodies in its output are set to zero.  The default number of source
+ * splits is chosen for the share's own tiles (so a share fills the GPU as the
+ * full sum does); with the same launch shape set explicitly
+ * (axs_set_interbody_config) its rows equal the full sum's bit for bit.  While
+ * a range is set, the operators and solves that need every
+ * row (axs_apply_matvec, axs_solve, axs_solve_skeleton) return AXS_ESTATE.
+ * (0, 0) restores every body.  AXS_EINVAL for an empty or out-of-range range. */
+axs_status axs_set_target_bodies(axs_ctx *ctx, int first_body, int count);
+
 /* ------------------------------------------------------------------------
  * Skeletonization (Sec. 5, eqs. ip0-ip6): each off-diagonal block is factored
  * as U_p A_pq(I_p, I_q) V_q^* by interpolative decompositions, and GMRES runs on

@@ -81,6 +81,7 @@ EXPORTS = {
                                                     ctypes.POINTER(ctypes.c_int)]),
     "axs_set_interbody_config": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                   ctypes.c_int, ctypes.c_int]),
+    "axs_set_target_bodies": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "axs_mlp_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "axs_mlp_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -323,6 +324,11 @@ class Context:
         targets_per_thread = groups of 16 targets per wavefront)."""
         self._check(self.lib.axs_set_interbody_config(self.h, int(precision), int(variant), int(targets_per_thread),
                                                       int(block), int(splits)))
+
+    def set_target_bodies(self, first_body=0, count=0):
+        """axs_set_target_bodies: the inter-body sum computes the rows of bodies
+        [first_body, first_body + count) only (one GPU's share); (0, 0) = all."""
+        self._check(self.lib.axs_set_target_bodies(self.h, int(first_body), int(count)))
 
     def interbody_launch_shape(self, precision, nrhs=1):
         """The resolved launch shape (variant, targets_per_thread, block, splits) for nrhs."""

@@ -475,9 +475,16 @@ static axs_status check_apply(Ctx &c, const void *a, const void *b, int nrhs, in
     return AXS_OK;
 }
 
+// the preconditioned operator and the solves need every row of the sum
+static void require_all_targets(const Ctx &c) {
+    AXS_REQUIRE(c.tgt_count < 0, AXS_ESTATE,
+                "a target-body range is set (axs_set_target_bodies): only axs_apply_interbody runs");
+}
+
 axs_status axs_apply_matvec(axs_ctx *ctx, const void *sigma, void *y, int nrhs, int precision) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         check_apply(c, sigma, y, nrhs, precision);
+        require_all_targets(c);
         axs::apply_operator(c, sigma, y, nrhs, precision);
         return AXS_OK;
     });
@@ -514,6 +521,7 @@ axs_status axs_solve(axs_ctx *ctx, const void *incident, const void *sigma0, voi
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         check_apply(c, incident, sigma, nrhs, AXS_FP64);
         if (sigma0) check_apply(c, sigma0, sigma, nrhs, AXS_FP64);
+        require_all_targets(c);
         const int base = mode & ~(AXS_SOLVE_CERTIFY | AXS_SOLVE_UNPRECONDITIONED);
         AXS_REQUIRE(base == AXS_SOLVE_FP64 || base == AXS_SOLVE_MIXED, AXS_EINVAL, "bad solve mode");
         AXS_REQUIRE(!(mode & AXS_SOLVE_UNPRECONDITIONED) || base == AXS_SOLVE_FP64, AXS_EINVAL,
@@ -617,6 +625,22 @@ axs_status axs_set_interbody_config(axs_ctx *ctx, int precision, int variant, in
     });
 }
 
+axs_status axs_set_target_bodies(axs_ctx *ctx, int first_body, int count) {
+    return guarded(ctx, [&](Ctx &c) -> axs_status {
+        const int nb = (int)c.bodies.size();
+        if (first_body == 0 && count == 0) {
+            c.tgt_first = 0;
+            c.tgt_count = -1;
+            return AXS_OK;
+        }
+        AXS_REQUIRE(first_body >= 0 && count >= 1 && (int64_t)first_body + count <= nb, AXS_EINVAL,
+                    "target bodies must be a non-empty range of built bodies, or (0, 0) for all");
+        c.tgt_first = first_body;
+        c.tgt_count = count;
+        return AXS_OK;
+    });
+}
+
 axs_status axs_skeletonize(axs_ctx *ctx, double eps, double proxy_factor, int64_t *out_nskel) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         skeletonize(c, eps, proxy_factor);
@@ -628,6 +652,7 @@ axs_status axs_skeletonize(axs_ctx *ctx, double eps, double proxy_factor, int64_
 axs_status axs_skeleton_rank(axs_ctx *ctx, int body_id, int *rings, int *contour_nodes) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         AXS_REQUIRE(c.skel, AXS_ESTATE, "call axs_skeletonize first");
+        require_all_targets(c);
         AXS_REQUIRE(rings && contour_nodes, AXS_EINVAL, "null output");
         AXS_REQUIRE(body_id >= 0 && body_id < (int)c.bodies.size(), AXS_EINVAL, "bad body id");
         const int sh = c.bodies[body_id].shape;

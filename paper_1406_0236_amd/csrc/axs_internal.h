@@ -143,13 +143,16 @@ struct Ctx {
     // so that alternating single and batched calls do not rebuild them
     IBWork *ib_work[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     int ib_nwork[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    int ib_key[2][3][4] = {};
+    int ib_key[2][3][6] = {};   // launch shape and target range of the cached table
 
     // launch configuration of the inter-body sum (0 = library default)
     int ib_variant[2] = {0, 0};   // 1 = point sources, 2 = azimuthal rings, 3 = MFMA, 4 = MFMA + FP16 MAC (FP32)
     int ib_tpt[2] = {0, 0};       // targets per thread [fp64, fp32]
     int ib_block[2] = {0, 0};
     int ib_splits[2] = {0, 0};
+    // target rows of the inter-body sum: bodies [tgt_first, tgt_first +
+    // tgt_count), tgt_count < 0 = every body (axs_set_target_bodies)
+    int tgt_first = 0, tgt_count = -1;
 
     // ring tables (one ring = one contour node of one body = its N_F azimuthal nodes)
     int nrings = 0;

@@ -1098,9 +1098,15 @@ __global__ void stage_density_kernel(const double2 *__restrict__ sigma, const do
 
 template <typename R>
 __global__ void reduce_parts_kernel(const typename C2T<R>::T *__restrict__ part, int splits,
-                                    int64_t total, int add, double2 *__restrict__ y) {
+                                    int64_t total, int add, double2 *__restrict__ y, int64_t N, int64_t row0,
+                                    int64_t row1) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
+    const int64_t row = i % N;
+    if (row < row0 || row >= row1) {   // rows of bodies outside the target range
+        if (!add) y[i] = make_double2(0.0, 0.0);
+        return;
+    }
     double re = 0, im = 0;
     if (add) {
         re = y[i].x;
@@ -1160,8 +1166,10 @@ static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
         // enough blocks to fill 256 CUs several times over; the FP32 ring order
         // (8 resident blocks per CU) takes 16K so that the last, partly filled
         // round of blocks is a small share of the launch
-        int64_t tiles = 0;
-        for (auto &b : c.bodies) tiles += ceil_div(b.n, (int64_t)ib_tile(s));
+        int64_t tiles = 0;   // of the target rows computed (all bodies, or the set range)
+        for (size_t bi = 0; bi < c.bodies.size(); ++bi)
+            if (c.tgt_count < 0 || ((int)bi >= c.tgt_first && (int)bi < c.tgt_first + c.tgt_count))
+                tiles += ceil_div(c.bodies[bi].n, (int64_t)ib_tile(s));
         const int64_t want = (prec == AXS_FP32 && s.variant == 2) ? 16384 : 4096;
         s.splits = 1;
         while (tiles * s.splits < want && s.splits < 64) s.splits *= 2;
@@ -1190,7 +1198,9 @@ static std::vector<IBWork> build_work(Ctx &c, int tile, int splits, Units units)
         const int64_t uoff = units == Units::rings ? c.ring_base[bi] : units == Units::blocks ? boff : b.offset;
         const int64_t un = units == Units::rings ? c.shapes[b.shape].NG : units == Units::blocks ? nbk : b.n;
         boff += nbk;
-        wb.push_back(WorkBody{b.offset, b.n, uoff, un});
+        // bodies outside the target range keep their sources, lose their targets
+        const bool own = c.tgt_count < 0 || ((int)bi >= c.tgt_first && (int)bi < c.tgt_first + c.tgt_count);
+        wb.push_back(WorkBody{b.offset, own ? b.n : 0, uoff, un});
     }
     const int64_t U = units == Units::rings ? c.nrings : units == Units::blocks ? c.nblk : c.N;
     return build_work_table(wb, U, tile, splits);
@@ -1445,7 +1455,8 @@ static void dispatch_ib(Ctx &c, const IBShape &s, const IBWork *work, int nwork,
 // cached work table [precision][wi] for a launch shape
 static const IBWork *get_work(Ctx &c, int pi, int wi, const IBShape &s, Units units, int &nwork) {
     int *key = c.ib_key[pi][wi];
-    if (!c.ib_work[pi][wi] || key[0] != s.tpt || key[1] != s.bs || key[2] != s.splits || key[3] != s.variant) {
+    if (!c.ib_work[pi][wi] || key[0] != s.tpt || key[1] != s.bs || key[2] != s.splits || key[3] != s.variant ||
+        key[4] != c.tgt_first || key[5] != c.tgt_count) {
         // work tables are cached per launch shape; rebuilt only when it changes
         std::vector<IBWork> work = build_work(c, ib_tile(s), s.splits, units);
         if (c.ib_work[pi][wi]) {
@@ -1459,6 +1470,8 @@ static const IBWork *get_work(Ctx &c, int pi, int wi, const IBShape &s, Units un
         key[1] = s.bs;
         key[2] = s.splits;
         key[3] = s.variant;
+        key[4] = c.tgt_first;
+        key[5] = c.tgt_count;
     }
     nwork = c.ib_nwork[pi][wi];
     return c.ib_work[pi][wi];
@@ -1549,12 +1562,20 @@ void interbody_reduce_to_c128(Ctx &c, void *y, int nrhs, int prec, bool add) {
     const int splits = interbody_splits(c, prec, nrhs);
     const int64_t total = (int64_t)nrhs * c.N;
     const int thr = 256;
+    int64_t row0 = 0, row1 = c.N;
+    if (c.tgt_count >= 0) {
+        const auto &f = c.bodies[c.tgt_first], &l = c.bodies[c.tgt_first + c.tgt_count - 1];
+        row0 = f.offset;
+        row1 = l.offset + l.n;
+    }
     if (prec == AXS_FP32)
         hipLaunchKernelGGL(reduce_parts_kernel<float>, dim3(ceil_div(total, thr)), dim3(thr), 0, c.stream,
-                           (const float2 *)c.scratch(WS_PART, 0), splits, total, add ? 1 : 0, (double2 *)y);
+                           (const float2 *)c.scratch(WS_PART, 0), splits, total, add ? 1 : 0, (double2 *)y, c.N,
+                           row0, row1);
     else
         hipLaunchKernelGGL(reduce_parts_kernel<double>, dim3(ceil_div(total, thr)), dim3(thr), 0, c.stream,
-                           (const double2 *)c.scratch(WS_PART, 0), splits, total, add ? 1 : 0, (double2 *)y);
+                           (const double2 *)c.scratch(WS_PART, 0), splits, total, add ? 1 : 0, (double2 *)y, c.N,
+                           row0, row1);
     AXS_HIP(hipGetLastError());
 }
 

@@ -590,6 +590,46 @@ def test_fp16_multiply_accumulate_negative_scale_exponent():
         ctx.close()
 
 
+def test_target_body_range_is_one_gpus_share(mixed):
+    """One GPU's share of the block rows (axs_set_target_bodies): the sum over
+    all sources for the targets of bodies 2-4 of the 8 mixed bodies, zero
+    elsewhere, in FP64 (3 rhs, ring order) and FP32 (16 rhs, FP16
+    multiply-accumulate; 5 rhs, ring order).  With the launch shape pinned the
+    rows equal the full sum's bit for bit; with the default shape (splits
+    chosen for the share) within rounding; the rows against the reference; the
+    solves refuse while the range is set; (0, 0) restores every row."""
+    from paper_1406_0236_amd import FP32, FP64, AxsError
+    wl, S, ctx = mixed
+    lo = sum(b.n_nodes for b in wl.bodies[:2])
+    hi = sum(b.n_nodes for b in wl.bodies[:5])
+    for prec, nrhs, seed in ((FP64, 3, 71), (FP32, 16, 72), (FP32, 5, 73)):
+        x = _dev(_rand(S.N, nrhs, seed))
+        full = ctx.apply_interbody(x, prec).cpu().numpy()
+        shape = ctx.interbody_launch_shape(prec, nrhs)
+        ctx.set_target_bodies(2, 3)
+        try:
+            part = ctx.apply_interbody(x, prec).cpu().numpy()
+            ctx.set_interbody_config(prec, *shape)
+            pinned = ctx.apply_interbody(x, prec).cpu().numpy()
+            ctx.set_interbody_config(prec, 0, 0, 0, 0)
+            with pytest.raises(AxsError, match="ESTATE"):
+                ctx.apply_matvec(x, prec)
+        finally:
+            ctx.set_target_bodies(0, 0)
+        assert np.array_equal(pinned[:, lo:hi], full[:, lo:hi]), (prec, nrhs)
+        assert rel(part[:, lo:hi], full[:, lo:hi]) < (1e-13 if prec == FP64 else 2e-6)
+        for y in (part, pinned):
+            assert np.all(y[:, :lo] == 0) and np.all(y[:, hi:] == 0)
+        ref = S.apply_B(x.cpu().numpy()[:2].T).T
+        e = rel(part[:2, lo:hi], ref[:, lo:hi])
+        print(f"prec {prec}, {nrhs} rhs, launch shape {ctx.interbody_launch_shape(prec, nrhs)}: "
+              f"rows of bodies 2-4 rel err {e:.2e}")
+        assert e < (1e-11 if prec == FP64 else 3e-5)
+    assert np.array_equal(ctx.apply_interbody(x, FP32).cpu().numpy(), ctx.apply_interbody(x, FP32).cpu().numpy())
+    with pytest.raises(AxsError, match="EINVAL"):
+        ctx.set_target_bodies(7, 2)
+
+
 def test_mfma_source_order_mixed_bodies_64_rhs(mixed):
     """Rotated spheroids and bowls, 8 bodies of three shapes, 64 right-hand sides
     (four MFMA-accumulated groups of 16); three columns against the reference."""
