@@ -133,9 +133,10 @@ def main():
                          "laplace_125_spheroids_table.txt): FP64 GMRES to 1e-9 with and without the "
                          "preconditioner at each (N_G, N_F), field error at 10 exterior targets")
     ap.add_argument("--cavities", action="store_true",
-                    help="the paper's cavity experiment (Sec. 6.2, Example 4) on 8 bowls 2 and 5 wavelengths "
-                         "across: FP64 GMRES to 1e-9 with and without the preconditioner (at most 300 "
-                         "iterations), field error at 10 exterior targets")
+                    help="the paper's cavity and ellipsoid experiments (Sec. 6.2, Examples 3 and 4): 8 bowls "
+                         "2 and 5 wavelengths across, 8 spheroids 10 wavelengths long; FP64 GMRES to 1e-9 with "
+                         "and without the preconditioner (at most 300 iterations), field error at 10 exterior "
+                         "targets")
     ap.add_argument("--shard", action="store_true",
                     help="one GPU's share of the 64-body inter-body sum (16 rhs): the bodies split into 8 "
                          "contiguous groups, equal in body count or balanced by pair count; each group's rows "
@@ -655,7 +656,8 @@ def laplace_table(args):
 def cavities(args):
     """8 bowl cavities with interior point sources: the paper's observation that
     for cavities the block-diagonal preconditioner is essential (without it
-    GMRES does not converge).  FP64 GMRES to 1e-9 with and without it, capped
+    GMRES does not converge); and 8 ellipsoids 10 wavelengths long, where it
+    halves the iteration count.  FP64 GMRES to 1e-9 with and without it, capped
     at 300 iterations, and the field error at 10 exterior targets against the
     exact field of the sources."""
     import numpy as np
@@ -663,8 +665,13 @@ def cavities(args):
     from paper_1406_0236_amd import SOLVE_FP64, SOLVE_MIXED, Context
     from workloads import configs
     rows = []
-    for kappa, ppu, M in ((2 * math.pi, 20.0 / math.pi, 25), (5 * math.pi, 50.0 / math.pi, 50)):
-        wl = configs.cavities_8(kappa=kappa, panels_per_unit=ppu, M=M)
+    cases = [configs.cavities_8(kappa=2 * math.pi, panels_per_unit=20.0 / math.pi, M=25),
+             configs.cavities_8(kappa=5 * math.pi, panels_per_unit=50.0 / math.pi, M=50),
+             # the paper's Example 3: 8 ellipsoids 10 wavelengths long, where the
+             # preconditioner halves the iterations
+             configs.ellipsoids_8(n_panels=10, M=50), configs.ellipsoids_8(n_panels=20, M=100)]
+    for wl in cases:
+        kappa, M = wl.kappa, wl.bodies[0].M
         ctx = Context(0).add_workload(wl)
         torch.cuda.synchronize()
         t0 = time.time()
@@ -694,9 +701,10 @@ def cavities(args):
             log(f"{wl.name} N={wl.N}: {name} {row[name]}")
         ctx.close()
         rows.append(row)
-    out = {"metric": "GMRES iterations to 1e-9 on 8 cavities with / without the preconditioner",
+    out = {"metric": "GMRES iterations to 1e-9 on 8 cavities and 8 ellipsoids with / without the preconditioner",
            "unit": "rows", "n_gpus": 1, "data": "synthetic",
-           "config": {"workload": "cavities8", "sources": "one inside each wall (seed 11)", "tol": 1e-9},
+           "config": {"workload": "cavities8, ellipsoids8", "sources": "one inside each body (seed 11)",
+                      "tol": 1e-9},
            "rows": rows}
     print(json.dumps(out), flush=True)
 

@@ -155,6 +155,18 @@ def laplace_small() -> Workload:
                     "kappa = 0: sphere, spheroid, bowl")
 
 
+def ellipsoids_8(kappa=10 * math.pi, n_panels=10, p=10, M=50) -> Workload:
+    """8 prolate spheroids (axes 2 x 1 x 1, so 10 wavelengths long at kappa =
+    10 pi) on a 2 x 2 x 2 lattice of spacing 2.05, long axes along z: the box
+    is [0, 4.05] along z and neighbouring tips are 0.05 apart; eta = kappa."""
+    c = geo.prolate(0.5, 1.0, n_panels, p)
+    offs = 1.0 + 2.05 * np.arange(2)
+    bodies = [BodySpec(c, np.array(xyz, dtype=np.float64), np.eye(3), M)
+              for xyz in itertools.product(offs, offs, offs)]
+    return Workload(f"ellipsoids8_k{kappa / math.pi:g}pi", kappa, kappa, bodies, np.array([[0.0, 0.0, 1.0]]),
+                    "8 spheroids 2 x 1 x 1, 2^3 lattice, spacing 2.05")
+
+
 def laplace_ellipsoids(per_side=5, spacing=2.05, n_panels=10, p=10, M=50, orient_seed=None) -> Workload:
     """125 prolate spheroids (axes 2 x 1 x 1) on a 5^3 lattice of spacing 2.05 inside
     [0, 10.2]^3; kappa = 0, eta = 1; 10 x 10 contour nodes x 101 azimuthal nodes =
