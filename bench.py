@@ -392,6 +392,7 @@ def learned(args):
         agg[mode] = {key: float(np.mean([r[mode][key] for r in rows]))
                      for key in ("zero_iters", "warm_iters", "zero_inner", "warm_inner", "zero_s", "warm_s")}
         agg[mode]["warm_used_fraction"] = float(np.sum([r[mode]["warm_used"] for r in rows]) / (8 * 64))
+    agg["guess_rel_residual_mean"] = float(np.mean([r["guess_rel_residual"]["mean"] for r in rows]))
     wl = wl_at(W.K_MAX)
     out = {
         "metric": "s to 1e-7 residual with learned warm start vs zero guess (64 rhs per solve)",

@@ -158,10 +158,19 @@ def evaluate(ws: WarmStart, workload_at, ks, dirs_per_k, tol=1e-7, log=None):
                 "warm_used": int(sum(x["used_warm_start"] for x in i1)),
                 "converged": bool(all(x["converged"] for x in i0 + i1)),
             }
-        # how good is the guess itself: FP64 residual of sigma0 relative to ||b||
+        # how good is the guess itself: the FP64 residual of sigma0 in the
+        # preconditioned system, b - (sigma0 + D^{-1} B sigma0) with b = -D^{-1} v,
+        # relative to ||b|| (1 for the zero guess); library applications,
+        # norms on the host
+        b = -ctx.apply_precond(v).cpu().numpy()
+        r = b - ctx.apply_matvec(sigma0).cpu().numpy()
+        rel = np.linalg.norm(r, axis=1) / np.linalg.norm(b, axis=1)
+        out["guess_rel_residual"] = {"mean": float(np.mean(rel)), "min": float(np.min(rel)),
+                                     "max": float(np.max(rel))}
         rows.append(out)
         if log:
-            log(f"held-out k = {k:.4f}: fp64 iters {out['fp64']['zero_iters']:.1f} -> {out['fp64']['warm_iters']:.1f}, "
+            log(f"held-out k = {k:.4f}: guess residual {out['guess_rel_residual']['mean']:.3f} (mean), "
+                f"fp64 iters {out['fp64']['zero_iters']:.1f} -> {out['fp64']['warm_iters']:.1f}, "
                 f"mixed {out['mixed']['zero_s']:.3f} s -> {out['mixed']['warm_s']:.3f} s "
                 f"(inner {out['mixed']['zero_inner']:.0f} -> {out['mixed']['warm_inner']:.0f})")
         ctx.close()
