@@ -4,8 +4,10 @@ complex128 tensors of shape (nrhs, N); PyTorch supplies device memory (through
 its caching allocator) and the stream."""
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -21,6 +23,27 @@ _STATUS = {0: "AXS_OK", 1: "AXS_NOT_CONVERGED", -1: "AXS_EINVAL", -2: "AXS_EHIP"
            -4: "AXS_ESTATE", -5: "AXS_ENONFINITE"}
 
 _lib = None
+
+# Live contexts and networks, in creation order (weak references).  They are
+# closed in reverse order at interpreter exit, while torch (whose allocator
+# frees their device memory) is still loaded: a network before the context it
+# lives on.
+_LIVE = []
+
+
+def _register(obj):
+    _LIVE.append(weakref.ref(obj))
+
+
+@atexit.register
+def _close_all():
+    for ref in reversed(_LIVE):
+        obj = ref()
+        if obj is not None:
+            try:
+                obj.close()
+            except Exception:
+                pass
 
 
 class AxsError(RuntimeError):
@@ -142,8 +165,13 @@ class Context:
                 except Exception:
                     return None
 
+            delete = torch.cuda.caching_allocator_delete
+
             def _free(p, _user):
-                torch.cuda.caching_allocator_delete(p)
+                try:
+                    delete(p)
+                except Exception:   # torch already torn down at interpreter exit
+                    pass
             alloc, free = ALLOC_FN(_alloc), FREE_FN(_free)
             self._cb = (alloc, free)
         h = ctypes.c_void_p()
@@ -151,6 +179,7 @@ class Context:
         if st != AXS_OK:
             raise AxsError(st, "axs_create failed")
         self.h = h
+        _register(self)
         self.N = 0
         self.max_nf = 0
         self.kappa = None
@@ -349,6 +378,7 @@ class Mlp:
         st = self.lib.axs_mlp_create(ctx.h, n_in, width, depth, n_out, ctypes.byref(h))
         ctx._check(st)
         self.h = h
+        _register(self)
         n = ctypes.c_int64()
         self.lib.axs_mlp_num_params(self.h, ctypes.byref(n))
         self.nparams = n.value
