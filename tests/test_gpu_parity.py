@@ -590,6 +590,52 @@ def test_fp16_multiply_accumulate_negative_scale_exponent():
         ctx.close()
 
 
+def test_lowest_mode_counts():
+    """Degenerate azimuthal resolutions: a sphere with M = 0 (one azimuthal node
+    per ring, the axisymmetric mode only), a sphere with M = 1 and a rotated
+    spheroid with M = 2, side by side (N = 180).  Modal matrices, the
+    preconditioned operator in FP64 and FP32 (1 and 17 rhs, every source
+    order the context allows) and a solve against the dense reference."""
+    from oracle.multibody import System
+    from paper_1406_0236_amd import FP32, FP64, SOLVE_FP64, SOLVE_MIXED
+    from workloads import configs, geometry as geo
+    wl = configs.Workload("low_modes", 2.0, 2.0, [
+        configs.BodySpec(geo.sphere(1.0, 2, 10), np.zeros(3), np.eye(3), 0),
+        configs.BodySpec(geo.sphere(0.7, 2, 10), np.array([2.5, 0.3, 0.0]), np.eye(3), 1),
+        configs.BodySpec(geo.prolate(0.4, 0.9, 2, 10), np.array([-0.4, 2.6, 0.5]),
+                         geo.random_rotation(np.random.default_rng(3)), 2)],
+        np.array([[0.0, 0.0, 1.0], [0.6, 0.0, 0.8]]))
+    assert [b.n_nodes for b in wl.bodies] == [20, 60, 100]
+    S = System.from_workload(wl)
+    ctx = _ctx_for(wl)
+    try:
+        for bid, body in enumerate(S.bodies):
+            sh = body.shape
+            e = rel(ctx.modal_matrices(bid, 1, sh.M, sh.NG).cpu().numpy(), sh.inverses())
+            assert e < 1e-9, (bid, e)
+        for nrhs, seed in ((1, 81), (17, 82)):
+            x = _rand(S.N, nrhs, seed)
+            ref = np.stack([S.matvec(x[c]) for c in range(nrhs)])
+            for prec, tol in ((FP64, 1e-11), (FP32, 3e-5)):
+                for variant in (0, 1, 2, 3):
+                    ctx.set_interbody_config(prec, variant, 0, 0, 0)
+                    y = ctx.apply_matvec(_dev(x), prec).cpu().numpy()
+                    e = rel(y, ref)
+                    assert e < tol, (nrhs, prec, variant, e)
+                ctx.set_interbody_config(prec, 0, 0, 0, 0)
+            print(f"{nrhs} rhs: operator rel err within tolerance for every source order")
+        v = S.plane_waves(wl.dirs)
+        x_ref = np.stack([S.solve_dense(v[:, c]) for c in range(2)])
+        vd = ctx.incident_plane_waves(wl.dirs)
+        for mode in (SOLVE_FP64, SOLVE_MIXED):
+            sol, info = ctx.solve(vd, mode=mode, tol=1e-11)
+            e = rel(sol.cpu().numpy(), x_ref)
+            print(f"mode {mode}: solve rel err {e:.2e}")
+            assert e < 1e-8
+    finally:
+        ctx.close()
+
+
 def test_target_body_range_is_one_gpus_share(mixed):
     """One GPU's share of the block rows (axs_set_target_bodies): the sum over
     all sources for the targets of bodies 2-4 of the 8 mixed bodies, zero
