@@ -590,6 +590,43 @@ def test_fp16_multiply_accumulate_negative_scale_exponent():
         ctx.close()
 
 
+def _low_modes_workload():
+    from workloads import configs, geometry as geo
+    return configs.Workload("low_modes", 2.0, 2.0, [
+        configs.BodySpec(geo.sphere(1.0, 2, 10), np.zeros(3), np.eye(3), 0),
+        configs.BodySpec(geo.sphere(0.7, 2, 10), np.array([2.5, 0.3, 0.0]), np.eye(3), 1),
+        configs.BodySpec(geo.prolate(0.4, 0.9, 2, 10), np.array([-0.4, 2.6, 0.5]),
+                         geo.random_rotation(np.random.default_rng(3)), 2)],
+        np.array([[0.0, 0.0, 1.0], [0.6, 0.0, 0.8]]))
+
+
+def test_maximum_rhs_count():
+    """The largest batch the ABI accepts, 4096 right-hand sides (256 groups of
+    16 in the MFMA order, with the FP16 multiply-accumulate in FP32), on a
+    small workload (N = 180): sampled columns of the preconditioned operator
+    against the reference, and 4097 refused."""
+    from oracle.multibody import System
+    from paper_1406_0236_amd import FP32, FP64, AxsError
+    wl = _low_modes_workload()
+    S = System.from_workload(wl)
+    ctx = _ctx_for(wl)
+    try:
+        x = _rand(S.N, 4096, 91)
+        cols = [0, 1, 1000, 2047, 4095]
+        ref = np.stack([S.matvec(x[c]) for c in cols])
+        xd = _dev(x)
+        for prec, tol in ((FP64, 1e-11), (FP32, 3e-5)):
+            y = ctx.apply_matvec(xd, prec).cpu().numpy()
+            e = rel(y[cols], ref)
+            print(f"prec {prec}, 4096 rhs, launch shape {ctx.interbody_launch_shape(prec, 4096)}: "
+                  f"sampled columns rel err {e:.2e}")
+            assert e < tol
+        with pytest.raises(AxsError, match="EINVAL"):
+            ctx.apply_matvec(_dev(_rand(S.N, 4097, 92)), FP64)
+    finally:
+        ctx.close()
+
+
 def test_lowest_mode_counts():
     """Degenerate azimuthal resolutions: a sphere with M = 0 (one azimuthal node
     per ring, the axisymmetric mode only), a sphere with M = 1 and a rotated
@@ -598,13 +635,7 @@ def test_lowest_mode_counts():
     order the context allows) and a solve against the dense reference."""
     from oracle.multibody import System
     from paper_1406_0236_amd import FP32, FP64, SOLVE_FP64, SOLVE_MIXED
-    from workloads import configs, geometry as geo
-    wl = configs.Workload("low_modes", 2.0, 2.0, [
-        configs.BodySpec(geo.sphere(1.0, 2, 10), np.zeros(3), np.eye(3), 0),
-        configs.BodySpec(geo.sphere(0.7, 2, 10), np.array([2.5, 0.3, 0.0]), np.eye(3), 1),
-        configs.BodySpec(geo.prolate(0.4, 0.9, 2, 10), np.array([-0.4, 2.6, 0.5]),
-                         geo.random_rotation(np.random.default_rng(3)), 2)],
-        np.array([[0.0, 0.0, 1.0], [0.6, 0.0, 0.8]]))
+    wl = _low_modes_workload()
     assert [b.n_nodes for b in wl.bodies] == [20, 60, 100]
     S = System.from_workload(wl)
     ctx = _ctx_for(wl)
