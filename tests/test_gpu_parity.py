@@ -299,6 +299,11 @@ def test_error_paths():
         ctx.build_body(s.rz, s.drz, s.gw, s.n_panels, s.p, 1.0, 1.0, 4, [5.0, 0, 0], np.eye(3))
     with pytest.raises(AxsError, match="EINVAL"):   # output overlaps input
         ctx.apply_matvec(y, FP64, out=y)
+    empty = torch.zeros((0, ctx.N), dtype=torch.complex128, device="cuda:0")
+    with pytest.raises(AxsError, match="EINVAL"):   # no right-hand sides
+        ctx.apply_matvec(empty, FP64)
+    with pytest.raises(AxsError, match="EINVAL"):
+        ctx.solve(empty)
     with pytest.raises(AxsError, match="EINVAL"):   # no such source order
         ctx.set_interbody_config(FP64, 5, 2, 256, 0)
     # a single body: no inter-body terms, the operator is the identity
