@@ -82,3 +82,68 @@ def test_wrong_jump_term_fails(jump):
     sh, c = _sphere()
     At = sh.modal_matrices() + (jump - 0.5) * np.eye(sh.NG)[None]
     assert _pin_error(At, sh, c) > 1e-3
+
+
+# --------------------------------------------------------------------------
+# the inter-body operator B: Green's identity (interior point sources, exact
+# exterior field) on the two-body system must break for a slip in B
+# --------------------------------------------------------------------------
+
+def _greens_error(S, wl):
+    from oracle.multibody import gmres
+    from workloads import configs
+    src = configs.point_sources(wl, seed=11)
+    amp = np.ones(len(src))
+    v = S.point_source_field(src, amp, S.x)
+    x, _, _ = gmres(S.matvec, S.rhs(v), tol=1e-10, max_iters=100)
+    xt = configs.exterior_targets(wl, 10, seed=12)
+    u = S.eval_field(x, xt)
+    ref = -S.point_source_field(src, amp, xt)
+    return float(np.max(np.abs(u - ref)) / np.max(np.abs(ref)))
+
+
+def _mutated_B(monkeypatch, S, kernel=None, weights=None, own_body=False):
+    """Route B through the numpy sum with one slip planted."""
+    import types
+    orig_kernel = type(S).kernel
+
+    def apply_B(self, sigma, rows=None):
+        sig = np.asarray(sigma, dtype=np.complex128)
+        vec = sig.ndim == 1
+        sig = sig[:, None] if vec else sig
+        w = self.w if weights is None else weights(self)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            G = (kernel or orig_kernel)(self, self.x, self.x, self.n)
+        G[~np.isfinite(G)] = 0.0
+        if not own_body:
+            G[self.body_of[:, None] == self.body_of[None, :]] = 0.0
+        out = G @ (w[:, None] * sig)
+        return out[:, 0] if vec else out
+    monkeypatch.setattr(S, "apply_B", types.MethodType(apply_B, S))
+
+
+def test_greens_identity_passes_with_the_numpy_sum(small_system, monkeypatch):
+    wl, S = small_system
+    _mutated_B(monkeypatch, S)
+    e = _greens_error(S, wl)
+    print(f"unmutated B: {e:.2e}")
+    assert e < 1e-6
+
+
+def test_inward_source_normals_in_B_fail(small_system, monkeypatch):
+    wl, S = small_system
+    orig = type(S).kernel
+    _mutated_B(monkeypatch, S, kernel=lambda self, xt, xs, ns: orig(self, xt, xs, -ns))
+    assert _greens_error(S, wl) > 1e-4
+
+
+def test_B_without_weights_fails(small_system, monkeypatch):
+    wl, S = small_system
+    _mutated_B(monkeypatch, S, weights=lambda self: np.ones_like(self.w))
+    assert _greens_error(S, wl) > 1e-4
+
+
+def test_B_with_the_own_body_fails(small_system, monkeypatch):
+    wl, S = small_system
+    _mutated_B(monkeypatch, S, own_body=True)
+    assert _greens_error(S, wl) > 1e-4
