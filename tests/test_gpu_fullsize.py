@@ -108,3 +108,21 @@ def test_fullsize_skeleton_solve(lattice):
           f"full residual {info[0]['rel_residual']:.2e}, vs uncompressed {d:.2e}")
     assert info[0]["rel_residual"] < 1e-7
     assert d < 1e-6
+
+
+def test_fullsize_reciprocity(lattice):
+    """At the benchmark's full size (27 spheres, N = 437,400, kappa = 4 pi): two
+    incident directions d1, d2 solved in one batched mixed solve to 1e-9;
+    reciprocity u_inf(x^ = -d2; d1) = u_inf(x^ = -d1; d2) of their far fields.
+    A property of the exact solution; the discrete one keeps it to 1e-9."""
+    from paper_1406_0236_amd import SOLVE_MIXED
+    wl, S, ctx = lattice
+    d = np.array([[0.0, 0.6, 0.8], [0.48, -0.6, 0.64]])
+    v = ctx.incident_plane_waves(d)
+    sol, info = ctx.solve(v, mode=SOLVE_MIXED, tol=1e-9)
+    assert all(i["converged"] for i in info)
+    u12 = ctx.far_field(sol[:1].contiguous(), -d[1:2]).cpu().numpy()[0, 0]
+    u21 = ctx.far_field(sol[1:2].contiguous(), -d[0:1]).cpu().numpy()[0, 0]
+    e = abs(u12 - u21) / max(abs(u12), abs(u21))
+    print(f"full size reciprocity: {e:.2e} ({info[0]['iterations']} outer, {info[0]['inner_iterations']} inner)")
+    assert e < 1e-7   # seen 1.1e-9
