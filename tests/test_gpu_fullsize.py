@@ -126,3 +126,31 @@ def test_fullsize_reciprocity(lattice):
     e = abs(u12 - u21) / max(abs(u12), abs(u21))
     print(f"full size reciprocity: {e:.2e} ({info[0]['iterations']} outer, {info[0]['inner_iterations']} inner)")
     assert e < 1e-7   # seen 1.1e-9
+
+
+def test_fullsize_greens_identity():
+    """The paper's accuracy protocol (Sec. 6) at the benchmark's full size: one
+    point source inside each of the 27 spheres, the incident field their
+    field, a mixed solve to 1e-9, and the scattered field at 10 exterior
+    targets against the exact one (minus the sources' field)."""
+    import math
+    from paper_1406_0236_amd import SOLVE_MIXED, Context
+    from workloads import configs
+    wl = configs.sphere_lattice()
+    ctx = Context(0).add_workload(wl)
+    try:
+        ctx.precompute_scattering()
+        src = configs.point_sources(wl, seed=11)
+        amp = np.random.default_rng(12).standard_normal(len(src))
+        v = ctx.incident_point_sources(src, amp)
+        sol, info = ctx.solve(v, mode=SOLVE_MIXED, tol=1e-9)
+        assert info[0]["converged"]
+        xt = configs.exterior_targets(wl, 10, seed=12)
+        u = ctx.eval_field(sol, xt).cpu().numpy()[0]
+        dist = np.linalg.norm(xt[:, None, :] - src[None, :, :], axis=-1)
+        exact = -(np.exp(1j * wl.kappa * dist) / (4.0 * math.pi * dist)) @ amp
+        e = float(np.max(np.abs(u - exact)) / np.max(np.abs(exact)))
+        print(f"full size Green's identity: E_inf {e:.2e}")
+        assert e < 1e-8   # seen 4.0e-10
+    finally:
+        ctx.close()
