@@ -303,6 +303,19 @@ axs_status axs_mlp_gradient(axs_mlp *mlp, const float *X, const float *T, int ba
 /* one Adam step on the batch (bias-corrected moments) */
 axs_status axs_mlp_adam_step(axs_mlp *mlp, const float *X, const float *T, int batch, double lr,
                              double beta1, double beta2, double eps, double *loss);
+/* `steps` Adam steps over sample rows held on the device: step s gathers rows
+ * order[s batch .. (s+1) batch - 1] of X (device float [rows][n_in]) and of T
+ * (device float [rows][n_out]) into the network's own batch buffers and takes
+ * the step of axs_mlp_adam_step with learning rate lr[s].  order (host int32
+ * [steps x batch], each in [0, rows)) and lr (host double [steps], each > 0)
+ * are checked and copied before the first step is queued, so the caller may
+ * reuse them on return; a bad entry gives AXS_EINVAL with nothing queued.
+ * Synchronises ctx's stream once before the copy; loss (may be NULL, else
+ * synchronises again) receives the last step's loss.  The result equals the
+ * same steps taken one by one through axs_mlp_adam_step on gathered batches. */
+axs_status axs_mlp_train_epoch(axs_mlp *mlp, const float *X, const float *T, int64_t rows, const int32_t *order,
+                               int batch, int steps, const double *lr, double beta1, double beta2, double eps,
+                               double *loss);
 
 /* Floats per right-hand side of the mode encoding below:
  * 2 * (2 m_max + 1) * sum over bodies of N_G. */

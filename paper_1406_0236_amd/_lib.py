@@ -117,6 +117,10 @@ EXPORTS = {
     "axs_mlp_adam_step": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            ctypes.POINTER(ctypes.c_double)]),
+    "axs_mlp_train_epoch": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_double)]),
     "axs_warm_start_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
     "axs_modes_from_density": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                                 ctypes.c_int, ctypes.c_void_p]),
@@ -429,6 +433,20 @@ class Mlp:
         loss = ctypes.c_double()
         self.ctx._check(self.lib.axs_mlp_adam_step(self.h, px, pt, b, float(lr), float(beta1), float(beta2),
                                                    float(eps), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def train_epoch(self, X, T, order, batch, lrs, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=True):
+        """len(lrs) Adam steps; step s trains on rows order[s*batch:(s+1)*batch] of X and T."""
+        px, rows = self._f32(X, self.sizes[0])
+        pt, rows_t = self._f32(T, self.sizes[-1])
+        assert rows == rows_t
+        o = np.ascontiguousarray(order, dtype=np.int32)
+        lr = np.ascontiguousarray(lrs, dtype=np.float64)
+        assert o.size == batch * lr.size
+        loss = ctypes.c_double()
+        self.ctx._check(self.lib.axs_mlp_train_epoch(self.h, px, pt, rows, _ptr(o), int(batch), int(lr.size),
+                                                     _ptr(lr), float(beta1), float(beta2), float(eps),
+                                                     ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 
 

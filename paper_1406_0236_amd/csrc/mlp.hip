@@ -31,7 +31,10 @@ struct Mlp {
     int cap_batch = 0;
     std::vector<float *> H, Z;       // H[k]: input to layer k (B x sizes[k]); Z[k]: pre-activation (B x sizes[k+1])
     float *G0 = nullptr, *G1 = nullptr, *loss_part = nullptr;
+    float *Tb = nullptr;             // gathered targets of one batch (B x n_out)
     double *loss_dev = nullptr;
+    int32_t *order = nullptr;        // row order of one epoch (device copy)
+    int64_t cap_order = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -177,6 +180,17 @@ __global__ void sum_parts_kernel(const float *__restrict__ part, int n, double s
     }
 }
 
+// dst[r][:] = src[idx[r]][:] for r < batch; idx already checked against the source rows
+__global__ __launch_bounds__(256) void gather_rows_kernel(const float *__restrict__ src, int ncol,
+                                                          const int32_t *__restrict__ idx, int batch,
+                                                          float *__restrict__ dst) {
+    const int64_t n = (int64_t)batch * ncol;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
+        const int64_t r = t / ncol, col = t - r * ncol;
+        dst[t] = src[(int64_t)idx[r] * ncol + col];
+    }
+}
+
 __global__ void adam_kernel(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
                             const float *__restrict__ g, int64_t n, float lr, float b1, float b2, float eps,
                             float c1, float c2) {
@@ -260,6 +274,7 @@ static void ensure_batch(Mlp &n, int B) {
     for (auto *p : n.Z) c.dfree(p);
     c.dfree(n.G0);
     c.dfree(n.G1);
+    c.dfree(n.Tb);
     const int L = (int)n.sizes.size() - 1;
     n.H.assign(L + 1, nullptr);
     n.Z.assign(L, nullptr);
@@ -269,20 +284,44 @@ static void ensure_batch(Mlp &n, int B) {
     for (int k = 0; k < L; ++k) n.Z[k] = (float *)c.dalloc((size_t)B * n.sizes[k + 1] * sizeof(float));
     n.G0 = (float *)c.dalloc((size_t)B * wmax * sizeof(float));
     n.G1 = (float *)c.dalloc((size_t)B * wmax * sizeof(float));
+    n.Tb = (float *)c.dalloc((size_t)B * n.sizes[L] * sizeof(float));
     n.cap_batch = B;
+}
+
+// forward pass from the input already in H[0]; H[L] = output
+static void mlp_forward_h0(Mlp &n, int B) {
+    Ctx &c = *n.ctx;
+    const int L = (int)n.sizes.size() - 1;
+    for (int k = 0; k < L; ++k) {
+        const int a = n.sizes[k], b = n.sizes[k + 1];
+        gemm<false, false>(c, B, b, a, n.H[k], a, n.p + n.woff[k], b, n.p + n.boff[k], k < L - 1 ? 1 : 0, n.Z[k],
+                           n.H[k + 1], b);
+    }
 }
 
 // forward pass: H[0] = X (copied), H[L] = output
 static void mlp_forward(Mlp &n, const float *X, int B) {
     Ctx &c = *n.ctx;
     ensure_batch(n, B);
-    const int L = (int)n.sizes.size() - 1;
     AXS_HIP(hipMemcpyAsync(n.H[0], X, (size_t)B * n.sizes[0] * sizeof(float), hipMemcpyDeviceToDevice, c.stream));
-    for (int k = 0; k < L; ++k) {
-        const int a = n.sizes[k], b = n.sizes[k + 1];
-        gemm<false, false>(c, B, b, a, n.H[k], a, n.p + n.woff[k], b, n.p + n.boff[k], k < L - 1 ? 1 : 0, n.Z[k],
-                           n.H[k + 1], b);
-    }
+    mlp_forward_h0(n, B);
+}
+
+// bias-corrected Adam update of the packed parameters from the gradient in n.g
+static void adam_update(Mlp &n, double lr, double b1, double b2, double eps) {
+    Ctx &c = *n.ctx;
+    n.step += 1;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)n.step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)n.step)));
+    hipLaunchKernelGGL(adam_kernel, dim3(ceil_div(n.nparams, 256)), dim3(256), 0, c.stream, n.p, n.m, n.v, n.g,
+                       n.nparams, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2);
+    AXS_HIP(hipGetLastError());
+}
+
+static void gather_rows(Ctx &c, const float *src, int ncol, const int32_t *idx, int batch, float *dst) {
+    const int nblk = (int)std::min<int64_t>(4096, ceil_div((int64_t)batch * ncol, 256));
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(nblk), dim3(256), 0, c.stream, src, ncol, idx, batch, dst);
+    AXS_HIP(hipGetLastError());
 }
 
 // loss and gradient of the packed parameters into n.g
@@ -393,7 +432,7 @@ axs_status axs_mlp_destroy(axs_mlp *h) {
         for (auto *p : n.H) n.ctx->dfree(p);
         for (auto *p : n.Z) n.ctx->dfree(p);
         for (void *p : {(void *)n.p, (void *)n.m, (void *)n.v, (void *)n.g, (void *)n.G0, (void *)n.G1,
-                        (void *)n.loss_part, (void *)n.loss_dev})
+                        (void *)n.Tb, (void *)n.loss_part, (void *)n.loss_dev, (void *)n.order})
             n.ctx->dfree(p);
     }
     delete h;
@@ -460,12 +499,48 @@ axs_status axs_mlp_adam_step(axs_mlp *h, const float *X, const float *T, int bat
                     AXS_EINVAL, "bad arguments");
         axs::mlp_forward(n, X, batch);
         axs::mlp_backward(n, T, batch);
-        n.step += 1;
-        const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)n.step)));
-        const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)n.step)));
-        hipLaunchKernelGGL(axs::adam_kernel, dim3(axs::ceil_div(n.nparams, 256)), dim3(256), 0, c.stream, n.p, n.m,
-                           n.v, n.g, n.nparams, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2);
-        AXS_HIP(hipGetLastError());
+        axs::adam_update(n, lr, b1, b2, eps);
+        if (loss) {
+            AXS_HIP(hipMemcpyAsync(loss, n.loss_dev, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            AXS_HIP(hipStreamSynchronize(c.stream));
+        }
+        return AXS_OK;
+    });
+}
+
+axs_status axs_mlp_train_epoch(axs_mlp *h, const float *X, const float *T, int64_t rows, const int32_t *order,
+                               int batch, int steps, const double *lr, double b1, double b2, double eps,
+                               double *loss) {
+    return mlp_guarded(h, [&](Mlp &n, Ctx &c) -> axs_status {
+        AXS_REQUIRE(X && T && order && lr && rows >= 1 && batch >= 1 && steps >= 1 && b1 >= 0 && b1 < 1 &&
+                        b2 >= 0 && b2 < 1 && eps > 0,
+                    AXS_EINVAL, "bad arguments");
+        AXS_REQUIRE(rows <= INT32_MAX, AXS_EINVAL, "more than 2^31 - 1 sample rows");
+        const int64_t total = (int64_t)batch * steps;
+        AXS_REQUIRE(total <= INT32_MAX, AXS_EINVAL, "batch x steps exceeds 2^31 - 1");
+        for (int s = 0; s < steps; ++s) AXS_REQUIRE(lr[s] > 0, AXS_EINVAL, "learning rates must be positive");
+        for (int64_t i = 0; i < total; ++i)
+            AXS_REQUIRE(order[i] >= 0 && order[i] < rows, AXS_EINVAL, "row index out of range");
+        if (total > n.cap_order) {
+            AXS_HIP(hipStreamSynchronize(c.stream));
+            c.dfree(n.order);
+            n.order = nullptr;
+            n.order = (int32_t *)c.dalloc((size_t)total * sizeof(int32_t));
+            n.cap_order = total;
+        }
+        // the host array may be reused once this returns: copy it before the first step is queued
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        AXS_HIP(hipMemcpy(n.order, order, (size_t)total * sizeof(int32_t), hipMemcpyHostToDevice));
+        axs::ensure_batch(n, batch);
+        const int L = (int)n.sizes.size() - 1;
+        for (int s = 0; s < steps; ++s) {
+            const int32_t *idx = n.order + (int64_t)s * batch;
+            axs::gather_rows(c, X, n.sizes[0], idx, batch, n.H[0]);
+            axs::gather_rows(c, T, n.sizes[L], idx, batch, n.Tb);
+            axs::mlp_forward_h0(n, batch);
+            axs::mlp_backward(n, n.Tb, batch);
+            axs::adam_update(n, lr[s], b1, b2, eps);
+        }
         if (loss) {
             AXS_HIP(hipMemcpyAsync(loss, n.loss_dev, sizeof(double), hipMemcpyDeviceToHost, c.stream));
             AXS_HIP(hipStreamSynchronize(c.stream));

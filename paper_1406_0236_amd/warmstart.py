@@ -96,22 +96,19 @@ class WarmStart:
         Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev)
         Yd = torch.from_numpy(np.ascontiguousarray(Y / scale, dtype=np.float32)).to(dev)
         S = Xd.shape[0]
+        batch = min(batch, S)
         rng = np.random.default_rng(seed)
         steps_per_epoch = max(1, S // batch)
         total = epochs * steps_per_epoch
         t0 = time.time()
         step = 0
         for ep in range(epochs):
-            perm = torch.from_numpy(rng.permutation(S)).to(dev)
-            for s in range(steps_per_epoch):
-                idx = perm[s * batch:(s + 1) * batch]
-                xb = Xd.index_select(0, idx).contiguous()
-                yb = Yd.index_select(0, idx).contiguous()
-                # cosine decay from lr to lr_final
-                a = lr_final + 0.5 * (lr - lr_final) * (1 + math.cos(math.pi * step / max(1, total - 1)))
-                last = s == steps_per_epoch - 1
-                loss = self.mlp.adam_step(xb, yb, a, want_loss=last)
-                step += 1
+            perm = rng.permutation(S)[:steps_per_epoch * batch]
+            # cosine decay from lr to lr_final over all steps
+            t = np.arange(step, step + steps_per_epoch, dtype=np.float64)
+            lrs = lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * t / max(1, total - 1)))
+            loss = self.mlp.train_epoch(Xd, Yd, perm, batch, lrs)
+            step += steps_per_epoch
             self.history.append(loss)
             if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
                 log(f"epoch {ep + 1}/{epochs}: loss {loss:.4e} (scaled targets), {time.time() - t0:.1f} s")

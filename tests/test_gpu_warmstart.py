@@ -74,6 +74,59 @@ def test_adam_steps_match_reference(dev_ctx):
     net.close()
 
 
+def test_train_epoch_matches_steps_one_by_one(dev_ctx):
+    """The library's epoch loop (row gather on the device) against the same
+    steps taken through axs_mlp_adam_step on batches gathered by the test:
+    bitwise equal, and within 5e-6 of the FP64 reference Adam."""
+    from oracle import mlp as ref
+    from paper_1406_0236_amd import Mlp
+    net, p, sizes, rng = _net(dev_ctx, 4, 48, 2, 10, 3)
+    twin = Mlp(dev_ctx, 4, 48, 2, 10)
+    twin.set_params(p)
+    rows = 70
+    X = rng.standard_normal((rows, 4)).astype(np.float32)
+    T = rng.standard_normal((rows, 10)).astype(np.float32)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    pr = p.copy()
+    t = 0
+    # 5 steps of 16 (repeated rows, last row included), then 3 of 7
+    for batch, steps in ((16, 5), (7, 3)):
+        order = rng.integers(0, rows, batch * steps).astype(np.int32)
+        order[-1] = rows - 1
+        lrs = 1e-3 * (1.0 + np.arange(steps)) / steps
+        loss = net.train_epoch(Xd, Td, order, batch, lrs)
+        for s in range(steps):
+            idx = order[s * batch:(s + 1) * batch]
+            il = torch.from_numpy(idx.astype(np.int64)).cuda()
+            loss1 = twin.adam_step(Xd.index_select(0, il).contiguous(), Td.index_select(0, il).contiguous(), lrs[s])
+            t += 1
+            _, g = ref.loss_and_grad(pr, sizes, X[idx].astype(np.float64), T[idx].astype(np.float64))
+            pr, m, v = ref.adam_step(pr, m, v, g, t, lrs[s])
+        assert loss == loss1
+        got = net.get_params()
+        assert np.array_equal(got, twin.get_params())
+        assert np.max(np.abs(got.astype(np.float64) - pr)) < 5e-6
+    twin.close()
+    net.close()
+
+
+def test_train_epoch_rejects_bad_rows_and_rates(dev_ctx):
+    from paper_1406_0236_amd import AxsError
+    net, p, sizes, rng = _net(dev_ctx, 4, 16, 1, 3, 4)
+    Xd = torch.randn(20, 4, device="cuda")
+    Td = torch.randn(20, 3, device="cuda")
+    before = net.get_params()
+    ok = np.arange(8, dtype=np.int32)
+    for order, lrs in ((np.array([0, 1, 2, 20], np.int32), [1e-3]), (np.array([0, -1, 2, 3], np.int32), [1e-3]),
+                       (ok, [1e-3, 0.0])):
+        with pytest.raises(AxsError):
+            net.train_epoch(Xd, Td, order, 4, lrs)
+    assert np.array_equal(net.get_params(), before)
+    net.close()
+
+
 def test_mode_encoding_matches_its_definition(small_system):
     """c_{b,i,m} = e^{-i k d.c_b} (1/N_F) sum_l sigma e^{-i m th_l}, and decoding
     band-limited densities gives them back."""
