@@ -310,7 +310,7 @@ axs_status axs_mlp_adam_step(axs_mlp *mlp, const float *X, const float *T, int b
  * [steps x batch], each in [0, rows)) and lr (host double [steps], each > 0)
  * are checked and copied before the first step is queued, so the caller may
  * reuse them on return; a bad entry gives AXS_EINVAL with nothing queued.
- * Synchronises ctx's stream once before the copy; loss (may be NULL, else
+ * Synchronises ctx's stream before and after the copy; loss (may be NULL, else
  * synchronises again) receives the last step's loss.  The result equals the
  * same steps taken one by one through axs_mlp_adam_step on gathered batches. */
 axs_status axs_mlp_train_epoch(axs_mlp *mlp, const float *X, const float *T, int64_t rows, const int32_t *order,

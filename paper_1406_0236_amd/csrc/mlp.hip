@@ -528,9 +528,11 @@ axs_status axs_mlp_train_epoch(axs_mlp *h, const float *X, const float *T, int64
             n.order = (int32_t *)c.dalloc((size_t)total * sizeof(int32_t));
             n.cap_order = total;
         }
-        // the host array may be reused once this returns: copy it before the first step is queued
+        // after the previous epoch's steps (readers of n.order), and complete before the
+        // first step is queued, so the caller may reuse the host array on return
         AXS_HIP(hipStreamSynchronize(c.stream));
-        AXS_HIP(hipMemcpy(n.order, order, (size_t)total * sizeof(int32_t), hipMemcpyHostToDevice));
+        AXS_HIP(hipMemcpyAsync(n.order, order, (size_t)total * sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
+        AXS_HIP(hipStreamSynchronize(c.stream));
         axs::ensure_batch(n, batch);
         const int L = (int)n.sizes.size() - 1;
         for (int s = 0; s < steps; ++s) {
