@@ -140,11 +140,18 @@ enum {
     AXS_SOLVE_CERTIFY = 16,   /* flag, OR-ed into the mode: after the iteration, apply
                                  the FP64 operator once more to the returned sigma and
                                  report (and test convergence on) that explicit residual */
-    AXS_SOLVE_UNPRECONDITIONED = 32  /* flag, FP64 mode only: GMRES on (D + B) sigma = -v,
+    AXS_SOLVE_UNPRECONDITIONED = 32, /* flag, FP64 mode only: GMRES on (D + B) sigma = -v,
                                  the system of Sec. 3.3 without the block-diagonal
                                  preconditioner of Sec. 4 (residual relative to ||v||);
                                  for the comparison the paper makes at zero frequency
                                  (Sec. 6.1), where it finds the preconditioner superfluous */
+    AXS_SOLVE_RESTART_INNER = 64 /* flag, mixed mode only: every inner GMRES starts from
+                                 scratch.  By default the first inner run keeps its Krylov
+                                 basis (up to 61 vectors of nrhs x N complex128) and every
+                                 later inner run is augmented with it (it orthogonalises
+                                 against A U = C as well and adds U's part to its result),
+                                 which saves inner iterations; the flag saves that memory.
+                                 The answer is certified by the FP64 outer residual either way. */
 };
 
 /* Solve (eq. "precond")  sigma + D^{-1} B sigma = -D^{-1} v  for nrhs incident fields
@@ -153,7 +160,8 @@ enum {
  *  sigma0   : device complex128 [nrhs][N] initial guess, or NULL for zero.  A guess
  *             whose FP64 residual is not below || b || is replaced by zero.
  *  sigma    : device complex128 [nrhs][N], the result.
- *  mode     : AXS_SOLVE_FP64 or AXS_SOLVE_MIXED, optionally | AXS_SOLVE_CERTIFY.
+ *  mode     : AXS_SOLVE_FP64 or AXS_SOLVE_MIXED, optionally | AXS_SOLVE_CERTIFY
+ *             (and, mixed only, | AXS_SOLVE_RESTART_INNER).
  *             Without the flag the residual is the one GMRES minimises in its FP64
  *             Arnoldi basis (classical Gram-Schmidt twice), equal to the explicit
  *             one up to FP64 rounding; the flag costs one more FP64 application.

@@ -19,6 +19,7 @@ FP64, FP32 = 0, 1
 SOLVE_FP64, SOLVE_MIXED = 0, 1
 SOLVE_CERTIFY = 16   # flag: recompute the final residual with one more FP64 application
 SOLVE_UNPRECONDITIONED = 32   # flag (FP64 mode): GMRES on (D + B) sigma = -v
+SOLVE_RESTART_INNER = 64   # flag (mixed mode): inner GMRES runs start from scratch
 _STATUS = {0: "AXS_OK", 1: "AXS_NOT_CONVERGED", -1: "AXS_EINVAL", -2: "AXS_EHIP", -3: "AXS_ENOMEM",
            -4: "AXS_ESTATE", -5: "AXS_ENONFINITE"}
 

@@ -522,10 +522,12 @@ axs_status axs_solve(axs_ctx *ctx, const void *incident, const void *sigma0, voi
         check_apply(c, incident, sigma, nrhs, AXS_FP64);
         if (sigma0) check_apply(c, sigma0, sigma, nrhs, AXS_FP64);
         require_all_targets(c);
-        const int base = mode & ~(AXS_SOLVE_CERTIFY | AXS_SOLVE_UNPRECONDITIONED);
+        const int base = mode & ~(AXS_SOLVE_CERTIFY | AXS_SOLVE_UNPRECONDITIONED | AXS_SOLVE_RESTART_INNER);
         AXS_REQUIRE(base == AXS_SOLVE_FP64 || base == AXS_SOLVE_MIXED, AXS_EINVAL, "bad solve mode");
         AXS_REQUIRE(!(mode & AXS_SOLVE_UNPRECONDITIONED) || base == AXS_SOLVE_FP64, AXS_EINVAL,
                     "the unpreconditioned solve is FP64 GMRES only");
+        AXS_REQUIRE(!(mode & AXS_SOLVE_RESTART_INNER) || base == AXS_SOLVE_MIXED, AXS_EINVAL,
+                    "inner restarts exist in the mixed solve only");
         AXS_REQUIRE(tol > 0 && tol < 1 && std::isfinite(tol), AXS_EINVAL, "tol must be in (0, 1)");
         AXS_REQUIRE(max_iters >= 1 && max_iters <= 2000, AXS_EINVAL, "max_iters must be in [1, 2000]");
         const bool t = c.timing;
@@ -670,8 +672,10 @@ axs_status axs_solve_skeleton(axs_ctx *ctx, const void *incident, void *sigma, i
                     AXS_EINVAL, "bad arguments");
         AXS_REQUIRE(incident != sigma, AXS_EINVAL, "sigma must not alias the incident field");
         const bool certify = (mode & AXS_SOLVE_CERTIFY) != 0;
-        const int base = mode & ~AXS_SOLVE_CERTIFY;
+        const int restart = mode & AXS_SOLVE_RESTART_INNER;
+        const int base = mode & ~(AXS_SOLVE_CERTIFY | AXS_SOLVE_RESTART_INNER);
         AXS_REQUIRE(base == AXS_SOLVE_FP64 || base == AXS_SOLVE_MIXED, AXS_EINVAL, "bad solve mode");
+        AXS_REQUIRE(!restart || base == AXS_SOLVE_MIXED, AXS_EINVAL, "inner restarts exist in the mixed solve only");
         AXS_REQUIRE(tol > 0 && tol < 1, AXS_EINVAL, "tol must be in (0, 1)");
         Ctx &ch = *c.skel->child;
         const int64_t N = c.N, Ns = c.skel->Ns;
@@ -683,7 +687,7 @@ axs_status axs_solve_skeleton(axs_ctx *ctx, const void *incident, void *sigma, i
         const auto t0 = std::chrono::steady_clock::now();
         apply_precond(c, incident, y, nrhs, AXS_FP64, 1.0);           // D^{-1} v
         skel_restrict(c, y, bs, nrhs, -1.0);                           // -v~ = -V^* D^{-1} v
-        axs_status st = solve_impl(ch, nullptr, nullptr, xs, nrhs, base, tol, max_iters, info, bs);
+        axs_status st = solve_impl(ch, nullptr, nullptr, xs, nrhs, base | restart, tol, max_iters, info, bs);
         interbody_partials(ch, xs, nrhs, AXS_FP64);                    // B~ s~
         interbody_reduce_to_c128(ch, ws, nrhs, AXS_FP64);
         skel_prolong(c, ws, incident, u, nrhs);                         // v + U B~ s~

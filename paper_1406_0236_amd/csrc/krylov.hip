@@ -7,10 +7,13 @@
 // Mixed mode: flexible GMRES (the outer Arnoldi process and operator in FP64)
 // whose variable right preconditioner is an inner GMRES on the FP32 operator;
 // the outer FP64 residual decides convergence, so the answer is FP64-accurate.
+// The first inner run keeps its Krylov basis; later inner runs are augmented
+// with it (GCRO style, see Recycle) instead of starting from nothing.
 #include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdlib>
+#include <memory>
 
 #include "axs_internal.h"
 
@@ -117,6 +120,22 @@ __global__ void csub_kernel(const double2 *__restrict__ a, const double2 *__rest
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     out[t] = make_double2(a[t].x - b[t].x, a[t].y - b[t].y);
+}
+
+// p[c][i] = sum_l M[c][i][l] a[c][l]  (K x K per right-hand side, row-major)
+__global__ void cmatvec_small_kernel(const double2 *__restrict__ M, const double2 *__restrict__ a, int K, int nrhs,
+                                     double2 *__restrict__ p) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= K * nrhs) return;
+    const int c = t / K, i = t % K;
+    const double2 *m = M + ((int64_t)c * K + i) * K;
+    const double2 *x = a + (int64_t)c * K;
+    double re = 0, im = 0;
+    for (int l = 0; l < K; ++l) {
+        re += m[l].x * x[l].x - m[l].y * x[l].y;
+        im += m[l].x * x[l].y + m[l].y * x[l].x;
+    }
+    p[t] = make_double2(re, im);
 }
 
 // ---------------------------------------------------------------------------
@@ -270,15 +289,52 @@ struct Basis {
     }
 };
 
+// The Krylov relation A V_k = V_{k+1} Hbar of an earlier GMRES run on the same
+// operator (per rhs, Hbar (k+1) x k), kept so that a later run on a new right-
+// hand side minimises its residual over span(U) plus its own Krylov space
+// (GCRO-style augmentation): with the thin QR Hbar = Q R, C = V_{k+1} Q is
+// orthonormal and A U = C for U = V_k R^{-1}.  The later run orthogonalises
+// its start vector and every new Arnoldi vector against C as well, which
+// records B = C^H A V_j next to its own Hessenberg matrix, and takes
+//   x = U (C^H r0 - B y) + V_j y
+// with y from its own least-squares problem (Sec. 4 solves the system with
+// GMRES; restarting an inner solve otherwise discards the space it built).
+struct Recycle {
+    const double2 *V = nullptr;               // the earlier basis, k + 1 vectors of nrhs * N
+    int k = 0;
+    std::vector<char> on;                     // per rhs: relation usable (no breakdown)
+    std::vector<std::vector<cd>> Q, R;        // per rhs: Q (k+1) x k and R k x k, column-major
+    double2 *M = nullptr;                     // device [nrhs][k+1][k+1]: Q Q^H, row-major
+    Ctx *ctx = nullptr;                       // owner of M
+    Recycle() = default;
+    Recycle(const Recycle &) = delete;
+    Recycle &operator=(const Recycle &) = delete;
+    ~Recycle() {
+        if (ctx) ctx->dfree(M);
+    }
+};
+
+// Arnoldi record of a run, for building a Recycle: the unrotated Hessenberg
+// columns per rhs ((maxit+1) x maxit column-major) and whether any step broke
+// down (a zero new vector) for that rhs.
+struct ArnoldiRecord {
+    std::vector<std::vector<cd>> H;
+    std::vector<char> breakdown;
+    int steps = 0;
+};
+
 // Run GMRES for nrhs systems: op(x, y) computes y = A x.  V grows to at most
 // (maxit+1) vectors of nrhs*N.  Optional flexible mode: prec(v, z) gives
 // z_j ~ A^{-1} v_j stored in Z (at most maxit vectors), and the solution update
-// uses Z.  On entry r0 holds the initial residual. On exit x += (V or Z) y.
-// Returns the iteration counts per rhs.
+// uses Z.  On entry r0 holds the initial residual. On exit x += (V or Z) y
+// (+ the U part with rc).  rc (may be null): augment with an earlier run's
+// Krylov relation; rec (may be null): record this run's.  Returns the
+// iteration counts per rhs.
 template <class Op, class Prec>
 static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, double tol, const double2 *r0,
                                    double2 *x, Basis &V, Basis *Z, const std::vector<double> &bnorm, Op op,
-                                   Prec prec, bool flexible, std::vector<double> &rel_est) {
+                                   Prec prec, bool flexible, std::vector<double> &rel_est,
+                                   const Recycle *rc = nullptr, ArnoldiRecord *rec = nullptr) {
     const int64_t ldv = N * nrhs;
     Gmres G(nrhs, maxit);
     G.bnorm = bnorm;
@@ -289,8 +345,69 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
     // the squared norm of the new vector [nrhs], read back in one copy
     double2 *cdev = (double2 *)c.dalloc((size_t)nrhs * (2 * maxit + 1) * sizeof(double2));
     std::vector<double2> chost((size_t)nrhs * (2 * maxit + 1));
-    // beta = ||r0||
-    D.run(r0, ldv, 1, r0);
+    if (rec) {
+        rec->H.assign(nrhs, std::vector<cd>((size_t)(maxit + 1) * maxit, 0.0));
+        rec->breakdown.assign(nrhs, 0);
+        rec->steps = 0;
+    }
+    // augmentation: coefficients against the earlier basis, two passes [2][nrhs][K]
+    const int K = rc ? rc->k + 1 : 0;
+    std::unique_ptr<Dots> DR;
+    double2 *adev = nullptr, *pdev = nullptr;
+    std::vector<double2> ahost;
+    std::vector<std::vector<cd>> Bm;   // per rhs: B = C^H A V_j, k x maxit column-major
+    std::vector<std::vector<cd>> cr0;  // per rhs: C^H r0
+    auto project_out = [&](double2 *w, double2 *acoef) {
+        // w -= C C^H w = V_rc (Q Q^H) (V_rc^H w); acoef receives V_rc^H w
+        DR->launch(rc->V, ldv, K, w, acoef);
+        hipLaunchKernelGGL(cmatvec_small_kernel, dim3(ceil_div(K * nrhs, 128)), dim3(128), 0, c.stream, rc->M,
+                           acoef, K, nrhs, pdev);
+        AXS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(caxpy_many_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, rc->V, ldv, K,
+                           pdev, -1.0, w, N, nrhs);
+        AXS_HIP(hipGetLastError());
+    };
+    // C^H w from the two passes' V_rc^H w
+    auto qh = [&](int cc, const double2 *a0, const double2 *a1) {
+        std::vector<cd> out(rc->k, 0.0);
+        if (!rc->on[cc]) return out;
+        for (int i = 0; i < rc->k; ++i) {
+            cd sacc = 0.0;
+            for (int l = 0; l < K; ++l) {
+                const cd a(a0[(size_t)cc * K + l].x + a1[(size_t)cc * K + l].x,
+                           a0[(size_t)cc * K + l].y + a1[(size_t)cc * K + l].y);
+                sacc += std::conj(rc->Q[cc][(size_t)i * K + l]) * a;
+            }
+            out[i] = sacc;
+        }
+        return out;
+    };
+    const double2 *start = r0;
+    if (rc) {
+        DR.reset(new Dots(c, N, nrhs, K));
+        adev = (double2 *)c.dalloc((size_t)2 * nrhs * K * sizeof(double2));
+        pdev = (double2 *)c.dalloc((size_t)nrhs * K * sizeof(double2));
+        ahost.resize((size_t)2 * nrhs * K);
+        Bm.assign(nrhs, std::vector<cd>((size_t)rc->k * maxit, 0.0));
+        // start vector: r0 less its component in range(C), twice
+        V.reserve(2, 0);
+        AXS_HIP(hipMemcpyAsync(V.vec(0), r0, (size_t)ldv * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
+        for (int pass = 0; pass < 2; ++pass) project_out(V.vec(0), adev + (size_t)pass * nrhs * K);
+        AXS_HIP(hipMemcpyAsync(ahost.data(), adev, ahost.size() * sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        cr0.resize(nrhs);
+        for (int cc = 0; cc < nrhs; ++cc) cr0[cc] = qh(cc, ahost.data(), ahost.data() + (size_t)nrhs * K);
+        start = V.vec(0);
+    }
+    auto release = [&]() {
+        c.dfree(hdev);
+        c.dfree(sdev);
+        c.dfree(cdev);
+        c.dfree(adev);
+        c.dfree(pdev);
+    };
+    // beta = ||r0|| (of the projected start vector with rc)
+    D.run(start, ldv, 1, start);
     std::vector<double> beta(nrhs), inv(nrhs);
     rel_est.assign(nrhs, 0.0);
     bool all_done = true;
@@ -304,73 +421,83 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
         else all_done = false;
     }
     std::vector<int> iters(nrhs, 0);
-    if (all_done) {
-        c.dfree(hdev);
-        c.dfree(sdev);
-        c.dfree(cdev);
-        return iters;
-    }
-    V.reserve(2, 0);
-    scale(c, r0, inv, V.vec(0), N, nrhs, sdev);
     int j = 0;
-    for (; j < maxit; ++j) {
-        V.reserve(j + 2, j + 1);
-        double2 *vj = V.vec(j);
-        double2 *w = V.vec(j + 1);
-        if (flexible) {
-            Z->reserve(j + 1, j);
-            double2 *zj = Z->vec(j);
-            prec(vj, zj);
-            op(zj, w);
-        } else {
-            op(vj, w);
-        }
-        // classical Gram-Schmidt, twice, then the norm and the normalisation of
-        // the new vector, all stream-ordered on the device; the coefficients
-        // come to the host in one copy, the only synchronisation of the step
-        const int nv = j + 1;
-        const int64_t nh = (int64_t)nrhs * nv;
-        for (int pass = 0; pass < 2; ++pass) {
-            double2 *hc = cdev + pass * nh;
-            D.launch(V.p, ldv, nv, w, hc);
-            hipLaunchKernelGGL(caxpy_many_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, V.p, ldv,
-                               nv, hc, -1.0, w, N, nrhs);
+    if (!all_done) {
+        V.reserve(2, 0);
+        scale(c, start, inv, V.vec(0), N, nrhs, sdev);
+        for (; j < maxit; ++j) {
+            V.reserve(j + 2, j + 1);
+            double2 *vj = V.vec(j);
+            double2 *w = V.vec(j + 1);
+            if (flexible) {
+                Z->reserve(j + 1, j);
+                double2 *zj = Z->vec(j);
+                prec(vj, zj);
+                op(zj, w);
+            } else {
+                op(vj, w);
+            }
+            // classical Gram-Schmidt, twice (against range(C) first with rc), then
+            // the norm and the normalisation of the new vector, all stream-ordered
+            // on the device; the coefficients come to the host in one copy, the
+            // only synchronisation of the step
+            const int nv = j + 1;
+            const int64_t nh = (int64_t)nrhs * nv;
+            for (int pass = 0; pass < 2; ++pass) {
+                if (rc) project_out(w, adev + (size_t)pass * nrhs * K);
+                double2 *hc = cdev + pass * nh;
+                D.launch(V.p, ldv, nv, w, hc);
+                hipLaunchKernelGGL(caxpy_many_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, V.p,
+                                   ldv, nv, hc, -1.0, w, N, nrhs);
+                AXS_HIP(hipGetLastError());
+            }
+            D.launch(w, ldv, 1, w, cdev + 2 * nh);
+            hipLaunchKernelGGL(cnormalize_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, w,
+                               cdev + 2 * nh, N, nrhs);
             AXS_HIP(hipGetLastError());
-        }
-        D.launch(w, ldv, 1, w, cdev + 2 * nh);
-        hipLaunchKernelGGL(cnormalize_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, w,
-                           cdev + 2 * nh, N, nrhs);
-        AXS_HIP(hipGetLastError());
-        AXS_HIP(hipMemcpyAsync(chost.data(), cdev, (size_t)(2 * nh + nrhs) * sizeof(double2),
-                               hipMemcpyDeviceToHost, c.stream));
-        AXS_HIP(hipStreamSynchronize(c.stream));
-        all_done = true;
-        for (int cc = 0; cc < nrhs; ++cc) {
-            const double hn = std::sqrt(std::max(0.0, chost[2 * nh + cc].x));
-            AXS_REQUIRE(std::isfinite(hn), AXS_ENONFINITE, "non-finite Arnoldi vector");
-            for (int i = 0; i < nv; ++i) {
-                const double2 a = chost[(size_t)cc * nv + i], b = chost[nh + (size_t)cc * nv + i];
-                G.h(cc, i, j) = cd(a.x + b.x, a.y + b.y);
+            AXS_HIP(hipMemcpyAsync(chost.data(), cdev, (size_t)(2 * nh + nrhs) * sizeof(double2),
+                                   hipMemcpyDeviceToHost, c.stream));
+            if (rc)
+                AXS_HIP(hipMemcpyAsync(ahost.data(), adev, ahost.size() * sizeof(double2), hipMemcpyDeviceToHost,
+                                       c.stream));
+            AXS_HIP(hipStreamSynchronize(c.stream));
+            all_done = true;
+            for (int cc = 0; cc < nrhs; ++cc) {
+                const double hn = std::sqrt(std::max(0.0, chost[2 * nh + cc].x));
+                AXS_REQUIRE(std::isfinite(hn), AXS_ENONFINITE, "non-finite Arnoldi vector");
+                for (int i = 0; i < nv; ++i) {
+                    const double2 a = chost[(size_t)cc * nv + i], b = chost[nh + (size_t)cc * nv + i];
+                    G.h(cc, i, j) = cd(a.x + b.x, a.y + b.y);
+                }
+                G.h(cc, j + 1, j) = hn;
+                if (rec) {
+                    for (int i = 0; i <= nv; ++i) rec->H[cc][(size_t)j * (maxit + 1) + i] = G.h(cc, i, j);
+                    if (hn == 0.0) rec->breakdown[cc] = 1;
+                }
+                if (rc) {
+                    const std::vector<cd> bcol = qh(cc, ahost.data(), ahost.data() + (size_t)nrhs * K);
+                    for (int i = 0; i < rc->k; ++i) Bm[cc][(size_t)j * rc->k + i] = bcol[i];
+                }
+                if (G.done_at[cc] < 0) {
+                    const double res = G.rotate(cc, j);
+                    rel_est[cc] = res / bnorm[cc];
+                    if (rel_est[cc] <= tol || hn == 0.0) G.done_at[cc] = j + 1;
+                }
+                if (G.done_at[cc] < 0) all_done = false;
             }
-            G.h(cc, j + 1, j) = hn;
-            if (G.done_at[cc] < 0) {
-                const double res = G.rotate(cc, j);
-                rel_est[cc] = res / bnorm[cc];
-                if (rel_est[cc] <= tol || hn == 0.0) G.done_at[cc] = j + 1;
+            if (verbose_level() > 0) {
+                double worst = 0;
+                for (int cc = 0; cc < nrhs; ++cc) worst = std::max(worst, rel_est[cc]);
+                std::fprintf(stderr, "[axs] %s iteration %d: max relative residual %.3e\n",
+                             flexible ? "outer" : "gmres", j + 1, worst);
             }
-            if (G.done_at[cc] < 0) all_done = false;
-        }
-        if (verbose_level() > 0) {
-            double worst = 0;
-            for (int cc = 0; cc < nrhs; ++cc) worst = std::max(worst, rel_est[cc]);
-            std::fprintf(stderr, "[axs] %s iteration %d: max relative residual %.3e\n",
-                         flexible ? "outer" : "gmres", j + 1, worst);
-        }
-        if (all_done) {
-            ++j;
-            break;
+            if (all_done) {
+                ++j;
+                break;
+            }
         }
     }
+    if (rec) rec->steps = j;
     // x += basis * y, per rhs with its own k
     const double2 *basis = flexible ? Z->p : V.p;
     int kmax = 0;
@@ -378,21 +505,86 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
         iters[cc] = G.done_at[cc] < 0 ? j : G.done_at[cc];
         kmax = std::max(kmax, iters[cc]);
     }
+    std::vector<std::vector<cd>> ys(nrhs);
+    for (int cc = 0; cc < nrhs; ++cc)
+        if (iters[cc] > 0) ys[cc] = G.lsq(cc, iters[cc]);
     if (kmax > 0) {
         std::vector<cd> y((size_t)nrhs * kmax, 0.0);
-        for (int cc = 0; cc < nrhs; ++cc) {
-            if (iters[cc] == 0) continue;
-            std::vector<cd> yc = G.lsq(cc, iters[cc]);
-            for (int i = 0; i < iters[cc]; ++i) y[(size_t)cc * kmax + i] = yc[i];
-        }
+        for (int cc = 0; cc < nrhs; ++cc)
+            for (int i = 0; i < iters[cc]; ++i) y[(size_t)cc * kmax + i] = ys[cc][i];
         double2 *ydev = (double2 *)c.dalloc(y.size() * sizeof(double2));
         axpy_many(c, basis, ldv, kmax, y, nrhs, 1.0, x, N, ydev);
         c.dfree(ydev);
     }
-    c.dfree(hdev);
-    c.dfree(sdev);
-    c.dfree(cdev);
+    if (rc) {
+        // x += U (C^H r0 - B y) = V_k R^{-1} (C^H r0 - B y)
+        const int k = rc->k;
+        std::vector<cd> d((size_t)nrhs * k, 0.0);
+        for (int cc = 0; cc < nrhs; ++cc) {
+            if (!rc->on[cc]) continue;
+            std::vector<cd> sv = cr0[cc];
+            for (int jj = 0; jj < iters[cc]; ++jj)
+                for (int i = 0; i < k; ++i) sv[i] -= Bm[cc][(size_t)jj * k + i] * ys[cc][jj];
+            const std::vector<cd> &R = rc->R[cc];
+            for (int i = k - 1; i >= 0; --i) {
+                cd acc = sv[i];
+                for (int l = i + 1; l < k; ++l) acc -= R[(size_t)l * k + i] * d[(size_t)cc * k + l];
+                d[(size_t)cc * k + i] = acc / R[(size_t)i * k + i];
+            }
+        }
+        double2 *ddev = (double2 *)c.dalloc(d.size() * sizeof(double2));
+        axpy_many(c, rc->V, ldv, k, d, nrhs, 1.0, x, N, ddev);
+        c.dfree(ddev);
+    }
+    release();
     return iters;
+}
+
+// Build the augmentation of later runs from the record of a run whose basis is
+// V (rec.steps + 1 vectors): thin QR of each rhs's Hbar by classical
+// Gram-Schmidt, twice; a rhs whose run broke down is left out.
+static void build_recycle(Ctx &c, const ArnoldiRecord &rec, int maxit, const double2 *V, int nrhs, Recycle &rc) {
+    const int k = rec.steps, K = k + 1;
+    rc.V = V;
+    rc.k = k;
+    rc.on.assign(nrhs, 0);
+    rc.Q.assign(nrhs, std::vector<cd>((size_t)K * k, 0.0));
+    rc.R.assign(nrhs, std::vector<cd>((size_t)k * k, 0.0));
+    std::vector<double2> M((size_t)nrhs * K * K, make_double2(0.0, 0.0));
+    for (int cc = 0; cc < nrhs; ++cc) {
+        if (rec.breakdown[cc] || k == 0) continue;
+        std::vector<cd> &Q = rc.Q[cc], &R = rc.R[cc];
+        bool ok = true;
+        for (int jj = 0; jj < k && ok; ++jj) {
+            std::vector<cd> q(K);
+            for (int i = 0; i < K; ++i) q[i] = rec.H[cc][(size_t)jj * (maxit + 1) + i];
+            for (int pass = 0; pass < 2; ++pass)
+                for (int l = 0; l < jj; ++l) {
+                    cd r = 0.0;
+                    for (int i = 0; i < K; ++i) r += std::conj(Q[(size_t)l * K + i]) * q[i];
+                    R[(size_t)jj * k + l] += r;
+                    for (int i = 0; i < K; ++i) q[i] -= r * Q[(size_t)l * K + i];
+                }
+            double nq = 0.0;
+            for (int i = 0; i < K; ++i) nq += std::norm(q[i]);
+            nq = std::sqrt(nq);
+            if (!(nq > 0.0) || !std::isfinite(nq)) ok = false;
+            R[(size_t)jj * k + jj] = nq;
+            for (int i = 0; i < K && ok; ++i) Q[(size_t)jj * K + i] = q[i] / nq;
+        }
+        if (!ok) continue;
+        rc.on[cc] = 1;
+        for (int i = 0; i < K; ++i)
+            for (int l = 0; l < K; ++l) {
+                cd sacc = 0.0;
+                for (int jj = 0; jj < k; ++jj) sacc += Q[(size_t)jj * K + i] * std::conj(Q[(size_t)jj * K + l]);
+                M[((size_t)cc * K + i) * K + l] = make_double2(sacc.real(), sacc.imag());
+            }
+    }
+    rc.ctx = &c;
+    rc.M = (double2 *)c.dalloc(M.size() * sizeof(double2));
+    AXS_HIP(hipMemcpyAsync(rc.M, M.data(), M.size() * sizeof(double2), hipMemcpyHostToDevice, c.stream));
+    AXS_HIP(hipStreamSynchronize(c.stream));   // M is pageable host memory
 }
 
 static std::vector<double> norms(Ctx &c, const double2 *v, int64_t N, int nrhs) {
@@ -408,7 +600,8 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
     const auto t0 = std::chrono::steady_clock::now();
     const bool certify = (mode & AXS_SOLVE_CERTIFY) != 0;
     const bool unprec = (mode & AXS_SOLVE_UNPRECONDITIONED) != 0;
-    mode &= ~(AXS_SOLVE_CERTIFY | AXS_SOLVE_UNPRECONDITIONED);
+    const bool restart_inner = (mode & AXS_SOLVE_RESTART_INNER) != 0;
+    mode &= ~(AXS_SOLVE_CERTIFY | AXS_SOLVE_UNPRECONDITIONED | AXS_SOLVE_RESTART_INNER);
     // the operator of the solve: I + D^{-1} B (FP64), or D + B without the preconditioner
     auto op64 = [&](const double2 *in, double2 *out) {
         if (unprec) apply_unpreconditioned(c, in, out, nrhs);
@@ -463,7 +656,11 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
         outer = gmres_core(c, N, nrhs, max_iters, tol, r, x, V, nullptr, bn, op64, none, false, est);
     } else {
         const int max_inner = 60;
-        Basis Z(c, vb, max_iters), Vi(c, vb, max_inner + 1);
+        // Vr keeps the first inner run's Krylov basis: every later inner run is
+        // augmented with that run's relation (Recycle) instead of starting over
+        Basis Z(c, vb, max_iters), Vi(c, vb, max_inner + 1), Vr(c, vb, max_inner + 1);
+        Recycle rc;
+        bool have_rc = false;
         auto prec = [&](const double2 *v, double2 *z) {
             // inner GMRES on the FP32 operator, zero initial guess, rhs v; it only
             // has to reduce the outer residual by the factor still missing
@@ -477,7 +674,20 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
             auto op32 = [&](const double2 *in, double2 *out) { apply_operator(c, in, out, nrhs, AXS_FP32); };
             auto none = [&](const double2 *, double2 *) {};
             std::vector<double> ie;
-            std::vector<int> it = gmres_core(c, N, nrhs, max_inner, tin, v, z, Vi, nullptr, vn, op32, none, false, ie);
+            std::vector<int> it;
+            if (restart_inner) {
+                it = gmres_core(c, N, nrhs, max_inner, tin, v, z, Vi, nullptr, vn, op32, none, false, ie);
+            } else if (!have_rc) {
+                ArnoldiRecord rec;
+                it = gmres_core(c, N, nrhs, max_inner, tin, v, z, Vr, nullptr, vn, op32, none, false, ie, nullptr,
+                                &rec);
+                if (rec.steps > 0) {
+                    build_recycle(c, rec, max_inner, Vr.p, nrhs, rc);
+                    have_rc = true;
+                }
+            } else {
+                it = gmres_core(c, N, nrhs, max_inner, tin, v, z, Vi, nullptr, vn, op32, none, false, ie, &rc);
+            }
             for (int cc = 0; cc < nrhs; ++cc) inner_total[cc] += it[cc];
         };
         outer = gmres_core(c, N, nrhs, max_iters, tol, r, x, V, &Z, bn, op64, prec, true, est);

@@ -83,6 +83,23 @@ def test_fullsize_solve_residual_certified_on_one_body(lattice):
     assert e <= 1.2e-7
 
 
+def test_fullsize_augmented_inner_runs_save_iterations(lattice):
+    """On the 27 spheres the second inner run, augmented with the first one's
+    Krylov space, needs fewer FP32 iterations than one restarted from scratch,
+    with the same number of outer steps and both answers certified."""
+    from paper_1406_0236_amd import SOLVE_MIXED, SOLVE_RESTART_INNER
+    wl, S, ctx = lattice
+    v = ctx.incident_plane_waves(wl.dirs)
+    res = {}
+    for name, mode in (("augmented", SOLVE_MIXED), ("restarted", SOLVE_MIXED | SOLVE_RESTART_INNER)):
+        sol, info = ctx.solve(v, mode=mode, tol=1e-7, certify=True)
+        print(name, info[0])
+        assert info[0]["converged"]
+        res[name] = info[0]
+    assert res["augmented"]["iterations"] == res["restarted"]["iterations"]
+    assert res["augmented"]["inner_iterations"] < res["restarted"]["inner_iterations"]
+
+
 def test_fullsize_skeleton_solve(lattice):
     """The benchmark problem through the ring skeletonization (Sec. 5, eps = 1e-8):
     the ring rank equals the reference's ID of the same shape and proxy sphere

@@ -243,6 +243,47 @@ def test_gmres_residual_equals_explicit_residual(small):
             assert a["converged"] and b["converged"]
 
 
+def test_augmented_inner_runs_against_restarted_ones(small, mixed):
+    """Mixed solves whose later inner GMRES runs are augmented with the first
+    inner run's Krylov space (the default) against inner runs restarted from
+    scratch (AXS_SOLVE_RESTART_INNER), to tol 1e-11 (several outer steps, so
+    several augmented runs): both certified by the explicit FP64 residual,
+    both within 1e-8 of the dense reference solve (two bodies, 3 directions)
+    and of each other (8 bodies, 64 directions, tol 1e-9), and the augmented
+    runs never take more inner iterations.  The flag is refused in FP64 mode."""
+    from paper_1406_0236_amd import SOLVE_FP64, SOLVE_MIXED, SOLVE_RESTART_INNER, AxsError
+    wl, S, ctx = small
+    dirs = np.array([[0.0, 0.6, 0.8], [0.48, -0.6, 0.64], [-0.8, 0.0, 0.6]])
+    v = S.plane_waves(dirs)
+    xd = np.stack([S.solve_dense(v[:, c]) for c in range(3)])
+    vd = ctx.incident_plane_waves(dirs)
+    inner = {}
+    for name, mode in (("augmented", SOLVE_MIXED), ("restarted", SOLVE_MIXED | SOLVE_RESTART_INNER)):
+        sol, info = ctx.solve(vd, mode=mode, tol=1e-11, max_iters=100, certify=True)
+        err = np.linalg.norm(sol.cpu().numpy() - xd) / np.linalg.norm(xd)
+        inner[name] = sum(i["inner_iterations"] for i in info)
+        print(f"{name}: outer {[i['iterations'] for i in info]} inner {inner[name]} err {err:.2e}")
+        assert all(i["converged"] and i["rel_residual"] <= 1e-11 for i in info)
+        assert err < 1e-8, err
+    assert inner["augmented"] <= inner["restarted"]
+    with pytest.raises(AxsError, match="EINVAL"):
+        ctx.solve(vd, mode=SOLVE_FP64 | SOLVE_RESTART_INNER, tol=1e-9)
+
+    wl, S, ctx = mixed
+    vd = ctx.incident_plane_waves(wl.dirs)
+    sols, inner = [], {}
+    for name, mode in (("augmented", SOLVE_MIXED), ("restarted", SOLVE_MIXED | SOLVE_RESTART_INNER)):
+        sol, info = ctx.solve(vd, mode=mode, tol=1e-9, max_iters=100, certify=True)
+        inner[name] = sum(i["inner_iterations"] for i in info)
+        print(f"{name}: inner iterations over 64 rhs {inner[name]}")
+        assert all(i["converged"] and i["rel_residual"] <= 1e-9 for i in info)
+        sols.append(sol.cpu().numpy())
+    d = np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(sols[1])
+    print(f"augmented vs restarted: {d:.2e}")
+    assert d < 1e-7, d
+    assert inner["augmented"] <= inner["restarted"]
+
+
 def test_warm_start_is_used_and_bad_guess_is_dropped(small):
     from paper_1406_0236_amd import SOLVE_FP64
     wl, S, ctx = small
