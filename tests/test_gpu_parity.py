@@ -284,6 +284,29 @@ def test_augmented_inner_runs_against_restarted_ones(small, mixed):
     assert inner["augmented"] <= inner["restarted"]
 
 
+def test_mixed_solve_with_a_zero_incident_field(small):
+    """A batch whose middle incident field is zero: its first inner run breaks
+    down at once (a zero Arnoldi vector), so it is left out of the augmentation
+    of the later inner runs while the other two keep it.  The zero column
+    comes back exactly zero and converged, the others match the dense
+    reference solve, for the augmented and the restarted inner runs alike."""
+    from paper_1406_0236_amd import SOLVE_MIXED, SOLVE_RESTART_INNER
+    wl, S, ctx = small
+    dirs = np.array([[0.0, 0.6, 0.8], [1.0, 0.0, 0.0], [-0.8, 0.0, 0.6]])
+    v = S.plane_waves(dirs)
+    vd = ctx.incident_plane_waves(dirs)
+    vd[1].zero_()
+    xd = [S.solve_dense(v[:, c]) for c in (0, 2)]
+    for mode in (SOLVE_MIXED, SOLVE_MIXED | SOLVE_RESTART_INNER):
+        sol, info = ctx.solve(vd, mode=mode, tol=1e-10, max_iters=100, certify=True)
+        x = sol.cpu().numpy()
+        print(mode, [(i["iterations"], i["inner_iterations"], i["rel_residual"]) for i in info])
+        assert np.all(x[1] == 0) and info[1]["converged"]
+        for c, ref in zip((0, 2), xd):
+            err = np.linalg.norm(x[c] - ref) / np.linalg.norm(ref)
+            assert info[c]["converged"] and err < 1e-8, (mode, c, err)
+
+
 def test_warm_start_is_used_and_bad_guess_is_dropped(small):
     from paper_1406_0236_amd import SOLVE_FP64
     wl, S, ctx = small
