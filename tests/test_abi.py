@@ -50,6 +50,20 @@ def test_binding_table_matches_header():
     assert set(_lib.EXPORTS) == header_functions()
 
 
+def test_binding_constants_match_header_enums():
+    """The precision, solve-mode and status values the binding passes and
+    decodes are the ones the header's enums define."""
+    from paper_1406_0236_amd import _lib
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    enum = {k: int(v) for k, v in re.findall(r"\b(AXS_[A-Z_0-9]+)\s*=\s*(-?\d+)", text)}
+    for name in ("FP32", "FP64", "SOLVE_FP64", "SOLVE_MIXED", "SOLVE_CERTIFY", "SOLVE_UNPRECONDITIONED",
+                 "SOLVE_RESTART_INNER"):
+        assert getattr(_lib, name) == enum["AXS_" + name], name
+    for code, name in _lib._STATUS.items():
+        assert enum[name] == code, name
+    assert (_lib.AXS_OK, _lib.AXS_NOT_CONVERGED) == (enum["AXS_OK"], enum["AXS_NOT_CONVERGED"])
+
+
 def test_null_handles_are_rejected(lib):
     assert lib.axs_destroy(None) == -1
     assert lib.axs_last_error(None) == b"null context"
