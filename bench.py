@@ -157,8 +157,8 @@ def main():
                          "multiply-accumulate")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the decomposition over several GPUs is a design, not built", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
+              "its decomposition over several GPUs is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
