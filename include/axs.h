@@ -113,7 +113,10 @@ axs_status axs_modal_matrices(axs_ctx *ctx, int body_id, int which, void *out);
 
 /* y = sigma + D^{-1} B sigma  (eq. "precond") for nrhs vectors.
  * sigma, y : device complex128 [nrhs][N]; they must not overlap.
- * precision : AXS_FP64 or AXS_FP32 (see above). */
+ * precision : AXS_FP64 or AXS_FP32 (see above).
+ * The input is scanned for NaN/Inf first (AXS_ENONFINITE, nothing computed);
+ * that scan synchronises the stream before the operator is queued.  The same
+ * holds for axs_apply_interbody and axs_apply_precond below. */
 axs_status axs_apply_matvec(axs_ctx *ctx, const void *sigma, void *y, int nrhs, int precision);
 
 /* Building blocks of the operator, same layouts as axs_apply_matvec:
@@ -285,17 +288,31 @@ axs_status axs_solve_skeleton(axs_ctx *ctx, const void *incident, void *sigma, i
 
 /* ------------------------------------------------------------------------ *
  * Learned warm start.  A multilayer perceptron maps (incident direction,
- * scaled wavenumber) to the low azimuthal modes of the density; it is
- * trained on solves of the method itself, and its prediction is decoded into
- * an initial guess sigma0 for axs_solve, which keeps it only if its FP64
+ * wavenumber) to an initial guess for axs_solve.  The guess is exact in its
+ * single-body part and learned in the rest: by eq. "precond" the solution
+ * satisfies sigma* = b~ - D^{-1} B sigma* with b~ = -D^{-1} v (the response of
+ * each body alone to the incident wave, one preconditioner application), and
+ * the network predicts the multiple-scattering part split by source body,
+ *     sigma*_b - b~_b = sum_{b' != b} u^{b'}_b,   u^{b'}_b = -D_b^{-1} B_{bb'} sigma*_{b'},
+ * each term with its leading phase phi_{bb'} = kappa (d.c_{b'} + |c_b - c_{b'}|)
+ * (the incident wave at the centre of b' carried to the centre of b) taken
+ * out and only its azimuthal modes |m| <= m_max kept.  It is trained on
+ * solves of the method itself.  axs_solve keeps a guess only if its FP64
  * residual is below || b || (the zero guess otherwise).
+ *
+ * Warm-start layout, floats per right-hand side (axs_warm_start_size):
+ *   for target body b (build order), source slot s = 0..B-2 (the other bodies
+ *   b' in build order), contour node i, m = -m_max..m_max: (re, im) of
+ *     Y = e^{-i phi_{bb'}} (1/N_F) sum_l u^{b'}_b(i, l) e^{-i m theta_l};
+ *   P = 2 (B - 1) (2 m_max + 1) sum_b N_G(b).
  * ------------------------------------------------------------------------ */
 typedef struct axs_mlp axs_mlp;
 
 /* Network n_in -> width (x depth hidden layers, GELU) -> n_out (linear), FP32,
- * on ctx's device and stream, parameters zero until axs_mlp_set_params.  The
- * network must be destroyed before its context.  Parameters are packed layer by
- * layer as [W_1 (n_in x width, row-major, input index first), b_1, W_2, b_2, ...]. */
+ * on ctx's device and stream, parameters zero until axs_mlp_set_params or
+ * axs_mlp_train.  The network must be destroyed before its context.  Parameters
+ * are packed layer by layer as [W_1 (n_in x width, row-major, input index
+ * first), b_1, W_2, b_2, ...].  For the warm start n_in = 4 and n_out = P. */
 axs_status axs_mlp_create(axs_ctx *ctx, int n_in, int width, int depth, int n_out, axs_mlp **out);
 axs_status axs_mlp_destroy(axs_mlp *mlp);
 axs_status axs_mlp_num_params(const axs_mlp *mlp, int64_t *count);
@@ -325,18 +342,53 @@ axs_status axs_mlp_train_epoch(axs_mlp *mlp, const float *X, const float *T, int
                                int batch, int steps, const double *lr, double beta1, double beta2, double eps,
                                double *loss);
 
-/* Floats per right-hand side of the mode encoding below:
- * 2 * (2 m_max + 1) * sum over bodies of N_G. */
+/* Train the warm-start network (n_in = 4) on S samples: X device float [S][4]
+ * = (d_x, d_y, d_z, k) per sample, Y device float [S][n_out] its targets
+ * (axs_warm_start_encode of the solution).  The library maps k to
+ * (2k - (k_min + k_max)) / (k_max - k_min), divides Y by its root mean
+ * square, initialises the parameters (He: W ~ N(0, 2 / fan_in), biases 0,
+ * from a counter-based generator seeded by init_seed; init_seed < 0 keeps the
+ * current network), and runs `epochs` epochs of Adam: each epoch a seeded
+ * permutation (Fisher-Yates) of the samples in floor(S / batch) batches, the
+ * learning rate decaying from lr to lr_final along a cosine over all steps;
+ * at the end the target scale is folded into the last layer, so that
+ * axs_mlp_forward returns Y-scaled outputs, and the Adam state is reset.
+ * hparams: a JSON object of numbers with keys k_min, k_max (required),
+ * epochs (200), batch (256), lr (1e-3), lr_final (1e-5), beta1 (0.9),
+ * beta2 (0.999), eps (1e-8), seed (5), init_seed (4); anything else is
+ * AXS_EINVAL.  loss_per_epoch: host double [epochs] receiving each epoch's
+ * last-step loss on the scaled targets, or NULL.  Synchronous. */
+axs_status axs_mlp_train(axs_mlp *mlp, const float *X, const float *Y, int64_t S, const char *hparams,
+                         double *loss_per_epoch);
+
+/* Initial guess sigma0 (device complex128 [nrhs][N]) for the plane waves dirs
+ * (host [nrhs][3]) on ctx: sigma0 = b~ + decode(network(features)), with the
+ * features (d, k mapped through k_range as in axs_mlp_train) at ctx's
+ * wavenumber, b~ = -D^{-1} v computed by the library, and the decoding of the
+ * warm-start layout above; m_max follows from the network's n_out (AXS_EINVAL
+ * if n_out is not a warm-start size of ctx).  kappas (host [nrhs]) may be
+ * NULL; if given, every entry must equal ctx's wavenumber (AXS_EINVAL).
+ * k_range: host double[2], the training range.  mlp and ctx must be on one
+ * device (they may use different streams).  Synchronous. */
+axs_status axs_mlp_predict(axs_mlp *mlp, axs_ctx *ctx, const double *dirs, const double *kappas, int nrhs,
+                           const double k_range[2], void *sigma0);
+
+/* Floats per right-hand side of the warm-start layout, P (above).  AXS_EINVAL
+ * for fewer than two bodies or m_max beyond a body's mode cutoff. */
 axs_status axs_warm_start_size(axs_ctx *ctx, int mmax, int64_t *P);
-/* coeff[c] (device float [nrhs][P]): for body b (build order), contour node i,
- * m = -m_max..m_max, (re, im) of e^{-i kappa d_c.centre_b} (1/N_F) sum_l
- * sigma[c](b, i, l) e^{-i m theta_l}; dirs host [nrhs][3]. */
-axs_status axs_modes_from_density(axs_ctx *ctx, const void *sigma, const double *dirs, int nrhs,
-                                  int mmax, float *coeff);
-/* the inverse map on the retained modes: sigma[c](b, i, l) = e^{i kappa d_c.centre_b}
- * sum_{|m| <= m_max} coeff e^{i m theta_l}; sigma device complex128 [nrhs][N]. */
-axs_status axs_density_from_modes(axs_ctx *ctx, const float *coeff, const double *dirs, int nrhs,
-                                  int mmax, void *sigma);
+/* Training targets: Y (device float [nrhs][P]) of the densities sigma (device
+ * complex128 [nrhs][N], normally solutions of axs_solve for the plane waves
+ * dirs, host [nrhs][3]): per source body b', the FP64 inter-body sum of sigma
+ * restricted to b', -D^{-1} of it, then the layout's modes and phases.
+ * Synchronous. */
+axs_status axs_warm_start_encode(axs_ctx *ctx, const void *sigma, const double *dirs, int nrhs, int mmax,
+                                 float *Y);
+/* sigma (device complex128 [nrhs][N]) = the decoding of Y (device float
+ * [nrhs][P]): sum over source slots and |m| <= m_max of e^{i phi_{bb'}} Y
+ * e^{i m theta_l}.  With m_max = every body's M, decode(encode(x)) =
+ * -D^{-1} B x for any x (the sum over sources is exact).  Synchronous. */
+axs_status axs_warm_start_decode(axs_ctx *ctx, const float *Y, const double *dirs, int nrhs, int mmax,
+                                 void *sigma);
 
 #ifdef __cplusplus
 }

@@ -59,6 +59,34 @@ Ctx::~Ctx() {
         if (e) (void)hipEventDestroy(e);
 }
 
+// p[0..n) = value (a kernel, not a memset, so that graph-captured callers record no memset node)
+__global__ void fill_int_kernel(int *__restrict__ p, int n, int value) {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = value;
+}
+
+// flag = 1 if any component of v[0..n) is NaN or Inf (integer OR, order-free)
+__global__ void nonfinite_kernel(const double2 *__restrict__ v, int64_t n, int *__restrict__ flag) {
+    int bad = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const double2 a = v[t];
+        bad |= !(isfinite(a.x) && isfinite(a.y));
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+void require_finite(Ctx &c, const void *v, int64_t n, const char *what) {
+    int *flag = (int *)c.scratch(WS_FLAG, sizeof(int));
+    hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, c.stream, flag, 1, 0);
+    AXS_HIP(hipGetLastError());
+    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(n, 256)));
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(nblk), dim3(256), 0, c.stream, (const double2 *)v, n, flag);
+    AXS_HIP(hipGetLastError());
+    int host = 0;
+    AXS_HIP(hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    AXS_HIP(hipStreamSynchronize(c.stream));
+    AXS_REQUIRE(host == 0, AXS_ENONFINITE, std::string("non-finite value (NaN or Inf) in ") + what);
+}
+
 // ---------------------------------------------------------------------------
 // operator composition
 // ---------------------------------------------------------------------------
@@ -485,6 +513,7 @@ axs_status axs_apply_matvec(axs_ctx *ctx, const void *sigma, void *y, int nrhs, 
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         check_apply(c, sigma, y, nrhs, precision);
         require_all_targets(c);
+        axs::require_finite(c, sigma, (int64_t)nrhs * c.N, "sigma");
         axs::apply_operator(c, sigma, y, nrhs, precision);
         return AXS_OK;
     });
@@ -493,6 +522,7 @@ axs_status axs_apply_matvec(axs_ctx *ctx, const void *sigma, void *y, int nrhs, 
 axs_status axs_apply_interbody(axs_ctx *ctx, const void *sigma, void *y, int nrhs, int precision) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         check_apply(c, sigma, y, nrhs, precision);
+        axs::require_finite(c, sigma, (int64_t)nrhs * c.N, "sigma");
         axs::rec(c, 0);
         axs::interbody_partials(c, sigma, nrhs, precision);
         axs::interbody_reduce_to_c128(c, y, nrhs, precision);
@@ -511,6 +541,7 @@ axs_status axs_apply_interbody(axs_ctx *ctx, const void *sigma, void *y, int nrh
 axs_status axs_apply_precond(axs_ctx *ctx, const void *x, void *y, int nrhs, int precision) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         check_apply(c, x, y, nrhs, precision);
+        axs::require_finite(c, x, (int64_t)nrhs * c.N, "x");
         axs::apply_precond(c, x, y, nrhs, precision, 1.0);
         return AXS_OK;
     });
@@ -668,6 +699,7 @@ axs_status axs_solve_skeleton(axs_ctx *ctx, const void *incident, void *sigma, i
                               int max_iters, axs_solve_info *info) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         AXS_REQUIRE(c.skel, AXS_ESTATE, "call axs_skeletonize first");
+        require_all_targets(c);
         AXS_REQUIRE(incident && sigma && nrhs >= 1 && nrhs <= 4096 && max_iters >= 1 && max_iters <= 2000,
                     AXS_EINVAL, "bad arguments");
         AXS_REQUIRE(incident != sigma, AXS_EINVAL, "sigma must not alias the incident field");

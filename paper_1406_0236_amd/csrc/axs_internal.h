@@ -196,7 +196,7 @@ struct Ctx {
     // device allocations owned by the context
     std::vector<void *> owned;
     // named scratch buffers (grow-only)
-    Buffer ws[18];
+    Buffer ws[19];
 
     void *dalloc(size_t bytes);
     void dfree(void *p);
@@ -223,6 +223,7 @@ enum ScratchSlot {
     WS_EVAL = 15,
     WS_Q16 = 16,     // FP16 density planes of the FP16 multiply-accumulate
     WS_QMAX = 17,    // per-rhs max |q| (float bits), then the per-slice partial maxima
+    WS_FLAG = 18,    // one int: set when an input vector holds NaN or Inf
 };
 
 struct Skeleton {
@@ -282,5 +283,9 @@ void apply_precond(Ctx &c, const void *x, void *y, int nrhs, int prec, double be
 void apply_unpreconditioned(Ctx &c, const void *x, void *y, int nrhs);  // y = (D + B) x, FP64
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// AXS_ENONFINITE if any of the n complex128 values at v (device) is NaN or Inf;
+// synchronises the context's stream
+void require_finite(Ctx &c, const void *v, int64_t n, const char *what);
 
 }  // namespace axs

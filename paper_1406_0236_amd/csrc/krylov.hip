@@ -141,25 +141,42 @@ __global__ void cmatvec_small_kernel(const double2 *__restrict__ M, const double
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
+// sqrt of a squared norm from the device: NaN or Inf stay non-finite (so the
+// checks below see them), a tiny negative rounding becomes 0
+static double norm_from_sq(double s) { return std::isfinite(s) ? std::sqrt(std::max(0.0, s)) : NAN; }
+
 struct Dots {
     Ctx &c;
     int64_t N;
     int nrhs;
     int nblk;
+    int cap = 0;                 // vectors per rhs the buffers hold (grown on demand)
     double2 *partial = nullptr, *dev = nullptr;
     std::vector<double2> host;
     Dots(Ctx &c_, int64_t N_, int nrhs_, int maxvec) : c(c_), N(N_), nrhs(nrhs_) {
         nblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, ceil_div(N, 4096)));
-        partial = (double2 *)c.dalloc((size_t)nrhs * nblk * maxvec * sizeof(double2));
-        dev = (double2 *)c.dalloc((size_t)nrhs * maxvec * sizeof(double2));
-        host.resize((size_t)nrhs * maxvec);
+        reserve(std::min(maxvec, 16));
     }
     ~Dots() {
         c.dfree(partial);
         c.dfree(dev);
     }
+    // room for nvec coefficients per rhs; the old buffers are released in
+    // stream order (their last readers were queued on c.stream before)
+    void reserve(int nvec) {
+        if (nvec <= cap) return;
+        const int nc = std::max(nvec, 2 * cap);
+        c.dfree(partial);
+        c.dfree(dev);
+        partial = nullptr;
+        dev = nullptr;
+        partial = (double2 *)c.dalloc((size_t)nrhs * nblk * nc * sizeof(double2));
+        dev = (double2 *)c.dalloc((size_t)nrhs * nc * sizeof(double2));
+        cap = nc;
+    }
     // out[c][i] = V_i^H w on the device (stream-ordered, no host copy)
     void launch(const double2 *V, int64_t ldv, int nvec, const double2 *w, double2 *out) {
+        reserve(nvec);
         hipLaunchKernelGGL(cdot_many_kernel, dim3(nblk, nrhs), dim3(KR_BS), 0, c.stream, V, ldv, nvec, w, N,
                            partial);
         AXS_HIP(hipGetLastError());
@@ -169,7 +186,9 @@ struct Dots {
     }
     // h[c][i] = V_i^H w (device + host copies)
     void run(const double2 *V, int64_t ldv, int nvec, const double2 *w) {
+        reserve(nvec);
         launch(V, ldv, nvec, w, dev);
+        host.resize((size_t)nrhs * nvec);
         AXS_HIP(hipMemcpyAsync(host.data(), dev, (size_t)nvec * nrhs * sizeof(double2), hipMemcpyDeviceToHost,
                                c.stream));
         AXS_HIP(hipStreamSynchronize(c.stream));
@@ -206,22 +225,33 @@ static int verbose_level() {
     return v;
 }
 
-// Arnoldi/GMRES state for nrhs independent systems sharing the operator.
+// Arnoldi/GMRES state for nrhs independent systems sharing the operator.  The
+// Hessenberg columns and rotations grow one step at a time, so host memory
+// follows the iterations taken, not the iteration limit.
 struct Gmres {
     int nrhs, maxit;
-    std::vector<std::vector<cd>> H;        // per rhs: (maxit+1) x maxit column-major
+    std::vector<std::vector<std::vector<cd>>> H;   // per rhs, per column j: rows 0..j+1
     std::vector<std::vector<cd>> cs, sn, g;
     std::vector<int> done_at;              // iteration count at convergence (-1 = running)
     std::vector<double> bnorm;
     Gmres(int nrhs_, int maxit_) : nrhs(nrhs_), maxit(maxit_) {
-        H.assign(nrhs, std::vector<cd>((size_t)(maxit + 1) * maxit));
-        cs.assign(nrhs, std::vector<cd>(maxit));
-        sn.assign(nrhs, std::vector<cd>(maxit));
-        g.assign(nrhs, std::vector<cd>(maxit + 1));
+        H.assign(nrhs, {});
+        cs.assign(nrhs, {});
+        sn.assign(nrhs, {});
+        g.assign(nrhs, std::vector<cd>(1, 0.0));
         done_at.assign(nrhs, -1);
         bnorm.assign(nrhs, 1.0);
     }
-    cd &h(int c, int i, int j) { return H[c][(size_t)j * (maxit + 1) + i]; }
+    // start column j (zero) for every rhs
+    void open_column(int j) {
+        for (int c = 0; c < nrhs; ++c) {
+            H[c].emplace_back((size_t)j + 2, cd(0.0));
+            cs[c].push_back(0.0);
+            sn[c].push_back(0.0);
+            g[c].push_back(0.0);
+        }
+    }
+    cd &h(int c, int i, int j) { return H[c][j][i]; }
     // apply previous rotations to column j, build the new one; returns |g_{j+1}|
     double rotate(int c, int j) {
         for (int i = 0; i < j; ++i) {
@@ -318,7 +348,7 @@ struct Recycle {
 // columns per rhs ((maxit+1) x maxit column-major) and whether any step broke
 // down (a zero new vector) for that rhs.
 struct ArnoldiRecord {
-    std::vector<std::vector<cd>> H;
+    std::vector<std::vector<std::vector<cd>>> H;   // per rhs, per column j: rows 0..j+1
     std::vector<char> breakdown;
     int steps = 0;
 };
@@ -339,14 +369,15 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
     Gmres G(nrhs, maxit);
     G.bnorm = bnorm;
     Dots D(c, N, nrhs, maxit + 1);
-    double2 *hdev = (double2 *)c.dalloc((size_t)nrhs * (maxit + 1) * sizeof(double2));
     double *sdev = (double *)c.dalloc(nrhs * sizeof(double));
     // per Arnoldi step: both Gram-Schmidt passes' coefficients [nrhs][j+1] and
-    // the squared norm of the new vector [nrhs], read back in one copy
-    double2 *cdev = (double2 *)c.dalloc((size_t)nrhs * (2 * maxit + 1) * sizeof(double2));
-    std::vector<double2> chost((size_t)nrhs * (2 * maxit + 1));
+    // the squared norm of the new vector [nrhs], read back in one copy; the
+    // device buffer grows with the step (doubling), like the host copy
+    double2 *cdev = nullptr;
+    int64_t cdev_cap = 0;
+    std::vector<double2> chost;
     if (rec) {
-        rec->H.assign(nrhs, std::vector<cd>((size_t)(maxit + 1) * maxit, 0.0));
+        rec->H.assign(nrhs, {});
         rec->breakdown.assign(nrhs, 0);
         rec->steps = 0;
     }
@@ -400,7 +431,6 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
         start = V.vec(0);
     }
     auto release = [&]() {
-        c.dfree(hdev);
         c.dfree(sdev);
         c.dfree(cdev);
         c.dfree(adev);
@@ -412,7 +442,7 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
     rel_est.assign(nrhs, 0.0);
     bool all_done = true;
     for (int cc = 0; cc < nrhs; ++cc) {
-        beta[cc] = std::sqrt(std::max(0.0, D.get(cc, 0, 1).real()));
+        beta[cc] = norm_from_sq(D.get(cc, 0, 1).real());
         AXS_REQUIRE(std::isfinite(beta[cc]), AXS_ENONFINITE, "non-finite residual");
         G.g[cc][0] = beta[cc];
         inv[cc] = beta[cc] > 0 ? 1.0 / beta[cc] : 0.0;
@@ -443,6 +473,15 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
             // only synchronisation of the step
             const int nv = j + 1;
             const int64_t nh = (int64_t)nrhs * nv;
+            if (2 * nh + nrhs > cdev_cap) {
+                const int64_t cap = std::max<int64_t>(2 * nh + nrhs, 2 * cdev_cap);
+                c.dfree(cdev);
+                cdev = nullptr;
+                cdev = (double2 *)c.dalloc((size_t)cap * sizeof(double2));
+                cdev_cap = cap;
+            }
+            chost.resize((size_t)(2 * nh + nrhs));
+            G.open_column(j);
             for (int pass = 0; pass < 2; ++pass) {
                 if (rc) project_out(w, adev + (size_t)pass * nrhs * K);
                 double2 *hc = cdev + pass * nh;
@@ -463,7 +502,7 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
             AXS_HIP(hipStreamSynchronize(c.stream));
             all_done = true;
             for (int cc = 0; cc < nrhs; ++cc) {
-                const double hn = std::sqrt(std::max(0.0, chost[2 * nh + cc].x));
+                const double hn = norm_from_sq(chost[2 * nh + cc].x);
                 AXS_REQUIRE(std::isfinite(hn), AXS_ENONFINITE, "non-finite Arnoldi vector");
                 for (int i = 0; i < nv; ++i) {
                     const double2 a = chost[(size_t)cc * nv + i], b = chost[nh + (size_t)cc * nv + i];
@@ -471,7 +510,8 @@ static std::vector<int> gmres_core(Ctx &c, int64_t N, int nrhs, int maxit, doubl
                 }
                 G.h(cc, j + 1, j) = hn;
                 if (rec) {
-                    for (int i = 0; i <= nv; ++i) rec->H[cc][(size_t)j * (maxit + 1) + i] = G.h(cc, i, j);
+                    rec->H[cc].emplace_back((size_t)nv + 1, cd(0.0));
+                    for (int i = 0; i <= nv; ++i) rec->H[cc][j][i] = G.h(cc, i, j);
                     if (hn == 0.0) rec->breakdown[cc] = 1;
                 }
                 if (rc) {
@@ -557,7 +597,7 @@ static void build_recycle(Ctx &c, const ArnoldiRecord &rec, int maxit, const dou
         bool ok = true;
         for (int jj = 0; jj < k && ok; ++jj) {
             std::vector<cd> q(K);
-            for (int i = 0; i < K; ++i) q[i] = rec.H[cc][(size_t)jj * (maxit + 1) + i];
+            for (int i = 0; i < K; ++i) q[i] = i < (int)rec.H[cc][jj].size() ? rec.H[cc][jj][i] : cd(0.0);
             for (int pass = 0; pass < 2; ++pass)
                 for (int l = 0; l < jj; ++l) {
                     cd r = 0.0;
@@ -591,7 +631,7 @@ static std::vector<double> norms(Ctx &c, const double2 *v, int64_t N, int nrhs) 
     Dots D(c, N, nrhs, 1);
     D.run(v, N * nrhs, 1, v);
     std::vector<double> out(nrhs);
-    for (int cc = 0; cc < nrhs; ++cc) out[cc] = std::sqrt(std::max(0.0, D.get(cc, 0, 1).real()));
+    for (int cc = 0; cc < nrhs; ++cc) out[cc] = norm_from_sq(D.get(cc, 0, 1).real());
     return out;
 }
 

@@ -380,6 +380,36 @@ def test_error_paths():
 # the two-sphere workload (kappa = pi, N = 8200)
 # --------------------------------------------------------------------------
 
+def test_nonfinite_inputs_are_refused(small):
+    """A NaN or Inf in the incident field stops the solve with AXS_ENONFINITE; a NaN
+    or Inf density stops axs_apply_matvec, axs_apply_interbody and
+    axs_apply_precond before anything is computed (the output is left as it
+    was); a non-finite initial guess is not kept (the zero guess is used) and
+    the solve converges."""
+    from paper_1406_0236_amd import AxsError, FP32, FP64, SOLVE_FP64, SOLVE_MIXED
+    wl, S, ctx = small
+    v = ctx.incident_plane_waves(wl.dirs)
+    for bad in (float("nan"), float("inf")):
+        vb = v.clone()
+        vb[0, S.N // 2] = complex(bad, 0.0)
+        for mode in (SOLVE_FP64, SOLVE_MIXED):
+            with pytest.raises(AxsError, match="ENONFINITE"):
+                ctx.solve(vb, mode=mode, tol=1e-8)
+        x = _dev(_rand(S.N, 2, 31))
+        x[1, 7] = complex(0.0, bad)
+        for fn in (ctx.apply_matvec, ctx.apply_interbody, ctx.apply_precond):
+            for prec in (FP64, FP32):
+                out = torch.full_like(x, 3.0)
+                with pytest.raises(AxsError, match="ENONFINITE"):
+                    fn(x, prec, out=out)
+                assert torch.all(out == 3.0)
+    guess = torch.full_like(v, float("nan"))
+    sol, info = ctx.solve(v, sigma0=guess, mode=SOLVE_MIXED, tol=1e-9)
+    assert info[0]["used_warm_start"] == 0 and info[0]["converged"]
+    ref, _ = ctx.solve(v, mode=SOLVE_MIXED, tol=1e-9)
+    assert torch.equal(sol, ref)
+
+
 @pytest.fixture(scope="module")
 def c1(c1_system):
     wl, S = c1_system
@@ -744,7 +774,7 @@ def test_target_body_range_is_one_gpus_share(mixed):
     rows equal the full sum's bit for bit; with the default shape (splits
     chosen for the share) within rounding; the rows against the reference; the
     solves refuse while the range is set; (0, 0) restores every row."""
-    from paper_1406_0236_amd import FP32, FP64, AxsError
+    from paper_1406_0236_amd import FP32, FP64, SOLVE_MIXED, AxsError
     wl, S, ctx = mixed
     lo = sum(b.n_nodes for b in wl.bodies[:2])
     hi = sum(b.n_nodes for b in wl.bodies[:5])
@@ -760,6 +790,8 @@ def test_target_body_range_is_one_gpus_share(mixed):
             ctx.set_interbody_config(prec, 0, 0, 0, 0)
             with pytest.raises(AxsError, match="ESTATE"):
                 ctx.apply_matvec(x, prec)
+            with pytest.raises(AxsError, match="target-body range"):
+                ctx.solve(ctx.incident_plane_waves(wl.dirs[:1]), mode=SOLVE_MIXED, tol=1e-7)
         finally:
             ctx.set_target_bodies(0, 0)
         assert np.array_equal(pinned[:, lo:hi], full[:, lo:hi]), (prec, nrhs)

@@ -56,6 +56,14 @@ def test_skeleton_solve_matches_full_and_reference(which, c1_system, small_syste
               f"full-system residual {info[0]['rel_residual']:.2e}, error vs full solution {e:.2e}")
         assert e < 1e-8, e
         assert info[0]["rel_residual"] < 1e-8
+    # one GPU's share of the rows set: the compressed solve needs every row and refuses
+    from paper_1406_0236_amd import AxsError
+    ctx.set_target_bodies(1, 1)
+    try:
+        with pytest.raises(AxsError, match="target-body range"):
+            ctx.solve_skeleton(vd, mode=SOLVE_MIXED, tol=1e-8, certify=True)
+    finally:
+        ctx.set_target_bodies(0, 0)
     xr, _ = K.solve(v, tol=1e-13)
     e = _rel(ctx.solve_skeleton(vd, mode=SOLVE_FP64, tol=1e-12)[0].cpu().numpy()[0], xr)
     print(f"vs the reference compressed solve: {e:.2e}")
