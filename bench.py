@@ -11,10 +11,17 @@ matrices (FP64, on the GPU) is timed separately and is not part of a step.
 
 Prints one JSON line.  The roofline object is for the dominant kernel, the
 FP32 inter-body sum: 39 flop per (target, source) pair on different bodies,
-timed with HIP events on the library's stream.  Beside the step, the line
-reports the same problem solved through the ring skeletonization of Sec. 5
-(`skeleton`: ID time, kept unknowns, compressed mixed solve, residual of the
-lifted density in the full system).
+timed with HIP events on the library's stream.  Beside the step the line
+carries
+  - `skeleton`: the same problem through the ring skeletonization of Sec. 5;
+  - `c5`: the largest workload (64 mixed bodies in a 24^3 box, kappa = 4 pi,
+    N = 1,351,890, 16 plane waves): one mixed and one FP64 batched solve to
+    1e-7, iterations and explicit FP64 residuals;
+  - `warm_start`: the learned warm start on the 8 mixed bodies (network trained
+    on 4,096 of the method's own solves, k in [1.5 pi, 2.5 pi]), 512 held-out
+    (k, direction) pairs solved from three initial guesses: zero, the
+    single-body responses -D^{-1} v, and those plus the network's
+    multiple-scattering part.
 """
 from __future__ import annotations
 
@@ -98,6 +105,8 @@ def cpu_baseline(wl, iters_fp64, seconds_budget=15.0):
         "unit": "s",
         "cores": num_threads(),
         "kind": "oracle",
+        "extrapolated": True,
+        "rows_fraction": rows / S.N,
         "sample": (f"FP64 reference inter-body sum (C/OpenMP) on {rows} random rows of N={S.N}: "
                    f"{tt:.2f} s; x N/rows = {full:.1f} s per operator application, x {iters_fp64} "
                    f"(the FP64 GPU GMRES iteration count, one operator application each); the per-body preconditioner "
@@ -114,6 +123,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--small", action="store_true", help="two-sphere workload (quick check)")
+    ap.add_argument("--no-c5", action="store_true", help="leave out the 64-body leg")
+    ap.add_argument("--no-warm-start", action="store_true", help="leave out the learned warm-start leg")
     ap.add_argument("--learned", action="store_true",
                     help="learned warm start on the 8 mixed bodies: 64 wavenumbers x 64 directions of "
                          "training solves, 8 x 64 held out")
@@ -187,6 +198,7 @@ def main():
     if args.skeleton:
         return skeleton(args)
 
+    t_start = time.time()
     wl = configs.two_spheres() if args.small else configs.sphere_lattice()
     log(f"workload {wl.name}: N={wl.N}, pairs={wl.pairs:.4g}")
     torch.cuda.init()
@@ -359,65 +371,117 @@ def main():
         "cpu_baseline": cpu,
         "autotuned": tuned,
     }
-    print(json.dumps(out), flush=True)
     ctx.close()
+    del ctx, v, sol, x
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    # the other legs, each only if the run stays well inside ten minutes
+    # (estimates from measured runs: 64 bodies about 200 s, warm start about 60 s)
+    if not args.small and not args.no_c5:
+        left = 600.0 - (time.time() - t_start)
+        out["c5"] = c5_leg(args) if left > 330.0 else {"skipped": f"{left:.0f} s left of a 600 s run"}
+        torch.cuda.empty_cache()
+    if not args.small and not args.no_warm_start:
+        left = 600.0 - (time.time() - t_start)
+        out["warm_start"] = warm_start_leg() if left > 120.0 else {"skipped": f"{left:.0f} s left of a 600 s run"}
+    out["wall_s"] = time.time() - t_start
+    print(json.dumps(out), flush=True)
 
 
-def learned(args):
-    """Learned warm start: train on method-generated solves, evaluate held-out."""
+def c5_leg(args):
+    """64 mixed bodies, 16 plane waves: one mixed and one FP64 batched solve to
+    args.tol from the zero guess (no network is trained for this geometry),
+    library default launch shapes; explicit FP64 residuals of both solutions."""
+    import torch
+    from paper_1406_0236_amd import FP64, SOLVE_FP64, SOLVE_MIXED, Context
+    from workloads import configs
+    wl = configs.mixed_many()
+    r = len(wl.dirs)
+    log(f"c5: workload {wl.name}: N={wl.N}, pairs={wl.pairs:.4g}, rhs={r}")
+    ctx = Context(0).add_workload(wl)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    ctx.precompute_scattering()
+    torch.cuda.synchronize()
+    t_pre = time.time() - t0
+    v = ctx.incident_plane_waves(wl.dirs)
+    b_ = ctx.apply_precond(v, FP64)
+    bn = torch.linalg.norm(b_, dim=1)
+    res = {}
+    for mode, name in ((SOLVE_MIXED, "mixed"), (SOLVE_FP64, "fp64")):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        sol, info = ctx.solve(v, mode=mode, tol=args.tol)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        expl = (torch.linalg.norm(ctx.apply_matvec(sol, FP64) + b_, dim=1) / bn).max().item()
+        res[name] = {"s": dt, "outer": max(i["iterations"] for i in info),
+                     "inner": max(i["inner_iterations"] for i in info),
+                     "max_rel_residual": max(i["rel_residual"] for i in info),
+                     "max_explicit_rel_residual": expl, "converged": all(i["converged"] for i in info)}
+        log(f"c5 {name}: {dt:.1f} s, {res[name]}")
+        del sol
+    ctx.close()
+    return {"workload": wl.name, "bodies": len(wl.bodies), "N": wl.N, "kappa": wl.kappa, "nrhs": r,
+            "tol": args.tol, "precompute_s": t_pre, "interbody_pairs": wl.pairs, **res,
+            "speedup_mixed_vs_fp64": res["fp64"]["s"] / res["mixed"]["s"],
+            "initial_guess": "zero (the learned warm start is trained for the 8-body geometry only)"}
+
+
+def warm_start_leg(n_k=64, n_d=64, held_k=8, held_d=64, epochs=200, log_fn=None):
+    """The learned warm start on the 8 mixed bodies: training set of n_k
+    wavenumbers x n_d directions (seed 4), held out held_k x held_d (seed 40)."""
     import numpy as np
     import torch
     from paper_1406_0236_amd import Context
     from paper_1406_0236_amd import warmstart as W
     from workloads import configs
-
+    log_fn = log_fn or log
     wl_at = lambda k: configs.mixed_bodies(kappa=k, disc_kappa=W.K_MAX, n_dirs=1)
     rng = np.random.default_rng(4)
-    n_k, n_d = 64, 64
     ks = rng.uniform(W.K_MIN, W.K_MAX, n_k)
     dirs = [W.random_directions(n_d, rng) for _ in ks]
     t0 = time.time()
-    X, Y = W.generate(wl_at, ks, dirs, mmax=8, tol=1e-8, log=log)
+    X, Y = W.generate(wl_at, ks, dirs, mmax=8, tol=1e-8)
     t_gen = time.time() - t0
-    log(f"training set: {X.shape[0]} solves, {Y.shape[1]} outputs, {t_gen:.1f} s")
+    log_fn(f"warm start: training set {X.shape[0]} solves, {Y.shape[1]} outputs, {t_gen:.1f} s")
     dev = Context(0)
-    ws = W.WarmStart(dev, Y.shape[1], mmax=8, width=512, depth=4)
-    hist = ws.train(X, Y, epochs=200, batch=256, lr=1e-3, log=log)
+    ws = W.WarmStart(dev, Y.shape[1], width=512, depth=4)
+    hist = ws.train(X, Y, epochs=epochs, batch=256, lr=1e-3, log=log_fn)
+    del X, Y
     rng2 = np.random.default_rng(40)
-    hk = rng2.uniform(W.K_MIN, W.K_MAX, 8)
-    hd = [W.random_directions(64, rng2) for _ in hk]
-    rows = W.evaluate(ws, wl_at, hk, hd, tol=args.tol, log=log)
-    agg = {}
-    for mode in ("fp64", "mixed"):
-        agg[mode] = {key: float(np.mean([r[mode][key] for r in rows]))
-                     for key in ("zero_iters", "warm_iters", "zero_inner", "warm_inner", "zero_s", "warm_s")}
-        agg[mode]["warm_used_fraction"] = float(np.sum([r[mode]["warm_used"] for r in rows]) / (8 * 64))
-    agg["guess_rel_residual_mean"] = float(np.mean([r["guess_rel_residual"]["mean"] for r in rows]))
+    hk = rng2.uniform(W.K_MIN, W.K_MAX, held_k)
+    hd = [W.random_directions(held_d, rng2) for _ in hk]
+    rows = W.evaluate(ws, wl_at, hk, hd, tol=1e-7, log=log_fn)
+    agg = W.summarise(rows)
     wl = wl_at(W.K_MAX)
-    out = {
-        "metric": "s to 1e-7 residual with learned warm start vs zero guess (64 rhs per solve)",
-        "value": agg["mixed"]["warm_s"],
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": len(rows),
-        "warmup": 0,
-        "ms_per_step": agg["mixed"]["warm_s"] * 1e3,
-        "higher_is_better": False,
-        "scaling": "strong",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "mixed8_seed3 at k in [1.5 pi, 2.5 pi], discretised at 2.5 pi", "N": wl.N,
-                   "train_solves": int(X.shape[0]), "held_out": 8 * 64, "m_max": 8,
-                   "mlp": [4, 512, 512, 512, 512, int(Y.shape[1])], "epochs": 200, "batch": 256},
-        "held_out_mean": agg,
-        "per_k": rows,
-        "train_loss_first_last": [hist[0], hist[-1]],
-        "train_seconds": ws.train_seconds,
-        "generate_seconds": t_gen,
-    }
-    print(json.dumps(out), flush=True)
+    out = {"workload": "mixed8_seed3 at k in [1.5 pi, 2.5 pi], discretised at 2.5 pi", "N": wl.N,
+           "train_solves": n_k * n_d, "held_out": held_k * held_d, "m_max": 8,
+           "mlp": ws.mlp.sizes, "epochs": epochs, "batch": 256,
+           "train_loss_first_last": [hist[0], hist[-1]], "train_s": ws.train_seconds, "generate_s": t_gen,
+           "held_out_mean": agg,
+           "learned_vs_single_body": {
+               "guess_residual_ratio": agg["learned"]["guess_rel_residual"] / agg["single_body"]["guess_rel_residual"],
+               "fp64_iters_saved": agg["single_body"]["fp64_iters"] - agg["learned"]["fp64_iters"],
+               "mixed_s_ratio": agg["learned"]["mixed_s"] / agg["single_body"]["mixed_s"]},
+           "seconds_note": "per 64-rhs solve, mean over the held-out wavenumbers; the learned guess includes "
+                           "its prediction"}
+    ws.mlp.close()
+    dev.close()
+    torch.cuda.empty_cache()
+    return out
 
+
+def learned(args):
+    """The warm-start leg alone, as its own JSON line."""
+    out = warm_start_leg()
+    a = out["held_out_mean"]["learned"]
+    print(json.dumps({
+        "metric": "s to 1e-7 residual with the learned warm start (64 rhs per solve)",
+        "value": a["mixed_s"], "unit": "s", "n_gpus": 1, "steps": out["held_out"] // 64, "warmup": 0,
+        "ms_per_step": a["mixed_s"] * 1e3, "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic", "config": {"workload": out["workload"], "N": out["N"]},
+        "warm_start": out}), flush=True)
 
 
 def pmc_probe():

@@ -123,10 +123,14 @@ EXPORTS = {
                                              ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                              ctypes.POINTER(ctypes.c_double)]),
     "axs_warm_start_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]),
-    "axs_modes_from_density": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
-                                                ctypes.c_int, ctypes.c_void_p]),
-    "axs_density_from_modes": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
-                                                ctypes.c_int, ctypes.c_void_p]),
+    "axs_warm_start_encode": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_void_p]),
+    "axs_warm_start_decode": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_int, ctypes.c_void_p]),
+    "axs_mlp_train": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_char_p, ctypes.c_void_p]),
+    "axs_mlp_predict": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 
@@ -452,28 +456,64 @@ class Mlp:
 
 
 def warm_start_size(ctx: Context, mmax: int) -> int:
+    """axs_warm_start_size: floats per right-hand side of the warm-start layout."""
     n = ctypes.c_int64()
     ctx._check(ctx.lib.axs_warm_start_size(ctx.h, int(mmax), ctypes.byref(n)))
     return n.value
 
 
-def modes_from_density(ctx: Context, sigma, dirs, mmax: int):
+def _dirs(dirs, nrhs=None):
+    d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+    assert d.ndim == 2 and d.shape[1] == 3 and (nrhs is None or d.shape[0] == nrhs)
+    return d
+
+
+def warm_start_encode(ctx: Context, sigma, dirs, mmax: int):
+    """axs_warm_start_encode: training targets (float32 [nrhs][P]) of densities sigma."""
     torch = ctx._torch
     ps, nrhs = ctx._vec(sigma)
-    d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
-    assert d.shape == (nrhs, 3)
-    P = warm_start_size(ctx, mmax)
-    out = torch.empty((nrhs, P), dtype=torch.float32, device=sigma.device)
-    ctx._check(ctx.lib.axs_modes_from_density(ctx.h, ps, _ptr(d), nrhs, int(mmax), ctypes.c_void_p(out.data_ptr())))
+    d = _dirs(dirs, nrhs)
+    out = torch.empty((nrhs, warm_start_size(ctx, mmax)), dtype=torch.float32, device=sigma.device)
+    ctx._check(ctx.lib.axs_warm_start_encode(ctx.h, ps, _ptr(d), nrhs, int(mmax), ctypes.c_void_p(out.data_ptr())))
     return out
 
 
-def density_from_modes(ctx: Context, coeff, dirs, mmax: int):
+def warm_start_decode(ctx: Context, Y, dirs, mmax: int):
+    """axs_warm_start_decode: densities (complex128 [nrhs][N]) of the layout Y."""
     torch = ctx._torch
-    d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+    d = _dirs(dirs)
     nrhs = d.shape[0]
-    assert coeff.dtype == torch.float32 and coeff.is_contiguous() and coeff.shape == (nrhs, warm_start_size(ctx, mmax))
+    assert Y.dtype == torch.float32 and Y.is_cuda and Y.is_contiguous() and Y.shape == (nrhs, warm_start_size(ctx, mmax))
     out = ctx._empty(nrhs)
-    ctx._check(ctx.lib.axs_density_from_modes(ctx.h, ctypes.c_void_p(coeff.data_ptr()), _ptr(d), nrhs, int(mmax),
-                                              ctypes.c_void_p(out.data_ptr())))
+    ctx._check(ctx.lib.axs_warm_start_decode(ctx.h, ctypes.c_void_p(Y.data_ptr()), _ptr(d), nrhs, int(mmax),
+                                             ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def mlp_train(net: Mlp, X, Y, hparams: dict):
+    """axs_mlp_train; X float32 cuda [S][4] = (d, k), Y float32 cuda [S][n_out];
+    hparams as in include/axs.h.  Returns the per-epoch losses."""
+    import json
+    px, S = net._f32(X, net.sizes[0])
+    py, S2 = net._f32(Y, net.sizes[-1])
+    assert S == S2
+    epochs = int(hparams.get("epochs", 200))
+    losses = np.zeros(epochs, dtype=np.float64)
+    text = json.dumps({k: float(v) for k, v in hparams.items()}).encode()
+    net.ctx._check(net.lib.axs_mlp_train(net.h, px, py, S, text, _ptr(losses)))
+    return losses
+
+
+def mlp_predict(net: Mlp, ctx: Context, dirs, k_range, kappas=None):
+    """axs_mlp_predict: the initial guess (complex128 [nrhs][N]) on ctx for plane waves dirs."""
+    d = _dirs(dirs)
+    nrhs = d.shape[0]
+    kr = np.ascontiguousarray(k_range, dtype=np.float64)
+    assert kr.shape == (2,)
+    kp = None
+    if kappas is not None:
+        kp = np.ascontiguousarray(np.broadcast_to(np.asarray(kappas, dtype=np.float64), (nrhs,)))
+    out = ctx._empty(nrhs)
+    ctx._check(net.lib.axs_mlp_predict(net.h, ctx.h, _ptr(d), _ptr(kp) if kp is not None else None, nrhs, _ptr(kr),
+                                       ctypes.c_void_p(out.data_ptr())))
     return out

@@ -9,12 +9,23 @@
 // GEMMs run on the matrix cores (16x16x4 FP32 MFMA) with 64x64 block tiles
 // staged through LDS; the bias and GELU are fused into the GEMM epilogue.
 //
-// Warm-start encoding (the network's output): for body b, contour node i and
-// |m| <= m_max, c_{b,i,m} = e^{-i kappa d.c_b} (1/N_F) sum_l sigma e^{-i m th_l},
-// i.e. the low azimuthal modes of the density with the incident plane wave's
-// phase at the body centre taken out; decoding puts the phase back and sums
-// the modes.  Modes above m_max are zero in the decoded guess.
+// Warm-start encoding (the network's output).  From eq. "precond" the solution
+// satisfies sigma* = b~ - D^{-1} B sigma*, b~ = -D^{-1} v, and b~ (the
+// single-body responses) costs one preconditioner application.  The network
+// predicts only the rest, split by source body:
+//   sigma*_b - b~_b = sum_{b' != b} u^{b'}_b,   u^{b'}_b = -D_b^{-1} B_{bb'} sigma*_{b'},
+// the response of body b to the field radiated by body b'.  The leading phase
+// of that term, the incident wave's phase at c_{b'} carried over the distance
+// between the centres, phi_{bb'} = kappa (d.c_{b'} + |c_b - c_{b'}|), is taken
+// out, and the low azimuthal modes of the rest are the outputs:
+//   Y[b][s][i][m] = e^{-i phi_{bb'}} (1/N_F) sum_l u^{b'}_b(i, l) e^{-i m th_l},
+// s the index of b' among the bodies other than b (build order), |m| <= m_max.
+// Decoding puts the phases back, sums over the sources and the modes, and the
+// guess is b~ plus that sum.
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <string>
 
 #include "axs_internal.h"
 
@@ -205,66 +216,6 @@ __global__ void adam_kernel(float *__restrict__ p, float *__restrict__ m, float 
 }
 
 // ---------------------------------------------------------------------------
-// density <-> low modes (with the plane-wave phase at each body centre removed)
-// ---------------------------------------------------------------------------
-// coeff layout per rhs: bodies in order, contour node i, m = -mmax..mmax, (re, im)
-__global__ void modes_from_density_kernel(const BodyDev *__restrict__ bodies, const int64_t *__restrict__ coff,
-                                          const double *__restrict__ frame, const double2 *__restrict__ sigma,
-                                          const double *__restrict__ dirs, int64_t N, int64_t P, int mmax,
-                                          double kappa, int nb, float *__restrict__ coeff) {
-    const int b = blockIdx.y, c = blockIdx.z;
-    const BodyDev bd = bodies[b];
-    const int nm = 2 * mmax + 1;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= bd.NG * nm) return;
-    const int i = t / nm, mi = t % nm, m = mi - mmax;
-    const double *d = dirs + 3 * c;
-    const double ph = kappa * (d[0] * frame[FRAME * b] + d[1] * frame[FRAME * b + 1] + d[2] * frame[FRAME * b + 2]);
-    double sr = 0, si = 0;
-    const double2 *row = sigma + (int64_t)c * N + bd.offset + (int64_t)i * bd.NF;
-    for (int l = 0; l < bd.NF; ++l) {
-        double sn, cs;
-        sincospi(-2.0 * (double)(((int64_t)m * l) % bd.NF) / bd.NF, &sn, &cs);
-        sr += row[l].x * cs - row[l].y * sn;
-        si += row[l].x * sn + row[l].y * cs;
-    }
-    double pn, pc;
-    sincos(-ph, &pn, &pc);
-    const double re = (sr * pc - si * pn) / bd.NF, im = (sr * pn + si * pc) / bd.NF;
-    float *o = coeff + (int64_t)c * P + coff[b] + 2 * (int64_t)t;
-    o[0] = (float)re;
-    o[1] = (float)im;
-}
-
-__global__ void density_from_modes_kernel(const BodyDev *__restrict__ bodies, const int64_t *__restrict__ coff,
-                                          const double *__restrict__ frame, const float *__restrict__ coeff,
-                                          const double *__restrict__ dirs, int64_t N, int64_t P, int mmax,
-                                          double kappa, double2 *__restrict__ sigma) {
-    const int b = blockIdx.y, c = blockIdx.z;
-    const BodyDev bd = bodies[b];
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= bd.NG * bd.NF) return;
-    const int i = t / bd.NF, l = t % bd.NF;
-    const int nm = 2 * mmax + 1;
-    const double *d = dirs + 3 * c;
-    const double ph = kappa * (d[0] * frame[FRAME * b] + d[1] * frame[FRAME * b + 1] + d[2] * frame[FRAME * b + 2]);
-    const float *cf = coeff + (int64_t)c * P + coff[b] + 2 * (int64_t)i * nm;
-    double sr = 0, si = 0;
-    for (int mi = 0; mi < nm; ++mi) {
-        const int m = mi - mmax;
-        int64_t ml = ((int64_t)m * l) % bd.NF;
-        double sn, cs;
-        sincospi(2.0 * (double)ml / bd.NF, &sn, &cs);
-        const double ar = cf[2 * mi], ai = cf[2 * mi + 1];
-        sr += ar * cs - ai * sn;
-        si += ar * sn + ai * cs;
-    }
-    double pn, pc;
-    sincos(ph, &pn, &pc);
-    sigma[(int64_t)c * N + bd.offset + t] = make_double2(sr * pc - si * pn, sr * pn + si * pc);
-}
-
-// ---------------------------------------------------------------------------
 // host
 // ---------------------------------------------------------------------------
 static void ensure_batch(Mlp &n, int B) {
@@ -357,6 +308,41 @@ static void mlp_backward(Mlp &n, const float *T, int B) {
             gemm<false, true>(c, B, a, b, G, b, n.p + n.woff[k], b, nullptr, 0, nullptr, Gn, a);
             std::swap(G, Gn);
         }
+    }
+}
+
+
+// copy one epoch's row order (host, already checked) to the device; the copy is
+// complete on return, so the caller may reuse the host array
+static void load_order(Mlp &n, const int32_t *order, int64_t total) {
+    Ctx &c = *n.ctx;
+    if (total > n.cap_order) {
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        c.dfree(n.order);
+        n.order = nullptr;
+        n.order = (int32_t *)c.dalloc((size_t)total * sizeof(int32_t));
+        n.cap_order = total;
+    }
+    // after the previous epoch's steps (readers of n.order)
+    AXS_HIP(hipStreamSynchronize(c.stream));
+    AXS_HIP(hipMemcpyAsync(n.order, order, (size_t)total * sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
+    AXS_HIP(hipStreamSynchronize(c.stream));
+}
+
+// `steps` Adam steps on the rows n.order[s batch .. (s+1) batch) of X and T,
+// queued without synchronisation
+static void queue_steps(Mlp &n, const float *X, const float *T, int batch, int steps, const double *lr, double b1,
+                        double b2, double eps) {
+    Ctx &c = *n.ctx;
+    ensure_batch(n, batch);
+    const int L = (int)n.sizes.size() - 1;
+    for (int s = 0; s < steps; ++s) {
+        const int32_t *idx = n.order + (int64_t)s * batch;
+        gather_rows(c, X, n.sizes[0], idx, batch, n.H[0]);
+        gather_rows(c, T, n.sizes[L], idx, batch, n.Tb);
+        mlp_forward_h0(n, batch);
+        mlp_backward(n, n.Tb, batch);
+        adam_update(n, lr[s], b1, b2, eps);
     }
 }
 
@@ -521,28 +507,8 @@ axs_status axs_mlp_train_epoch(axs_mlp *h, const float *X, const float *T, int64
         for (int s = 0; s < steps; ++s) AXS_REQUIRE(lr[s] > 0, AXS_EINVAL, "learning rates must be positive");
         for (int64_t i = 0; i < total; ++i)
             AXS_REQUIRE(order[i] >= 0 && order[i] < rows, AXS_EINVAL, "row index out of range");
-        if (total > n.cap_order) {
-            AXS_HIP(hipStreamSynchronize(c.stream));
-            c.dfree(n.order);
-            n.order = nullptr;
-            n.order = (int32_t *)c.dalloc((size_t)total * sizeof(int32_t));
-            n.cap_order = total;
-        }
-        // after the previous epoch's steps (readers of n.order), and complete before the
-        // first step is queued, so the caller may reuse the host array on return
-        AXS_HIP(hipStreamSynchronize(c.stream));
-        AXS_HIP(hipMemcpyAsync(n.order, order, (size_t)total * sizeof(int32_t), hipMemcpyHostToDevice, c.stream));
-        AXS_HIP(hipStreamSynchronize(c.stream));
-        axs::ensure_batch(n, batch);
-        const int L = (int)n.sizes.size() - 1;
-        for (int s = 0; s < steps; ++s) {
-            const int32_t *idx = n.order + (int64_t)s * batch;
-            axs::gather_rows(c, X, n.sizes[0], idx, batch, n.H[0]);
-            axs::gather_rows(c, T, n.sizes[L], idx, batch, n.Tb);
-            axs::mlp_forward_h0(n, batch);
-            axs::mlp_backward(n, n.Tb, batch);
-            axs::adam_update(n, lr[s], b1, b2, eps);
-        }
+        axs::load_order(n, order, total);
+        axs::queue_steps(n, X, T, batch, steps, lr, b1, b2, eps);
         if (loss) {
             AXS_HIP(hipMemcpyAsync(loss, n.loss_dev, sizeof(double), hipMemcpyDeviceToHost, c.stream));
             AXS_HIP(hipStreamSynchronize(c.stream));
@@ -553,63 +519,425 @@ axs_status axs_mlp_train_epoch(axs_mlp *h, const float *X, const float *T, int64
 
 }  // extern "C"
 
+
+// ===========================================================================
+// Training, encoding, decoding and prediction of the warm start
+// ===========================================================================
 namespace axs {
-// shared by the two mode maps: per-body coefficient offsets (per rhs) and checks
-static int64_t mode_layout(Ctx &c, int mmax, std::vector<int64_t> &coff) {
-    coff.clear();
+
+// per-target-body offsets of the warm-start layout (per rhs); returns the
+// floats per rhs, 2 (B - 1) (2 m_max + 1) sum_b N_G(b)
+static int64_t ws_layout(const Ctx &c, int mmax, std::vector<int64_t> &toff) {
+    toff.clear();
+    const int64_t B = (int64_t)c.bodies.size();
     int64_t P = 0;
     for (auto &b : c.bodies) {
-        coff.push_back(P);
-        P += 2LL * c.shapes[b.shape].NG * (2 * mmax + 1);
+        toff.push_back(P);
+        P += 2 * (B - 1) * c.shapes[b.shape].NG * (2 * mmax + 1);
     }
     return P;
 }
+
+// e^{i phi}, phi = kappa (d_c . c_{b'} + |c_b - c_{b'}|), for rhs c, target b,
+// source slot s (b' = s for s < b, s + 1 otherwise): ph[(c nb + b) (nb - 1) + s]
+__global__ void ws_phase_kernel(const double *__restrict__ frame, const double *__restrict__ dirs, int nb, int nrhs,
+                                double kappa, double2 *__restrict__ ph) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)nb * (nb - 1);
+    if (t >= per * nrhs) return;
+    const int c = (int)(t / per), r = (int)(t % per), b = r / (nb - 1), s = r % (nb - 1);
+    const int bs = s < b ? s : s + 1;
+    const double *d = dirs + 3 * c, *cb = frame + FRAME * b, *cs = frame + FRAME * bs;
+    const double dx = cb[0] - cs[0], dy = cb[1] - cs[1], dz = cb[2] - cs[2];
+    const double phi = kappa * (d[0] * cs[0] + d[1] * cs[1] + d[2] * cs[2] + sqrt(dx * dx + dy * dy + dz * dz));
+    double sn, cn;
+    sincos(phi, &sn, &cn);
+    ph[t] = make_double2(cn, sn);
+}
+
+// out[(b' nch + c)][n] = sigma[c][n] on the nodes of body b', 0 elsewhere
+__global__ void mask_by_body_kernel(const double2 *__restrict__ sigma, const int64_t *__restrict__ body_off, int nb,
+                                    int nch, int64_t N, double2 *__restrict__ out) {
+    const int64_t total = (int64_t)nb * nch * N;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t n = t % N, z = t / N;
+        const int bp = (int)(z / nch), c = (int)(z % nch);
+        const bool in = n >= body_off[bp] && n < body_off[bp + 1];
+        out[t] = in ? sigma[(int64_t)c * N + n] : make_double2(0.0, 0.0);
+    }
+}
+
+// targets of one rhs chunk: u[(b' nch + c)][N] = -D^{-1} B (sigma_c masked to
+// body b'); Y[c][toff[b] + 2 ((s N_G + i) nm + mi)] for every target b and slot s
+__global__ void ws_encode_kernel(const BodyDev *__restrict__ bodies, const int64_t *__restrict__ toff,
+                                 const double2 *__restrict__ ph, const double2 *__restrict__ u, int64_t N, int64_t P,
+                                 int mmax, int nb, int nch, float *__restrict__ Y) {
+    const int b = blockIdx.y, z = blockIdx.z;
+    const int c = z / (nb - 1), s = z % (nb - 1);
+    const int bs = s < b ? s : s + 1;
+    const BodyDev bd = bodies[b];
+    const int nm = 2 * mmax + 1;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= bd.NG * nm) return;
+    const int i = t / nm, mi = t % nm, m = mi - mmax;
+    const double2 *row = u + ((int64_t)bs * nch + c) * N + bd.offset + (int64_t)i * bd.NF;
+    double sr = 0, si = 0;
+    for (int l = 0; l < bd.NF; ++l) {
+        double sn, cs;
+        sincospi(-2.0 * (double)(((int64_t)m * l) % bd.NF) / bd.NF, &sn, &cs);
+        sr += row[l].x * cs - row[l].y * sn;
+        si += row[l].x * sn + row[l].y * cs;
+    }
+    const double2 e = ph[((int64_t)c * nb + b) * (nb - 1) + s];   // multiply by conj(e) / N_F
+    const double re = (sr * e.x + si * e.y) / bd.NF, im = (si * e.x - sr * e.y) / bd.NF;
+    float *o = Y + (int64_t)c * P + toff[b] + 2 * (((int64_t)s * bd.NG + i) * nm + mi);
+    o[0] = (float)re;
+    o[1] = (float)im;
+}
+
+// sigma[c](b, i, l) (+)= sum_m e^{i m th_l} sum_s e^{i phi_{b b'_s}} Y[c][b][s][i][m]
+__global__ void ws_decode_kernel(const BodyDev *__restrict__ bodies, const int64_t *__restrict__ toff,
+                                 const double2 *__restrict__ ph, const float *__restrict__ Y, int64_t N, int64_t P,
+                                 int mmax, int nb, int add, double2 *__restrict__ sigma) {
+    const int b = blockIdx.y, c = blockIdx.z;
+    const BodyDev bd = bodies[b];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= bd.NG * bd.NF) return;
+    const int i = t / bd.NF, l = t % bd.NF;
+    const int nm = 2 * mmax + 1;
+    const double2 *e = ph + ((int64_t)c * nb + b) * (nb - 1);
+    const float *cf = Y + (int64_t)c * P + toff[b];
+    double sr = 0, si = 0;
+    for (int mi = 0; mi < nm; ++mi) {
+        double ar = 0, ai = 0;
+        for (int s = 0; s < nb - 1; ++s) {
+            const float *y = cf + 2 * (((int64_t)s * bd.NG + i) * nm + mi);
+            const double yr = y[0], yi = y[1];
+            ar += e[s].x * yr - e[s].y * yi;
+            ai += e[s].x * yi + e[s].y * yr;
+        }
+        const int64_t ml = ((int64_t)(mi - mmax) * l) % bd.NF;
+        double sn, cs;
+        sincospi(2.0 * (double)ml / bd.NF, &sn, &cs);
+        sr += ar * cs - ai * sn;
+        si += ar * sn + ai * cs;
+    }
+    double2 *o = sigma + (int64_t)c * N + bd.offset + t;
+    if (add) {
+        const double2 v = *o;
+        *o = make_double2(v.x + sr, v.y + si);
+    } else {
+        *o = make_double2(sr, si);
+    }
+}
+
+// network input: (d_x, d_y, d_z, (2 k - (k_min + k_max)) / (k_max - k_min)) from (d, k)
+__global__ void ws_features_kernel(const float *__restrict__ X, int64_t S, double kmin, double kmax,
+                                   float *__restrict__ Xs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S) return;
+    const float *x = X + 4 * t;
+    float *o = Xs + 4 * t;
+    o[0] = x[0];
+    o[1] = x[1];
+    o[2] = x[2];
+    o[3] = (float)((2.0 * (double)x[3] - (kmin + kmax)) / (kmax - kmin));
+}
+
+// per-block partial sums of squares (FP64), fixed order
+__global__ __launch_bounds__(256) void sumsq_f32_kernel(const float *__restrict__ a, int64_t n,
+                                                        double *__restrict__ part) {
+    __shared__ double red[256];
+    double s = 0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
+        const double v = a[t];
+        s += v * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out[0..n) = f * in[0..n)
+__global__ void scale_f32_kernel(const float *__restrict__ in, int64_t n, float f, float *__restrict__ out) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        out[t] = f * in[t];
+}
+
+static void scale_f32(Ctx &c, const float *in, int64_t n, float f, float *out) {
+    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ceil_div(n, 256)));
+    hipLaunchKernelGGL(scale_f32_kernel, dim3(nblk), dim3(256), 0, c.stream, in, n, f, out);
+    AXS_HIP(hipGetLastError());
+}
+
+// the number m_max with n_out = 2 (B - 1) (2 m_max + 1) sum N_G, or -1
+static int ws_mmax_for(const Ctx &c, int64_t nout) {
+    const int64_t B = (int64_t)c.bodies.size();
+    if (B < 2) return -1;
+    int64_t ng = 0;
+    for (auto &b : c.bodies) ng += c.shapes[b.shape].NG;
+    const int64_t unit = 2 * (B - 1) * ng;
+    if (nout % unit) return -1;
+    const int64_t nm = nout / unit;
+    if (nm % 2 == 0) return -1;
+    return (int)((nm - 1) / 2);
+}
+
+static void ws_check_mmax(const Ctx &c, int mmax) {
+    AXS_REQUIRE(c.bodies.size() >= 2, AXS_EINVAL, "the warm start needs at least two bodies");
+    AXS_REQUIRE(mmax >= 0, AXS_EINVAL, "m_max must be >= 0");
+    for (auto &s : c.shapes) AXS_REQUIRE(mmax <= s.M, AXS_EINVAL, "m_max exceeds a body's mode cutoff");
+}
+
+// device copies of the layout offsets and the phase table for nrhs directions
+struct WsTables {
+    Ctx &c;
+    int64_t *toff = nullptr;
+    double *dirs = nullptr;
+    double2 *ph = nullptr;
+    WsTables(Ctx &c_, const std::vector<int64_t> &off, const double *dirs_host, int nrhs) : c(c_) {
+        const int nb = (int)c.bodies.size();
+        toff = (int64_t *)c.dalloc(off.size() * sizeof(int64_t));
+        dirs = (double *)c.dalloc((size_t)3 * nrhs * sizeof(double));
+        ph = (double2 *)c.dalloc((size_t)nrhs * nb * (nb - 1) * sizeof(double2));
+        AXS_HIP(hipMemcpy(toff, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        AXS_HIP(hipMemcpy(dirs, dirs_host, (size_t)3 * nrhs * sizeof(double), hipMemcpyHostToDevice));
+        const int64_t n = (int64_t)nrhs * nb * (nb - 1);
+        hipLaunchKernelGGL(ws_phase_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c.stream, c.frame64, dirs,
+                           nb, nrhs, c.kappa, ph);
+        AXS_HIP(hipGetLastError());
+    }
+    ~WsTables() {
+        (void)hipStreamSynchronize(c.stream);
+        c.dfree(toff);
+        c.dfree(dirs);
+        c.dfree(ph);
+    }
+};
+
+static void ws_decode(Ctx &c, const WsTables &T, const float *Y, int64_t P, int mmax, int nrhs, bool add,
+                      double2 *sigma) {
+    int maxn = 0;
+    for (auto &s : c.shapes) maxn = std::max(maxn, s.NG * s.NF);
+    const int nb = (int)c.bodies.size();
+    dim3 grid((unsigned)ceil_div(maxn, 128), nb, nrhs);
+    hipLaunchKernelGGL(ws_decode_kernel, grid, dim3(128), 0, c.stream, c.body_dev, T.toff, T.ph, Y, c.N, P, mmax, nb,
+                       add ? 1 : 0, sigma);
+    AXS_HIP(hipGetLastError());
+}
+
+static void check_dirs(const double *dirs, int nrhs) {
+    for (int i = 0; i < 3 * nrhs; ++i) AXS_REQUIRE(std::isfinite(dirs[i]), AXS_ENONFINITE, "non-finite direction");
+}
+
+// ---------------------------------------------------------------------------
+// hyperparameters: a flat JSON object of numbers
+// ---------------------------------------------------------------------------
+struct TrainParams {
+    double epochs = 200, batch = 256, lr = 1e-3, lr_final = 1e-5, beta1 = 0.9, beta2 = 0.999, eps = 1e-8;
+    double seed = 5, init_seed = 4, k_min = NAN, k_max = NAN;
+};
+
+static TrainParams parse_hparams(const char *txt) {
+    TrainParams hp;
+    struct Key {
+        const char *name;
+        double *dst;
+    } keys[] = {{"epochs", &hp.epochs}, {"batch", &hp.batch},   {"lr", &hp.lr},
+                {"lr_final", &hp.lr_final}, {"beta1", &hp.beta1}, {"beta2", &hp.beta2},
+                {"eps", &hp.eps},           {"seed", &hp.seed},   {"init_seed", &hp.init_seed},
+                {"k_min", &hp.k_min},       {"k_max", &hp.k_max}};
+    const char *p = txt;
+    auto ws = [&]() {
+        while (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r') ++p;
+    };
+    ws();
+    AXS_REQUIRE(*p == '{', AXS_EINVAL, "hparams: expected a JSON object");
+    ++p;
+    ws();
+    if (*p == '}') {
+        ++p;
+    } else {
+        for (;;) {
+            ws();
+            AXS_REQUIRE(*p == '"', AXS_EINVAL, "hparams: expected a quoted key");
+            const char *k0 = ++p;
+            while (*p && *p != '"') ++p;
+            AXS_REQUIRE(*p == '"', AXS_EINVAL, "hparams: unterminated key");
+            const std::string key(k0, p - k0);
+            ++p;
+            ws();
+            AXS_REQUIRE(*p == ':', AXS_EINVAL, "hparams: expected ':'");
+            ++p;
+            ws();
+            char *end = nullptr;
+            const double v = std::strtod(p, &end);
+            AXS_REQUIRE(end != p, AXS_EINVAL, "hparams: value of \"" + key + "\" is not a number");
+            p = end;
+            bool known = false;
+            for (auto &k : keys)
+                if (key == k.name) {
+                    *k.dst = v;
+                    known = true;
+                }
+            AXS_REQUIRE(known, AXS_EINVAL, "hparams: unknown key \"" + key + "\"");
+            ws();
+            if (*p == ',') {
+                ++p;
+                continue;
+            }
+            AXS_REQUIRE(*p == '}', AXS_EINVAL, "hparams: expected ',' or '}'");
+            ++p;
+            break;
+        }
+    }
+    ws();
+    AXS_REQUIRE(*p == 0, AXS_EINVAL, "hparams: trailing characters");
+    return hp;
+}
+
+// counter-based generator (splitmix64 of seed + counter)
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ULL;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+    return x ^ (x >> 31);
+}
+static double uniform01(uint64_t seed, uint64_t k) {   // in (0, 1)
+    return ((double)(splitmix64(seed * 0x632be59bd9b4e019ULL + k) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+// He initialisation: W_k ~ N(0, 2 / fan_in) by Box-Muller, biases zero
+static void he_init(Mlp &n, uint64_t seed) {
+    std::vector<float> p((size_t)n.nparams, 0.f);
+    uint64_t k = 0;
+    for (size_t l = 0; l + 1 < n.sizes.size(); ++l) {
+        const int64_t a = n.sizes[l], b = n.sizes[l + 1];
+        const double sd = std::sqrt(2.0 / (double)a);
+        for (int64_t e = 0; e < a * b; ++e, k += 2) {
+            const double u1 = uniform01(seed, k), u2 = uniform01(seed, k + 1);
+            p[(size_t)(n.woff[l] + e)] = (float)(sd * std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2));
+        }
+    }
+    AXS_HIP(hipMemcpy(n.p, p.data(), p.size() * sizeof(float), hipMemcpyHostToDevice));
+}
+
+static void reset_adam(Mlp &n) {
+    AXS_HIP(hipMemsetAsync(n.m, 0, n.nparams * sizeof(float), n.ctx->stream));
+    AXS_HIP(hipMemsetAsync(n.v, 0, n.nparams * sizeof(float), n.ctx->stream));
+    n.step = 0;
+}
+
+// multiply the last layer (weights and bias) by f: the network's output scales by f
+static void scale_last_layer(Mlp &n, float f) {
+    const size_t L = n.sizes.size() - 1;
+    const int64_t off = n.woff[L - 1], len = n.nparams - off;
+    scale_f32(*n.ctx, n.p + off, len, f, n.p + off);
+}
+
+// root mean square of n floats on the device
+static double rms_f32(Ctx &c, const float *a, int64_t n) {
+    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(n, 256)));
+    double *part = (double *)c.dalloc((size_t)nblk * sizeof(double));
+    hipLaunchKernelGGL(sumsq_f32_kernel, dim3(nblk), dim3(256), 0, c.stream, a, n, part);
+    AXS_HIP(hipGetLastError());
+    std::vector<double> h(nblk);
+    AXS_HIP(hipMemcpyAsync(h.data(), part, (size_t)nblk * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+    AXS_HIP(hipStreamSynchronize(c.stream));
+    c.dfree(part);
+    double s = 0;
+    for (double v : h) s += v;
+    return std::sqrt(s / (double)n);
+}
+
 }  // namespace axs
 
 extern "C" {
 
 axs_status axs_warm_start_size(axs_ctx *ctx, int mmax, int64_t *P) {
-    if (!ctx || !P || mmax < 0) return AXS_EINVAL;
-    std::vector<int64_t> coff;
-    *P = axs::mode_layout(ctx->c, mmax, coff);
-    return AXS_OK;
+    if (!ctx || !P) return AXS_EINVAL;
+    Ctx &c = ctx->c;
+    c.err.clear();
+    try {
+        axs::ws_check_mmax(c, mmax);
+        std::vector<int64_t> toff;
+        *P = axs::ws_layout(c, mmax, toff);
+        return AXS_OK;
+    } catch (const Error &e) {
+        c.err = e.msg;
+        return e.code;
+    }
 }
 
-static axs_status mode_map(axs_ctx *ctx, bool to_modes, const void *sigma, const float *coeff_in, float *coeff_out,
-                           const double *dirs, int nrhs, int mmax, void *sigma_out) {
+axs_status axs_warm_start_encode(axs_ctx *ctx, const void *sigma, const double *dirs, int nrhs, int mmax, float *Y) {
     if (!ctx) return AXS_EINVAL;
     Ctx &c = ctx->c;
     c.err.clear();
     try {
         AXS_REQUIRE(c.precomputed, AXS_ESTATE, "call axs_precompute_scattering first");
-        AXS_REQUIRE(dirs && nrhs >= 1 && nrhs <= 4096 && mmax >= 0, AXS_EINVAL, "bad arguments");
-        for (auto &s : c.shapes) AXS_REQUIRE(mmax <= s.M, AXS_EINVAL, "m_max exceeds a body's mode cutoff");
-        std::vector<int64_t> coff;
-        const int64_t P = axs::mode_layout(c, mmax, coff);
-        const size_t extra = coff.size() * sizeof(int64_t) + 3 * nrhs * sizeof(double);
-        char *d = (char *)c.scratch(axs::WS_EVAL, extra);
-        AXS_HIP(hipMemcpy(d, coff.data(), coff.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-        AXS_HIP(hipMemcpy(d + coff.size() * sizeof(int64_t), dirs, 3 * nrhs * sizeof(double), hipMemcpyHostToDevice));
-        const int64_t *dcoff = (const int64_t *)d;
-        const double *ddirs = (const double *)(d + coff.size() * sizeof(int64_t));
-        int maxng = 0, maxn = 0;
-        for (auto &s : c.shapes) {
-            maxng = std::max(maxng, s.NG);
-            maxn = std::max(maxn, s.NG * s.NF);
-        }
+        AXS_REQUIRE(c.tgt_count < 0, AXS_ESTATE, "a target-body range is set (axs_set_target_bodies)");
+        AXS_REQUIRE(sigma && dirs && Y && nrhs >= 1 && nrhs <= 4096, AXS_EINVAL, "bad arguments");
+        axs::ws_check_mmax(c, mmax);
+        axs::check_dirs(dirs, nrhs);
+        axs::require_finite(c, sigma, (int64_t)nrhs * c.N, "sigma");
+        std::vector<int64_t> toff;
+        const int64_t P = axs::ws_layout(c, mmax, toff);
+        axs::WsTables T(c, toff, dirs, nrhs);
         const int nb = (int)c.bodies.size();
-        if (to_modes) {
-            AXS_REQUIRE(sigma && coeff_out, AXS_EINVAL, "null vector");
-            dim3 grid((unsigned)axs::ceil_div((int64_t)maxng * (2 * mmax + 1), 128), nb, nrhs);
-            hipLaunchKernelGGL(axs::modes_from_density_kernel, grid, dim3(128), 0, c.stream, c.body_dev, dcoff,
-                               c.frame64, (const double2 *)sigma, ddirs, c.N, P, mmax, c.kappa, nb, coeff_out);
-        } else {
-            AXS_REQUIRE(coeff_in && sigma_out, AXS_EINVAL, "null vector");
-            dim3 grid((unsigned)axs::ceil_div(maxn, 128), nb, nrhs);
-            hipLaunchKernelGGL(axs::density_from_modes_kernel, grid, dim3(128), 0, c.stream, c.body_dev, dcoff,
-                               c.frame64, coeff_in, ddirs, c.N, P, mmax, c.kappa, (double2 *)sigma_out);
+        // rhs per chunk: the masked copies (nb per rhs) stay within one inter-body
+        // application (4096 rhs) and about 512 MiB per buffer
+        const int64_t per_rhs = (int64_t)nb * c.N * (int64_t)sizeof(double2);
+        const int nch = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nrhs, 4096 / nb,
+                                                                      ((int64_t)512 << 20) / per_rhs}));
+        double2 *masked = (double2 *)c.dalloc((size_t)nch * per_rhs);
+        double2 *bsum = (double2 *)c.dalloc((size_t)nch * per_rhs);
+        double2 *u = (double2 *)c.dalloc((size_t)nch * per_rhs);
+        int maxng = 0;
+        for (auto &s : c.shapes) maxng = std::max(maxng, s.NG);
+        for (int c0 = 0; c0 < nrhs; c0 += nch) {
+            const int ch = std::min(nch, nrhs - c0);
+            const int64_t tot = (int64_t)nb * ch * c.N;
+            const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(8192, axs::ceil_div(tot, 256)));
+            hipLaunchKernelGGL(axs::mask_by_body_kernel, dim3(nblk), dim3(256), 0, c.stream,
+                               (const double2 *)sigma + (int64_t)c0 * c.N, c.body_off, nb, ch, c.N, masked);
+            AXS_HIP(hipGetLastError());
+            axs::interbody_partials(c, masked, nb * ch, AXS_FP64);
+            axs::interbody_reduce_to_c128(c, bsum, nb * ch, AXS_FP64);
+            axs::apply_precond(c, bsum, u, nb * ch, AXS_FP64, -1.0);
+            dim3 grid((unsigned)axs::ceil_div((int64_t)maxng * (2 * mmax + 1), 128), nb, ch * (nb - 1));
+            hipLaunchKernelGGL(axs::ws_encode_kernel, grid, dim3(128), 0, c.stream, c.body_dev, T.toff,
+                               T.ph + (int64_t)c0 * nb * (nb - 1), u, c.N, P, mmax, nb, ch, Y + (int64_t)c0 * P);
+            AXS_HIP(hipGetLastError());
         }
-        AXS_HIP(hipGetLastError());
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        c.dfree(masked);
+        c.dfree(bsum);
+        c.dfree(u);
+        return AXS_OK;
+    } catch (const Error &e) {
+        c.err = e.msg;
+        return e.code;
+    }
+}
+
+axs_status axs_warm_start_decode(axs_ctx *ctx, const float *Y, const double *dirs, int nrhs, int mmax,
+                                 void *sigma) {
+    if (!ctx) return AXS_EINVAL;
+    Ctx &c = ctx->c;
+    c.err.clear();
+    try {
+        AXS_REQUIRE(c.precomputed, AXS_ESTATE, "call axs_precompute_scattering first");
+        AXS_REQUIRE(sigma && dirs && Y && nrhs >= 1 && nrhs <= 4096, AXS_EINVAL, "bad arguments");
+        axs::ws_check_mmax(c, mmax);
+        axs::check_dirs(dirs, nrhs);
+        std::vector<int64_t> toff;
+        const int64_t P = axs::ws_layout(c, mmax, toff);
+        axs::WsTables T(c, toff, dirs, nrhs);
+        axs::ws_decode(c, T, Y, P, mmax, nrhs, false, (double2 *)sigma);
         AXS_HIP(hipStreamSynchronize(c.stream));
         return AXS_OK;
     } catch (const Error &e) {
@@ -618,14 +946,129 @@ static axs_status mode_map(axs_ctx *ctx, bool to_modes, const void *sigma, const
     }
 }
 
-axs_status axs_modes_from_density(axs_ctx *ctx, const void *sigma, const double *dirs, int nrhs, int mmax,
-                                  float *coeff) {
-    return mode_map(ctx, true, sigma, nullptr, coeff, dirs, nrhs, mmax, nullptr);
+axs_status axs_mlp_train(axs_mlp *h, const float *X, const float *Y, int64_t S, const char *hparams,
+                         double *loss_per_epoch) {
+    if (!hparams) return AXS_EINVAL;
+    return mlp_guarded(h, [&](Mlp &n, Ctx &c) -> axs_status {
+        AXS_REQUIRE(X && Y && S >= 1, AXS_EINVAL, "bad arguments");
+        AXS_REQUIRE(S <= INT32_MAX, AXS_EINVAL, "more than 2^31 - 1 samples");
+        AXS_REQUIRE(n.sizes.front() == 4, AXS_EINVAL, "the network input must be (d_x, d_y, d_z, k)");
+        const axs::TrainParams hp = axs::parse_hparams(hparams);
+        AXS_REQUIRE(std::isfinite(hp.k_min) && std::isfinite(hp.k_max) && hp.k_max > hp.k_min, AXS_EINVAL,
+                    "hparams: k_min < k_max are required");
+        AXS_REQUIRE(hp.epochs >= 1 && hp.epochs <= 1e6 && hp.batch >= 1 && hp.batch <= 65536, AXS_EINVAL,
+                    "hparams: epochs in [1, 1e6], batch in [1, 65536]");
+        AXS_REQUIRE(hp.lr > 0 && hp.lr_final > 0 && hp.beta1 >= 0 && hp.beta1 < 1 && hp.beta2 >= 0 &&
+                        hp.beta2 < 1 && hp.eps > 0,
+                    AXS_EINVAL, "hparams: lr, lr_final, eps > 0 and beta1, beta2 in [0, 1)");
+        const int epochs = (int)hp.epochs;
+        const int batch = (int)std::min<int64_t>((int64_t)hp.batch, S);
+        const int L = (int)n.sizes.size() - 1;
+        const int64_t nout = n.sizes[L];
+        // target scale: the root mean square of Y, folded into the last layer at the end
+        double scale = axs::rms_f32(c, Y, S * nout);
+        AXS_REQUIRE(std::isfinite(scale), AXS_ENONFINITE, "non-finite training targets");
+        if (!(scale > 0)) scale = 1.0;
+        float *Xs = (float *)c.dalloc((size_t)S * 4 * sizeof(float));
+        float *Ys = (float *)c.dalloc((size_t)S * nout * sizeof(float));
+        hipLaunchKernelGGL(axs::ws_features_kernel, dim3((unsigned)axs::ceil_div(S, 256)), dim3(256), 0, c.stream, X,
+                           S, hp.k_min, hp.k_max, Xs);
+        AXS_HIP(hipGetLastError());
+        axs::scale_f32(c, Y, S * nout, (float)(1.0 / scale), Ys);
+        if (hp.init_seed >= 0)
+            axs::he_init(n, (uint64_t)hp.init_seed);
+        else
+            axs::scale_last_layer(n, (float)(1.0 / scale));   // continue from the current network
+        axs::reset_adam(n);
+        const int steps = (int)std::max<int64_t>(1, S / batch);
+        const int64_t total = (int64_t)epochs * steps;
+        std::vector<int32_t> perm((size_t)S), order((size_t)steps * batch);
+        std::vector<double> lrs(steps);
+        const uint64_t seed = (uint64_t)hp.seed;
+        uint64_t draw = 0;
+        for (int ep = 0; ep < epochs; ++ep) {
+            // a fresh permutation per epoch (Fisher-Yates); its first steps x batch rows
+            for (int64_t i = 0; i < S; ++i) perm[(size_t)i] = (int32_t)i;
+            for (int64_t i = S - 1; i > 0; --i) {
+                const int64_t j = (int64_t)(axs::uniform01(seed, draw++) * (double)(i + 1));
+                std::swap(perm[(size_t)i], perm[(size_t)std::min(j, i)]);
+            }
+            std::copy(perm.begin(), perm.begin() + (int64_t)steps * batch, order.begin());
+            // cosine decay from lr to lr_final over all steps
+            for (int s = 0; s < steps; ++s) {
+                const double t = (double)((int64_t)ep * steps + s) / (double)std::max<int64_t>(1, total - 1);
+                lrs[s] = hp.lr_final + 0.5 * (hp.lr - hp.lr_final) * (1.0 + std::cos(M_PI * t));
+            }
+            axs::load_order(n, order.data(), (int64_t)steps * batch);
+            axs::queue_steps(n, Xs, Ys, batch, steps, lrs.data(), hp.beta1, hp.beta2, hp.eps);
+            if (loss_per_epoch) {
+                AXS_HIP(hipMemcpyAsync(&loss_per_epoch[ep], n.loss_dev, sizeof(double), hipMemcpyDeviceToHost,
+                                       c.stream));
+                AXS_HIP(hipStreamSynchronize(c.stream));
+            }
+        }
+        axs::scale_last_layer(n, (float)scale);
+        axs::reset_adam(n);
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        c.dfree(Xs);
+        c.dfree(Ys);
+        return AXS_OK;
+    });
 }
 
-axs_status axs_density_from_modes(axs_ctx *ctx, const float *coeff, const double *dirs, int nrhs, int mmax,
-                                  void *sigma) {
-    return mode_map(ctx, false, nullptr, coeff, nullptr, dirs, nrhs, mmax, sigma);
+axs_status axs_mlp_predict(axs_mlp *h, axs_ctx *ctx, const double *dirs, const double *kappas, int nrhs,
+                           const double k_range[2], void *sigma0) {
+    if (!h || !h->n.ctx || !ctx) return AXS_EINVAL;
+    Ctx &c = ctx->c;
+    Mlp &n = h->n;
+    c.err.clear();
+    try {
+        AXS_REQUIRE(c.precomputed, AXS_ESTATE, "call axs_precompute_scattering first");
+        AXS_REQUIRE(c.tgt_count < 0, AXS_ESTATE, "a target-body range is set (axs_set_target_bodies)");
+        AXS_REQUIRE(n.ctx->device == c.device, AXS_EINVAL, "network and context on different devices");
+        AXS_REQUIRE(dirs && k_range && sigma0 && nrhs >= 1 && nrhs <= 4096, AXS_EINVAL, "bad arguments");
+        AXS_REQUIRE(std::isfinite(k_range[0]) && std::isfinite(k_range[1]) && k_range[1] > k_range[0], AXS_EINVAL,
+                    "k_range must be finite with k_range[0] < k_range[1]");
+        AXS_REQUIRE(n.sizes.front() == 4, AXS_EINVAL, "the network input must be (d_x, d_y, d_z, k)");
+        const int L = (int)n.sizes.size() - 1;
+        const int mmax = axs::ws_mmax_for(c, n.sizes[L]);
+        AXS_REQUIRE(mmax >= 0, AXS_EINVAL, "the network's output size is not the warm-start layout of this context");
+        axs::ws_check_mmax(c, mmax);
+        axs::check_dirs(dirs, nrhs);
+        if (kappas)
+            for (int i = 0; i < nrhs; ++i)
+                AXS_REQUIRE(std::fabs(kappas[i] - c.kappa) <= 1e-12 * std::max(1.0, c.kappa), AXS_EINVAL,
+                            "kappas must equal the context's wavenumber (its discretisation and matrices are for it)");
+        // features and the forward pass on the network's stream
+        std::vector<float> xf((size_t)4 * nrhs);
+        const double ks = (2.0 * c.kappa - (k_range[0] + k_range[1])) / (k_range[1] - k_range[0]);
+        for (int i = 0; i < nrhs; ++i) {
+            for (int a = 0; a < 3; ++a) xf[(size_t)4 * i + a] = (float)dirs[3 * i + a];
+            xf[(size_t)4 * i + 3] = (float)ks;
+        }
+        float *xd = (float *)n.ctx->dalloc(xf.size() * sizeof(float));
+        AXS_HIP(hipMemcpy(xd, xf.data(), xf.size() * sizeof(float), hipMemcpyHostToDevice));
+        axs::mlp_forward(n, xd, nrhs);
+        AXS_HIP(hipStreamSynchronize(n.ctx->stream));
+        n.ctx->dfree(xd);
+        // sigma0 = b~ = -D^{-1} v, then the decoded multiple-scattering part on top
+        std::vector<int64_t> toff;
+        const int64_t P = axs::ws_layout(c, mmax, toff);
+        axs::WsTables T(c, toff, dirs, nrhs);
+        double2 *v = (double2 *)c.dalloc((size_t)nrhs * c.N * sizeof(double2));
+        axs::incident_plane_launch(c, T.dirs, nrhs, v);
+        axs::apply_precond(c, v, sigma0, nrhs, AXS_FP64, -1.0);
+        axs::ws_decode(c, T, n.H[L], P, mmax, nrhs, true, (double2 *)sigma0);
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        c.dfree(v);
+        return AXS_OK;
+    } catch (const Error &e) {
+        c.err = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        c.err = e.what();
+        return AXS_EINVAL;
+    }
 }
 
 }  // extern "C"

@@ -73,6 +73,20 @@ def test_null_handles_are_rejected(lib):
     assert lib.axs_num_unknowns(None, ctypes.byref(n)) == -1
 
 
+def test_warm_start_entry_points_reject_bad_handles(lib):
+    """Training, prediction and the warm-start encoding refuse null handles and a
+    missing hyperparameter string before touching a device."""
+    n = ctypes.c_int64()
+    kr = (ctypes.c_double * 2)(1.0, 2.0)
+    assert lib.axs_mlp_train(None, None, None, 1, b'{"k_min": 1, "k_max": 2}', None) == -1
+    assert lib.axs_mlp_train(None, None, None, 1, None, None) == -1
+    assert lib.axs_mlp_predict(None, None, None, None, 1, kr, None) == -1
+    assert lib.axs_warm_start_size(None, 8, ctypes.byref(n)) == -1
+    assert lib.axs_warm_start_encode(None, None, None, 1, 8, None) == -1
+    assert lib.axs_warm_start_decode(None, None, None, 1, 8, None) == -1
+    assert lib.axs_mlp_destroy(None) == -1
+
+
 def test_create_rejects_bad_arguments(lib):
     from paper_1406_0236_amd import _lib
     h = ctypes.c_void_p()

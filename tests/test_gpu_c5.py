@@ -5,8 +5,9 @@ At this size the FP64 reference computes sampled outputs one by one: rows of the
 inter-body sum over all 1.35 million sources for 16 right-hand sides (FP32 in
 the launch shape the library picks for 16 rhs -- the MFMA order with the
 FP16 multiply-accumulate -- and FP64),
-and rows of the modal matrices of the bowl and of the most elongated spheroid.
-Tolerances as in test_gpu_fullsize.py."""
+and rows of the modal matrices of the bowl and of the most elongated spheroid;
+and the residual of the bench's 16-rhs mixed solve on every row of those two
+bodies.  Tolerances as in test_gpu_fullsize.py."""
 import numpy as np
 import pytest
 
@@ -67,3 +68,49 @@ def test_c5_modal_matrix_rows(many):
             e = rel(A[:, i, :], row)
             print(f"{kind} body {b} (NG={sh.NG}, M={sh.M}) row {i}: rel err {e:.2e}", flush=True)
             assert e < 1e-9, e
+
+
+@pytest.mark.timeout(900)
+def test_c5_mixed_solve_certified_on_a_bowl_and_the_longest_spheroid(many):
+    """The bench's 64-body leg: one mixed solve of the 16 plane waves to 1e-7.
+    The reference recomputes the residual sigma + D^{-1} B sigma - b on every row
+    of a bowl and of the longest spheroid for the first plane wave (its own
+    inter-body sum over all 1.35 million sources, its own per-mode inverses of
+    the two shapes and plane wave): those rows' residual is within the
+    tolerance (relative to the library's ||b|| over all rows) and equals the
+    library's own FP64 residual on the same rows to 1e-10."""
+    import time
+    from oracle.multibody import apply_B_c
+    from paper_1406_0236_amd import FP64, SOLVE_MIXED
+    wl, S, ctx = many
+    v = ctx.incident_plane_waves(wl.dirs)
+    t0 = time.time()
+    sol, info = ctx.solve(v, mode=SOLVE_MIXED, tol=1e-7)
+    print(f"[gpu] mixed solve {time.time() - t0:.1f} s: outer {info[0]['iterations']}, "
+          f"inner {info[0]['inner_iterations']}, worst residual {max(i['rel_residual'] for i in info):.2e}", flush=True)
+    assert all(i["converged"] for i in info)
+    b_lib = -ctx.apply_precond(v, FP64)
+    r_lib = (b_lib - ctx.apply_matvec(sol, FP64)).cpu().numpy()[0]
+    bnorm = float(torch.linalg.norm(b_lib[0]))
+    x = sol.cpu().numpy()[0]
+    picks = {}
+    for b, bs in enumerate(wl.bodies):
+        c = bs.contour
+        if c.kind == "bowl" and "bowl" not in picks:
+            picks["bowl"] = b
+        if c.kind == "prolate" and ("prolate" not in picks or c.NG > wl.bodies[picks["prolate"]].contour.NG):
+            picks["prolate"] = b
+    vr = S.plane_waves(wl.dirs[:1])[:, 0]
+    for kind, b in picks.items():
+        o0, o1 = S.offsets[b], S.offsets[b + 1]
+        sh = S.bodies[b].shape
+        t0 = time.time()
+        Bx = apply_B_c(S, x, np.arange(o0, o1))
+        bb = -sh.apply_Ainv(vr[o0:o1].reshape(sh.NG, sh.NF)).reshape(-1)
+        r = x[o0:o1] + sh.apply_Ainv(Bx.reshape(sh.NG, sh.NF)).reshape(-1) - bb
+        e = np.linalg.norm(r) / bnorm
+        d = np.linalg.norm(r - r_lib[o0:o1]) / bnorm
+        print(f"{kind} body {b} ({o1 - o0} rows, {time.time() - t0:.0f} s): reference residual {e:.2e}, "
+              f"vs library rows {d:.1e}", flush=True)
+        assert e <= 1e-7
+        assert d < 1e-10

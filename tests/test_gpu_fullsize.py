@@ -1,8 +1,7 @@
 """Parity at the benchmark's full size (27 spheres, kappa = 4 pi, N = 437,400) and
 in the launch configuration bench.py times (library defaults), on outputs the
 FP64 reference can compute one by one: sampled rows of the inter-body sum,
-sampled rows of the modal matrices, and the residual of the solve restricted to
-one body's rows.  Tolerances as in test_gpu_parity.py; the FP32 bound is
+sampled rows of the modal matrices, and the residual of the solve on every row.  Tolerances as in test_gpu_parity.py; the FP32 bound is
 looser here (phases reach kappa R ~ 200 rad, so FP32 coordinates give
 kappa |x| 2^-24 ~ 4e-6 rad per pair)."""
 import numpy as np
@@ -56,31 +55,39 @@ def test_fullsize_modal_matrix_rows(lattice):
         assert e < 1e-9, e
 
 
-def test_fullsize_solve_residual_certified_on_one_body(lattice):
+@pytest.mark.timeout(900)
+def test_fullsize_solve_residual_certified_on_every_row(lattice):
     """Mixed solve to 1e-7 as in the benchmark; the reference recomputes the
-    residual sigma + D^{-1} B sigma - b on all rows of body 13 (the centre)."""
-    from oracle.multibody import apply_B_c
+    residual sigma + D^{-1} B sigma - b, b = -D^{-1} v, on all 437,400 rows with
+    its own inter-body sum (C/OpenMP, every pair), per-mode inverses and plane
+    wave: its relative residual is within the tolerance and equals the
+    library's explicit FP64 residual to 1e-10 (the two operators agree to about
+    1e-13).  About 4-5 minutes of host time on 16 threads."""
+    import time
+    from oracle.multibody import apply_B_c, num_threads
     from paper_1406_0236_amd import SOLVE_MIXED
     wl, S, ctx = lattice
     v = ctx.incident_plane_waves(wl.dirs)
-    sol, info = ctx.solve(v, mode=SOLVE_MIXED, tol=1e-7)
-    print(info[0])
+    sol, info = ctx.solve(v, mode=SOLVE_MIXED, tol=1e-7, certify=True)
+    print(info[0], flush=True)
     assert info[0]["converged"]
     x = sol.cpu().numpy()[0]
-    b_id = 13
-    o0, o1 = S.offsets[b_id], S.offsets[b_id + 1]
-    rows = np.arange(o0, o1)
-    Bx = apply_B_c(S, x, rows)
-    sh = S.bodies[b_id].shape
-    DinvBx = sh.apply_Ainv(Bx.reshape(sh.NG, sh.NF)).reshape(-1)
-    vb = S.plane_waves(wl.dirs)[o0:o1, 0]
-    bb = -sh.apply_Ainv(vb.reshape(sh.NG, sh.NF)).reshape(-1)
-    r = x[o0:o1] + DinvBx - bb
-    # ||b|| over all bodies, from the library's own b = -D^{-1} v
-    bfull = ctx.apply_precond(v).cpu().numpy()[0]
-    e = np.linalg.norm(r) / np.linalg.norm(bfull)
-    print(f"body {b_id}: reference residual {e:.2e} (library total {info[0]['rel_residual']:.2e})")
-    assert e <= 1.2e-7
+    t0 = time.time()
+    print(f"[gpu] reference inter-body sum on all {S.N} rows, {num_threads()} threads", flush=True)
+    Bx = apply_B_c(S, x)
+    print(f"[gpu] done in {time.time() - t0:.0f} s", flush=True)
+    vr = S.plane_waves(wl.dirs)[:, 0]
+    r = np.empty_like(x)
+    bb = np.empty_like(x)
+    for b_id, body in enumerate(S.bodies):
+        o0, o1 = S.offsets[b_id], S.offsets[b_id + 1]
+        sh = body.shape
+        bb[o0:o1] = -sh.apply_Ainv(vr[o0:o1].reshape(sh.NG, sh.NF)).reshape(-1)
+        r[o0:o1] = x[o0:o1] + sh.apply_Ainv(Bx[o0:o1].reshape(sh.NG, sh.NF)).reshape(-1) - bb[o0:o1]
+    e = np.linalg.norm(r) / np.linalg.norm(bb)
+    print(f"every row: reference residual {e:.3e}, library explicit residual {info[0]['rel_residual']:.3e}")
+    assert e <= 1e-7 * (1 + 1e-3)
+    assert abs(e - info[0]["rel_residual"]) < 1e-10
 
 
 def test_fullsize_augmented_inner_runs_save_iterations(lattice):
