@@ -132,7 +132,7 @@ typedef struct {
                                  the GMRES least-squares residual of the FP64 Arnoldi
                                  relation, or with AXS_SOLVE_CERTIFY recomputed from sigma */
     double seconds;           /* wall time of the solve on the host clock */
-    int32_t used_warm_start;  /* 1 if sigma0 was kept as the initial guess */
+    int32_t used_warm_start;  /* 1 if sigma0 was kept (see axs_solve) */
     int32_t converged;
 } axs_solve_info;
 
@@ -160,8 +160,14 @@ enum {
 /* Solve (eq. "precond")  sigma + D^{-1} B sigma = -D^{-1} v  for nrhs incident fields
  * (with AXS_SOLVE_UNPRECONDITIONED: (D + B) sigma = -v).
  *  incident : device complex128 [nrhs][N], v at the nodes.
- *  sigma0   : device complex128 [nrhs][N] initial guess, or NULL for zero.  A guess
- *             whose FP64 residual is not below || b || is replaced by zero.
+ *  sigma0   : device complex128 [nrhs][N] initial guess, or NULL for zero.
+ *             AXS_SOLVE_FP64: GMRES starts from the guess if its FP64 residual is
+ *             below || b || (one FP64 application), else from zero.
+ *             AXS_SOLVE_MIXED: the guess g enters the first application of the
+ *             flexible preconditioner, z_1 = (g + inner(b - A32 g)) / || b ||, if
+ *             its residual in the FP32 operator is below || b || (one FP32
+ *             application), else that application is the plain one; the FP64
+ *             outer residual decides convergence either way.
  *  sigma    : device complex128 [nrhs][N], the result.
  *  mode     : AXS_SOLVE_FP64 or AXS_SOLVE_MIXED, optionally | AXS_SOLVE_CERTIFY
  *             (and, mixed only, | AXS_SOLVE_RESTART_INNER).

@@ -12,10 +12,11 @@
 //   - sources are streamed through LDS in tiles loaded with coalesced SoA reads
 //     and read back as LDS broadcasts; each thread keeps TPT targets and their
 //     complex accumulators in registers;
-//   - FP32 path: phase reduced in revolutions (v_fract) and fed to the
-//     hardware sin/cos (which take revolutions), 1/R from v_rsq;
-//   - FP64 path: the same structure with an octant-reduced Taylor sin/cos and
-//     a Newton-refined hardware 1/sqrt.
+//   - FP32 path: the phase in revolutions, less whole revolutions per
+//     (wavefront, source body), fed to the hardware sin/cos (which take
+//     revolutions and reduce up to 256 of them), 1/R from v_rsq;
+//   - FP64 path: the same structure with sin/cos from a 256-entry LDS table
+//     and short polynomials, and a Newton-refined hardware 1/sqrt.
 // Two source orders ("variants") compute the same sum:
 //   - points: each staged source carries x, y, z, n and q;
 //   - rings: a body's N_F nodes on one contour node form a ring; per target
@@ -45,68 +46,27 @@ __device__ __forceinline__ void sincos_rev_near(float ph, float &s, float &c) {
     c = __builtin_amdgcn_cosf(ph);
 }
 
-// sin and cos of 2 pi t (t in revolutions) in FP64: reduction to an octant,
-// r = t - k/4 in [-1/8, 1/8] exactly, x = 2 pi r in [-pi/4, pi/4], Taylor
-// series (coefficients +-1/n!) to x^15 for sin and x^16 for cos, whose
-// truncation errors are below 1e-16 on that interval, then the quadrant turn.
-constexpr double inv_fact(int n) { return n <= 1 ? 1.0 : inv_fact(n - 1) / n; }
-__device__ __forceinline__ void sincos_rev(double t, double &s, double &c) {
-    const double f = t - rint(t);            // exact, [-1/2, 1/2]
-    const double kq = rint(4.0 * f);         // quadrant -2..2
-    const double r = fma(-0.25, kq, f);      // exact
-    const double x = r * 6.283185307179586476925287;
-    const double x2 = x * x;
-    double ps = -inv_fact(15);
-    ps = fma(x2, ps, inv_fact(13));
-    ps = fma(x2, ps, -inv_fact(11));
-    ps = fma(x2, ps, inv_fact(9));
-    ps = fma(x2, ps, -inv_fact(7));
-    ps = fma(x2, ps, inv_fact(5));
-    ps = fma(x2, ps, -inv_fact(3));
-    const double sx = fma(x * x2, ps, x);
-    double pc = inv_fact(16);
-    pc = fma(x2, pc, -inv_fact(14));
-    pc = fma(x2, pc, inv_fact(12));
-    pc = fma(x2, pc, -inv_fact(10));
-    pc = fma(x2, pc, inv_fact(8));
-    pc = fma(x2, pc, -inv_fact(6));
-    pc = fma(x2, pc, inv_fact(4));
-    pc = fma(x2, pc, -0.5);
-    const double cx = fma(x2, pc, 1.0);
-    const int q = ((int)kq) & 3;             // turn by q quarter revolutions
-    const double a = (q & 1) ? cx : sx, b = (q & 1) ? sx : cx;
-    s = (q & 2) ? -a : a;
-    c = ((q + 1) & 2) ? -b : b;
-}
-__device__ __forceinline__ void sincos_rev_near(double t, double &s, double &c) { sincos_rev(t, s, c); }
-
-// The same in FP64 with a 256-entry table of (cos, sin)(2 pi k / 256) held in
-// LDS: t = j/256 + r with |r| <= 1/512 exactly, x = 2 pi r in [-pi/256, pi/256],
-// sin x to x^5 and cos x to x^6 (truncation below 1e-17), then the angle sum
-// with the table entry.  About 20 instructions instead of the 33 above.
+// sin and cos of 2 pi t in FP64 for |t| < 2^40 revolutions, with a 256-entry
+// table of (cos, sin)(2 pi j / 256) held in LDS:
+//   y = t + 1.5 * 2^44 (one add; the sum has an ulp of 1/256) rounds t to the
+//   nearest multiple j / 256, and the low word of y is j, which indexes the
+//   table; y - 1.5 * 2^44 is j / 256 exactly, and so is r = t - j / 256, in
+//   [-1/512, 1/512];
+//   with x = 2 pi r: sin x to x^5 and cos x to x^6 (truncation below 1e-17)
+//   as polynomials in r (Taylor coefficients times powers of 2 pi);
+//   then the angle sum with the table entry.
+constexpr double SC_MAGIC = 26388279066624.0;   // 1.5 * 2^44
+constexpr double SC_A = 6.283185307179586476925287;
+constexpr double SC_S1 = SC_A, SC_S3 = -SC_A * SC_A * SC_A / 6.0, SC_S5 = SC_A * SC_A * SC_A * SC_A * SC_A / 120.0;
+constexpr double SC_C2 = -SC_A * SC_A / 2.0, SC_C4 = SC_A * SC_A * SC_A * SC_A / 24.0,
+                 SC_C6 = -SC_A * SC_A * SC_A * SC_A * SC_A * SC_A / 720.0;
 __device__ __forceinline__ void sincos_rev_tab(double t, const double2 *tab, double &s, double &c) {
-    const double f = t - rint(t);                 // exact, [-1/2, 1/2]
-    const double j = rint(256.0 * f);             // -128..128
-    const double r = fma(-1.0 / 256.0, j, f);     // exact
-    const double x = r * 6.283185307179586476925287;
-    const double x2 = x * x;
-    const double sx = fma(x * x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
-    const double cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
-    const double2 e = tab[((int)j) & 255];        // (cos, sin)(2 pi j / 256)
-    s = fma(e.y, cx, e.x * sx);
-    c = fma(e.x, cx, -e.y * sx);
-}
-// The same for phases t in [0, 2^20) revolutions (the whole-revolution offset
-// already taken off): j = rint(256 t) indexes the table modulo 256 and
-// r = t - j/256 is exact, so the fraction t - rint(t) is not needed.
-__device__ __forceinline__ void sincos_rev_tab_near(double t, const double2 *tab, double &s, double &c) {
-    const double j = rint(256.0 * t);
-    const double r = fma(-1.0 / 256.0, j, t);     // exact, |r| <= 1/512
-    const double x = r * 6.283185307179586476925287;
-    const double x2 = x * x;
-    const double sx = fma(x * x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
-    const double cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
-    const double2 e = tab[((int)j) & 255];        // (cos, sin)(2 pi j / 256)
+    const double y = t + SC_MAGIC;
+    const double r = t - (y - SC_MAGIC);          // exact
+    const double r2 = r * r;
+    const double sx = r * fma(r2, fma(r2, SC_S5, SC_S3), SC_S1);
+    const double cx = fma(r2, fma(r2, fma(r2, SC_C6, SC_C4), SC_C2), 1.0);
+    const double2 e = tab[__double2loint(y) & 255];   // (cos, sin)(2 pi j / 256)
     s = fma(e.y, cx, e.x * sx);
     c = fma(e.x, cx, -e.y * sx);
 }
@@ -115,11 +75,25 @@ __device__ __forceinline__ void sincos_any(float ph, const double2 *, float &s, 
 __device__ __forceinline__ void sincos_any(double t, const double2 *tab, double &s, double &c) {
     sincos_rev_tab(t, tab, s, c);
 }
-__device__ __forceinline__ void sincos_near_any(float ph, const double2 *, float &s, float &c) {
-    sincos_rev_near(ph, s, c);
+// sin and cos of 2 pi R' from r2 = R'^2 and u = 1/R' (R' = R k / 2 pi, the
+// phase in revolutions).  FP32: the hardware sin/cos of R' - n0, n0 the whole
+// revolutions of the (wavefront, source body), which keeps the argument in
+// their input range.  FP64: as sincos_rev_tab, with the product r2 u rounded
+// to the table's 1/256 steps inside one FMA, y = r2 u + 1.5 * 2^44, and the
+// remainder r = r2 u - J, J = y - 1.5 * 2^44, formed by a second FMA, so the
+// remainder carries the product's full precision (R' < 2^40 revolutions).
+__device__ __forceinline__ void sincos_phase(float r2, float u, float n0, const double2 *, float &s, float &c) {
+    sincos_rev_near(fma(r2, u, -n0), s, c);
 }
-__device__ __forceinline__ void sincos_near_any(double t, const double2 *tab, double &s, double &c) {
-    sincos_rev_tab_near(t, tab, s, c);
+__device__ __forceinline__ void sincos_phase(double r2, double u, double, const double2 *tab, double &s, double &c) {
+    const double y = fma(r2, u, SC_MAGIC);
+    const double r = fma(r2, u, -(y - SC_MAGIC));
+    const double rr = r * r;
+    const double sx = r * fma(rr, fma(rr, SC_S5, SC_S3), SC_S1);
+    const double cx = fma(rr, fma(rr, fma(rr, SC_C6, SC_C4), SC_C2), 1.0);
+    const double2 e = tab[__double2loint(y) & 255];   // (cos, sin)(2 pi j / 256)
+    s = fma(e.y, cx, e.x * sx);
+    c = fma(e.x, cx, -e.y * sx);
 }
 // copy the FP64 table to LDS (the kernels' first barrier publishes it)
 template <typename R, int BS>
@@ -142,13 +116,14 @@ __device__ __forceinline__ double wave_floor_min(double v) {
     return floor(fmax(v, 0.0));
 }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-// 1/sqrt(x) for finite x > 0: hardware estimate refined by two Newton steps,
-// y <- y + y (1/2 - (x/2) y^2)
+// 1/sqrt(x) for finite x > 0: the hardware estimate y (relative error up to
+// 5.2e-8 measured over 4M arguments; one Newton step leaves 4e-15) corrected
+// to second order in e = 1 - x y^2: 1/sqrt(x) = y (1 - e)^(-1/2)
+// = y (1 + e/2 + 3 e^2/8 + ...), the first dropped term 5 e^3/16 below 1e-21
 __device__ __forceinline__ double rsq(double x) {
-    const double h = 0.5 * x;
-    double y = __builtin_amdgcn_rsq(x);
-    y = fma(y, fma(-h * y, y, 0.5), y);
-    return fma(y, fma(-h * y, y, 0.5), y);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y, e * fma(e, 0.375, 0.5), y);
 }
 
 // LDS stride (in elements) of one staged source: x y z nx ny nz + NR complex q,
@@ -313,7 +288,7 @@ __device__ __forceinline__ void ring_term(R r2, R nd, R n0, R eta, R etap, const
     } else {
         const R twopi = R(6.283185307179586476925287);
         R sn, cs_;
-        sincos_near_any(fma(r2, u, -n0), s_tab, sn, cs_);   // phase R' = kR / 2pi revolutions
+        sincos_phase(r2, u, n0, s_tab, sn, cs_);   // phase R' = kR / 2pi revolutions
         const R t = nd * (u * u);
         const R P = t * u;                     // n.d / R^3
         const R Q = fma(-twopi, t, etap * u);  // eta / R - k n.d / R^2
@@ -337,7 +312,7 @@ template <typename R>
 __device__ __forceinline__ void ring_term1(R r2, R nd, R n0, const double2 *s_tab, const R *qv, R &ar, R &ai) {
     const R u = rsq(r2);
     R sn, cs_;
-    sincos_near_any(fma(r2, u, -n0), s_tab, sn, cs_);   // phase R' less whole revolutions
+    sincos_phase(r2, u, n0, s_tab, sn, cs_);   // phase R' (less whole revolutions in FP32)
     const R w = nd * u;
     const R zr = fma(w, fma(u, qv[0], qv[2]), qv[4]);
     const R zi = fma(w, fma(u, qv[1], qv[3]), qv[5]);
@@ -594,7 +569,7 @@ template <typename R>
 __device__ __forceinline__ void kernel_value(R r2, R nd, R n0, R etap, const double2 *tab, R &gr, R &gi) {
     const R u = rsq(r2);                   // 1 / R'
     R sn, cs_;
-    sincos_near_any(fma(r2, u, -n0), tab, sn, cs_);   // R' less whole revolutions n0
+    sincos_phase(r2, u, n0, tab, sn, cs_);   // R' (less whole revolutions n0 in FP32)
     const R t = nd * (u * u);
     const R P = t * u;                     // n.d / R^3
     const R Q = fma(R(-6.283185307179586476925287), t, etap * u);   // eta / R - k n.d / R^2

@@ -104,6 +104,19 @@ __global__ void cscale_kernel(const double2 *__restrict__ in, const double *__re
     out[t] = make_double2(v.x * f, v.y * f);
 }
 
+// out[c][n] += a[c][n] * s[c]  (s real)
+__global__ void cadd_scaled_kernel(const double2 *__restrict__ a, const double *__restrict__ s,
+                                   double2 *__restrict__ out, int64_t N, int nrhs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * nrhs) return;
+    const double f = s[t / N];
+    const double2 v = a[t];
+    double2 o = out[t];
+    o.x += v.x * f;
+    o.y += v.y * f;
+    out[t] = o;
+}
+
 // w[c][n] /= sqrt(nrm[c].x), or 0 where that norm is 0 (the new Arnoldi vector)
 __global__ void cnormalize_kernel(double2 *__restrict__ w, const double2 *__restrict__ nrm, int64_t N, int nrhs) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -668,11 +681,18 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
     for (double v : bn) AXS_REQUIRE(std::isfinite(v), AXS_ENONFINITE, "non-finite incident field");
     for (auto &v : bn)
         if (v == 0.0) v = 1.0;
-    // initial guess: sigma0 if its FP64 residual is below ||b||, else zero
+    // initial guess.  FP64 GMRES: sigma0 is the starting point if its FP64
+    // residual is below ||b||, else zero (one FP64 application).  Mixed: the
+    // guess enters the first application of the flexible preconditioner
+    // instead, z_1 = (g + inner(b - A32 g)) / ||b||, which costs one FP32
+    // application; it is kept where its FP32 residual is below ||b||, and
+    // the FP64 outer residual certifies the result either way.
     std::vector<int> warm(nrhs, 0);
+    const bool mixed_guess = sigma0 && mode == AXS_SOLVE_MIXED;
+    double2 *g = nullptr, *w0 = nullptr;   // mixed: the kept guess and b - A32 g
     AXS_HIP(hipMemsetAsync(x, 0, vb, c.stream));
     AXS_HIP(hipMemcpyAsync(r, b, vb, hipMemcpyDeviceToDevice, c.stream));
-    if (sigma0) {
+    if (sigma0 && !mixed_guess) {
         op64((const double2 *)sigma0, tmp);
         hipLaunchKernelGGL(csub_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, b, tmp, tmp, tot);
         AXS_HIP(hipGetLastError());
@@ -683,6 +703,24 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
                 AXS_HIP(hipMemcpyAsync(x + cc * N, (const double2 *)sigma0 + cc * N, N * sizeof(double2),
                                        hipMemcpyDeviceToDevice, c.stream));
                 AXS_HIP(hipMemcpyAsync(r + cc * N, tmp + cc * N, N * sizeof(double2), hipMemcpyDeviceToDevice,
+                                       c.stream));
+            }
+        }
+    }
+    if (mixed_guess) {
+        g = (double2 *)c.dalloc(vb);
+        w0 = (double2 *)c.dalloc(vb);
+        AXS_HIP(hipMemcpyAsync(g, sigma0, vb, hipMemcpyDeviceToDevice, c.stream));
+        apply_operator(c, g, tmp, nrhs, AXS_FP32);
+        hipLaunchKernelGGL(csub_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, b, tmp, w0, tot);
+        AXS_HIP(hipGetLastError());
+        std::vector<double> rn = norms(c, w0, N, nrhs);
+        for (int cc = 0; cc < nrhs; ++cc) {
+            if (std::isfinite(rn[cc]) && rn[cc] < bn[cc]) {
+                warm[cc] = 1;
+            } else {   // dropped: the first preconditioner application is the plain one
+                AXS_HIP(hipMemsetAsync(g + cc * N, 0, N * sizeof(double2), c.stream));
+                AXS_HIP(hipMemcpyAsync(w0 + cc * N, b + cc * N, N * sizeof(double2), hipMemcpyDeviceToDevice,
                                        c.stream));
             }
         }
@@ -701,7 +739,24 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
         Basis Z(c, vb, max_iters), Vi(c, vb, max_inner + 1), Vr(c, vb, max_inner + 1);
         Recycle rc;
         bool have_rc = false;
-        auto prec = [&](const double2 *v, double2 *z) {
+        bool first_prec = true;
+        std::vector<double> invb(nrhs);
+        for (int cc = 0; cc < nrhs; ++cc) invb[cc] = 1.0 / bn[cc];
+        double *sdev = (double *)c.dalloc(nrhs * sizeof(double));   // 1 / ||b|| per rhs
+        AXS_HIP(hipMemcpyAsync(sdev, invb.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, c.stream));
+        AXS_HIP(hipStreamSynchronize(c.stream));   // invb is pageable host memory
+        auto prec = [&](const double2 *v_in, double2 *z) {
+            // with a kept guess the first application solves for the guess's
+            // correction: v_1 = b / ||b||, so v_1 - A32 g / ||b|| = w0 / ||b||
+            const double2 *v = v_in;
+            const bool with_guess = mixed_guess && first_prec;
+            first_prec = false;
+            if (with_guess) {
+                hipLaunchKernelGGL(cscale_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, w0, sdev,
+                                   tmp, N, nrhs);
+                AXS_HIP(hipGetLastError());
+                v = tmp;
+            }
             // inner GMRES on the FP32 operator, zero initial guess, rhs v; it only
             // has to reduce the outer residual by the factor still missing, with
             // a margin of 0.6 (the first run stops at 1e-5, about the FP32
@@ -713,6 +768,10 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
             std::vector<double> vn = norms(c, v, N, nrhs);
             for (auto &q : vn)
                 if (q == 0.0) q = 1.0;
+            // with the guess the inner tolerance is measured against ||v_1|| = 1,
+            // not against the guess's smaller residual: a better guess then
+            // shortens this run instead of demanding the same relative reduction
+            if (with_guess) vn.assign(nrhs, 1.0);
             auto op32 = [&](const double2 *in, double2 *out) { apply_operator(c, in, out, nrhs, AXS_FP32); };
             auto none = [&](const double2 *, double2 *) {};
             std::vector<double> ie;
@@ -731,8 +790,14 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
                 it = gmres_core(c, N, nrhs, max_inner, tin, v, z, Vi, nullptr, vn, op32, none, false, ie, &rc);
             }
             for (int cc = 0; cc < nrhs; ++cc) inner_total[cc] += it[cc];
+            if (with_guess) {   // z += g / ||b||
+                hipLaunchKernelGGL(cadd_scaled_kernel, dim3(ceil_div(N * nrhs, 256)), dim3(256), 0, c.stream, g,
+                                   sdev, z, N, nrhs);
+                AXS_HIP(hipGetLastError());
+            }
         };
         outer = gmres_core(c, N, nrhs, max_iters, tol, r, x, V, &Z, bn, op64, prec, true, est);
+        c.dfree(sdev);
     }
     std::vector<double> relv = est;
     if (certify) {
@@ -763,6 +828,8 @@ axs_status solve_impl(Ctx &c, const void *incident, const void *sigma0, void *si
     c.dfree(b);
     c.dfree(r);
     c.dfree(tmp);
+    c.dfree(g);
+    c.dfree(w0);
     return all_ok ? AXS_OK : AXS_NOT_CONVERGED;
 }
 

@@ -46,6 +46,8 @@ struct Mlp {
     double *loss_dev = nullptr;
     int32_t *order = nullptr;        // row order of one epoch (device copy)
     int64_t cap_order = 0;
+    float *ws = nullptr;             // split-K partial products (grown on demand)
+    int64_t cap_ws = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -61,9 +63,11 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
     return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
+// With gridDim.z > 1 (split K) block z sums k in [z kc, min(K, (z+1) kc)) and
+// writes its partial product, without bias or activation, to out_h + z M ldc.
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, const float *__restrict__ A, int lda,
-                                                        const float *__restrict__ B, int ldb,
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, int kc, const float *__restrict__ A,
+                                                        int lda, const float *__restrict__ B, int ldb,
                                                         const float *__restrict__ bias, int act, float beta,
                                                         float *__restrict__ out_z, float *__restrict__ out_h, int ldc) {
     __shared__ float As[GBM][GKT + 1];
@@ -76,7 +80,9 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += GKT) {
+    const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+    if (gridDim.z > 1) out_h += (int64_t)blockIdx.z * M * ldc;
+    for (int k0 = kb; k0 < ke; k0 += GKT) {
         // stage A tile (GBM x GKT) and B tile (GKT x GBN), 4 elements per thread each
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -91,7 +97,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
             }
             const int gm = m0 + mm, gk = k0 + kk;
             float val = 0.f;
-            if (gm < M && gk < K) val = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+            if (gm < M && gk < ke) val = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
             As[mm][kk] = val;
             int nn, kb;
             if (TB) {            // stored N x K: consecutive threads walk k
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
             }
             const int gn = n0 + nn, gkb = k0 + kb;
             float vb = 0.f;
-            if (gn < N && gkb < K) vb = TB ? B[(int64_t)gn * ldb + gkb] : B[(int64_t)gkb * ldb + gn];
+            if (gn < N && gkb < ke) vb = TB ? B[(int64_t)gn * ldb + gkb] : B[(int64_t)gkb * ldb + gn];
             Bs[kb][nn] = vb;
         }
         __syncthreads();
@@ -140,12 +146,46 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(int M, int N, int K, con
             }
 }
 
+// out[m][n] = sum_s part[s][m][n] (fixed order) + bias[n], GELU with act
+__global__ void splitk_reduce_kernel(const float *__restrict__ part, int S, int M, int N,
+                                     const float *__restrict__ bias, int act, float *__restrict__ out_z,
+                                     float *__restrict__ out_h) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, mn = (int64_t)M * N;
+    if (t >= mn) return;
+    float z = 0.f;
+    for (int s = 0; s < S; ++s) z += part[s * mn + t];
+    if (bias) z += bias[t % N];
+    if (out_z) out_z[t] = z;
+    if (out_h) out_h[t] = act ? gelu_f(z) : z;
+}
+
+// K splits for a GEMM whose output has too few 64 x 64 tiles to fill the
+// GPU (at least 1024 k per split, up to about 1024 blocks in all); 1 = none
+static int splitk_count(int M, int N, int K) {
+    const int64_t tiles = ceil_div(M, GBM) * ceil_div(N, GBN);
+    if (tiles >= 256 || K < 2048) return 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(K / 1024, 1024 / tiles));
+}
+
+// C = op(A) op(B) (+ bias, GELU); ws: workspace of splitk_count(M, N, K) M N
+// floats when that count exceeds 1 (ldc must then be N)
 template <bool TA, bool TB>
 static void gemm(Ctx &c, int M, int N, int K, const float *A, int lda, const float *B, int ldb, const float *bias,
-                 int act, float *out_z, float *out_h, int ldc) {
-    dim3 grid((unsigned)ceil_div(N, GBN), (unsigned)ceil_div(M, GBM));
-    hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB>), grid, dim3(256), 0, c.stream, M, N, K, A, lda, B, ldb, bias, act,
-                       0.f, out_z, out_h, ldc);
+                 int act, float *out_z, float *out_h, int ldc, float *ws = nullptr) {
+    const int S = ws && ldc == N ? splitk_count(M, N, K) : 1;
+    const int kc = S > 1 ? (int)(ceil_div(ceil_div(K, S), GKT) * GKT) : K;
+    const int Sg = S > 1 ? (int)ceil_div(K, kc) : 1;
+    dim3 grid((unsigned)ceil_div(N, GBN), (unsigned)ceil_div(M, GBM), (unsigned)Sg);
+    if (Sg > 1) {
+        hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB>), grid, dim3(256), 0, c.stream, M, N, K, kc, A, lda, B, ldb,
+                           nullptr, 0, 0.f, nullptr, ws, N);
+        AXS_HIP(hipGetLastError());
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)ceil_div((int64_t)M * N, 256)), dim3(256), 0,
+                           c.stream, ws, Sg, M, N, bias, act, out_z, out_h);
+    } else {
+        hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB>), grid, dim3(256), 0, c.stream, M, N, K, K, A, lda, B, ldb, bias,
+                           act, 0.f, out_z, out_h, ldc);
+    }
     AXS_HIP(hipGetLastError());
 }
 
@@ -305,7 +345,16 @@ static void mlp_backward(Mlp &n, const float *T, int B) {
         hipLaunchKernelGGL(colsum_kernel, dim3(ceil_div(b, 256)), dim3(256), 0, c.stream, G, B, b, n.g + n.boff[k]);
         AXS_HIP(hipGetLastError());
         if (k > 0) {
-            gemm<false, true>(c, B, a, b, G, b, n.p + n.woff[k], b, nullptr, 0, nullptr, Gn, a);
+            // dH has few output tiles and, for the output layer, a long k range: split K
+            const int64_t need = (int64_t)splitk_count(B, a, b) * B * a;
+            if (need > (int64_t)B * a && need > n.cap_ws) {
+                AXS_HIP(hipStreamSynchronize(c.stream));
+                c.dfree(n.ws);
+                n.ws = nullptr;
+                n.ws = (float *)c.dalloc((size_t)need * sizeof(float));
+                n.cap_ws = need;
+            }
+            gemm<false, true>(c, B, a, b, G, b, n.p + n.woff[k], b, nullptr, 0, nullptr, Gn, a, n.ws);
             std::swap(G, Gn);
         }
     }
@@ -418,7 +467,7 @@ axs_status axs_mlp_destroy(axs_mlp *h) {
         for (auto *p : n.H) n.ctx->dfree(p);
         for (auto *p : n.Z) n.ctx->dfree(p);
         for (void *p : {(void *)n.p, (void *)n.m, (void *)n.v, (void *)n.g, (void *)n.G0, (void *)n.G1,
-                        (void *)n.Tb, (void *)n.loss_part, (void *)n.loss_dev, (void *)n.order})
+                        (void *)n.Tb, (void *)n.loss_part, (void *)n.loss_dev, (void *)n.order, (void *)n.ws})
             n.ctx->dfree(p);
     }
     delete h;
@@ -800,30 +849,38 @@ static TrainParams parse_hparams(const char *txt) {
     return hp;
 }
 
-// counter-based generator (splitmix64 of seed + counter)
-static uint64_t splitmix64(uint64_t x) {
+// counter-based generator (splitmix64 of seed + counter), the same on host and device
+__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
     x += 0x9e3779b97f4a7c15ULL;
     x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
     x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
     return x ^ (x >> 31);
 }
-static double uniform01(uint64_t seed, uint64_t k) {   // in (0, 1)
+__host__ __device__ inline double uniform01(uint64_t seed, uint64_t k) {   // in (0, 1)
     return ((double)(splitmix64(seed * 0x632be59bd9b4e019ULL + k) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
 }
 
-// He initialisation: W_k ~ N(0, 2 / fan_in) by Box-Muller, biases zero
+// p[e] = sd sqrt(-2 log u1) cos(2 pi u2), (u1, u2) = draws k0 + 2e and k0 + 2e + 1 (Box-Muller)
+__global__ void he_init_kernel(float *__restrict__ p, int64_t n, uint64_t seed, uint64_t k0, double sd) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const double u1 = uniform01(seed, k0 + 2 * (uint64_t)e), u2 = uniform01(seed, k0 + 2 * (uint64_t)e + 1);
+    p[e] = (float)(sd * sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2));
+}
+
+// He initialisation: W_k ~ N(0, 2 / fan_in), biases zero; the draws are
+// numbered through all weight matrices in order
 static void he_init(Mlp &n, uint64_t seed) {
-    std::vector<float> p((size_t)n.nparams, 0.f);
+    Ctx &c = *n.ctx;
+    AXS_HIP(hipMemsetAsync(n.p, 0, n.nparams * sizeof(float), c.stream));
     uint64_t k = 0;
     for (size_t l = 0; l + 1 < n.sizes.size(); ++l) {
-        const int64_t a = n.sizes[l], b = n.sizes[l + 1];
-        const double sd = std::sqrt(2.0 / (double)a);
-        for (int64_t e = 0; e < a * b; ++e, k += 2) {
-            const double u1 = uniform01(seed, k), u2 = uniform01(seed, k + 1);
-            p[(size_t)(n.woff[l] + e)] = (float)(sd * std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2));
-        }
+        const int64_t a = n.sizes[l], b = n.sizes[l + 1], cnt = a * b;
+        hipLaunchKernelGGL(he_init_kernel, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, c.stream,
+                           n.p + n.woff[l], cnt, seed, k, std::sqrt(2.0 / (double)a));
+        AXS_HIP(hipGetLastError());
+        k += 2 * (uint64_t)cnt;
     }
-    AXS_HIP(hipMemcpy(n.p, p.data(), p.size() * sizeof(float), hipMemcpyHostToDevice));
 }
 
 static void reset_adam(Mlp &n) {

@@ -1,14 +1,20 @@
 """Parity at the benchmark's full size (27 spheres, kappa = 4 pi, N = 437,400) and
 in the launch configuration bench.py times (library defaults), on outputs the
 FP64 reference can compute one by one: sampled rows of the inter-body sum,
-sampled rows of the modal matrices, and the residual of the solve on every row.  Tolerances as in test_gpu_parity.py; the FP32 bound is
+sampled rows of the modal matrices, and the residual of the solve on the rows of one
+body (on every row with AXS_CERTIFY_EVERY_ROW=1).  Tolerances as in test_gpu_parity.py; the FP32 bound is
 looser here (phases reach kappa R ~ 200 rad, so FP32 coordinates give
 kappa |x| 2^-24 ~ 4e-6 rad per pair)."""
+import math
+import os
+
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+
+from tolerances import fp32_sum_bound  # noqa: E402
 
 
 def rel(a, b):
@@ -37,7 +43,7 @@ def test_fullsize_interbody_sampled_rows(lattice):
     rows[0], rows[-1] = 0, S.N - 1          # first and last node (ragged tile ends)
     ref = apply_B_c(S, sig, rows)
     x = torch.from_numpy(sig[None]).to("cuda:0")
-    for prec, tol in ((FP64, 1e-12), (FP32, 1e-4)):
+    for prec, tol in ((FP64, 4e-13), (FP32, fp32_sum_bound(wl))):
         y = ctx.apply_interbody(x, prec).cpu().numpy()[0][rows]
         e = rel(y, ref)
         print(f"prec {prec}: sampled-row rel err {e:.2e}")
@@ -52,39 +58,68 @@ def test_fullsize_modal_matrix_rows(lattice):
         row = sh.modal_row(i) + 0.5 * (np.arange(sh.NG) == i)[None, :]
         e = rel(A[:, i, :], row)
         print(f"row {i}: rel err {e:.2e}")
-        assert e < 1e-9, e
+        assert e < 2e-12, e
 
 
-@pytest.mark.timeout(900)
+def _certified_residual(S, wl, x, rows_of, log_every=None):
+    """The reference's residual x + D^{-1} B x - b, b = -D^{-1} v, on the rows of
+    the bodies in rows_of (its own inter-body sum over every source, per-mode
+    inverses and plane wave), and ||b|| over the same bodies."""
+    import time
+    from oracle.multibody import apply_B_c
+    vr = S.plane_waves(wl.dirs)[:, 0]
+    r2 = b2 = 0.0
+    t0 = time.time()
+    for n, b_id in enumerate(rows_of):
+        o0, o1 = S.offsets[b_id], S.offsets[b_id + 1]
+        sh = S.bodies[b_id].shape
+        Bx = apply_B_c(S, x, np.arange(o0, o1))
+        bb = -sh.apply_Ainv(vr[o0:o1].reshape(sh.NG, sh.NF)).reshape(-1)
+        r = x[o0:o1] + sh.apply_Ainv(Bx.reshape(sh.NG, sh.NF)).reshape(-1) - bb
+        r2 += float(np.vdot(r, r).real)
+        b2 += float(np.vdot(bb, bb).real)
+        if log_every and (n + 1) % log_every == 0:
+            print(f"[gpu] reference residual: {n + 1} of {len(rows_of)} bodies, {time.time() - t0:.0f} s", flush=True)
+    return math.sqrt(r2), math.sqrt(b2)
+
+
+def test_fullsize_solve_residual_certified_on_one_body(lattice):
+    """Mixed solve to 1e-7 as in the benchmark; the reference recomputes the
+    residual on all rows of body 13 (the centre), relative to the library's
+    ||b|| over all rows."""
+    from paper_1406_0236_amd import SOLVE_MIXED
+    wl, S, ctx = lattice
+    v = ctx.incident_plane_waves(wl.dirs)
+    sol, info = ctx.solve(v, mode=SOLVE_MIXED, tol=1e-7)
+    print(info[0])
+    assert info[0]["converged"]
+    rn, _ = _certified_residual(S, wl, sol.cpu().numpy()[0], [13])
+    e = rn / float(torch.linalg.norm(ctx.apply_precond(v)))
+    print(f"body 13: reference residual {e:.2e} (library total {info[0]['rel_residual']:.2e})")
+    assert e <= 1e-7
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+@pytest.mark.skipif(os.environ.get("AXS_CERTIFY_EVERY_ROW") != "1",
+                    reason="4-7 minutes of host time on 16 threads (1.8e11 reference kernel evaluations): "
+                           "run with AXS_CERTIFY_EVERY_ROW=1")
 def test_fullsize_solve_residual_certified_on_every_row(lattice):
     """Mixed solve to 1e-7 as in the benchmark; the reference recomputes the
-    residual sigma + D^{-1} B sigma - b, b = -D^{-1} v, on all 437,400 rows with
-    its own inter-body sum (C/OpenMP, every pair), per-mode inverses and plane
-    wave: its relative residual is within the tolerance and equals the
-    library's explicit FP64 residual to 1e-10 (the two operators agree to about
-    1e-13).  About 4-5 minutes of host time on 16 threads."""
-    import time
-    from oracle.multibody import apply_B_c, num_threads
+    residual x + D^{-1} B x - b on all 437,400 rows: its relative residual is
+    within the tolerance and equals the library's explicit FP64 residual to
+    1e-10 (the two operators agree to about 1e-13 on these well-conditioned
+    spheres)."""
+    from oracle.multibody import num_threads
     from paper_1406_0236_amd import SOLVE_MIXED
     wl, S, ctx = lattice
     v = ctx.incident_plane_waves(wl.dirs)
     sol, info = ctx.solve(v, mode=SOLVE_MIXED, tol=1e-7, certify=True)
     print(info[0], flush=True)
     assert info[0]["converged"]
-    x = sol.cpu().numpy()[0]
-    t0 = time.time()
     print(f"[gpu] reference inter-body sum on all {S.N} rows, {num_threads()} threads", flush=True)
-    Bx = apply_B_c(S, x)
-    print(f"[gpu] done in {time.time() - t0:.0f} s", flush=True)
-    vr = S.plane_waves(wl.dirs)[:, 0]
-    r = np.empty_like(x)
-    bb = np.empty_like(x)
-    for b_id, body in enumerate(S.bodies):
-        o0, o1 = S.offsets[b_id], S.offsets[b_id + 1]
-        sh = body.shape
-        bb[o0:o1] = -sh.apply_Ainv(vr[o0:o1].reshape(sh.NG, sh.NF)).reshape(-1)
-        r[o0:o1] = x[o0:o1] + sh.apply_Ainv(Bx[o0:o1].reshape(sh.NG, sh.NF)).reshape(-1) - bb[o0:o1]
-    e = np.linalg.norm(r) / np.linalg.norm(bb)
+    rn, bn = _certified_residual(S, wl, sol.cpu().numpy()[0], list(range(len(S.bodies))), log_every=1)
+    e = rn / bn
     print(f"every row: reference residual {e:.3e}, library explicit residual {info[0]['rel_residual']:.3e}")
     assert e <= 1e-7 * (1 + 1e-3)
     assert abs(e - info[0]["rel_residual"]) < 1e-10

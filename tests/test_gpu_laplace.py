@@ -3,8 +3,9 @@ field adds the single layer with the real coefficient eta (= 1), through the C
 ABI against the FP64 reference on a sphere, a rotated spheroid and a rotated
 bowl (tests/conftest.py::laplace_system).
 
-Tolerances as in test_gpu_parity.py: modal matrices 1e-9, FP64 sums 1e-12, FP32
-sums 3e-5, solves to 1e-11 within 1e-8 of the dense reference; the exterior
+Tolerances as in test_gpu_parity.py: modal matrices 2e-12 (3e-13 seen), FP64 sums
+1e-13, FP32 sums fp32_sum_bound (2^-24 x 32 at kappa = 0), solves to 1e-11
+within 1e-8 of the dense reference; the exterior
 field of interior point sources within 1e-6 of the exact one (the reference
 itself reaches 9e-9 on this discretisation)."""
 import numpy as np
@@ -12,6 +13,8 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+
+from tolerances import fp32_sum_bound  # noqa: E402
 
 
 def rel(a, b):
@@ -39,7 +42,7 @@ def test_laplace_modal_matrices(lap):
         eA = rel(ctx.modal_matrices(b, 0, sh.M, sh.NG).cpu().numpy(), sh.modal_matrices())
         eS = rel(ctx.modal_matrices(b, 1, sh.M, sh.NG).cpu().numpy(), sh.inverses())
         print(f"body {b} ({wl.bodies[b].contour.kind}): A~ {eA:.2e} S {eS:.2e}")
-        assert eA < 1e-9 and eS < 1e-9
+        assert eA < 2e-12 and eS < 2e-12
 
 
 def test_laplace_interbody_sum_all_orders(lap):
@@ -51,7 +54,7 @@ def test_laplace_interbody_sum_all_orders(lap):
     rng = np.random.default_rng(31)
     x = rng.standard_normal((5, S.N)) + 1j * rng.standard_normal((5, S.N))
     ref = S.apply_B(x.T).T
-    for prec, tol in ((FP64, 1e-12), (FP32, 3e-5)):
+    for prec, tol in ((FP64, 1e-13), (FP32, fp32_sum_bound(wl))):
         for variant in (1, 2):
             for tpt, block, splits in ((1, 128, 1), (2, 256, 3), (4, 256, 0)):
                 ctx.set_interbody_config(prec, variant, tpt, block, splits)

@@ -1,12 +1,24 @@
 """Parity of the HIP library (through the C ABI) with the FP64 reference.
 
-Tolerances (relative to the largest entry of the compared quantity):
-  * setup matrices A~_m and S_m (FP64 on the device):  1e-9 -- the two sides use
-    different quadratures (graded Gauss vs tanh-sinh) for the same exact
-    integrals; near-singular cancellation leaves ~1e-11..1e-10;
-  * FP64 operator / inter-body sum / preconditioner:   1e-11;
-  * FP32 operator:  3e-5 -- FP32 rounding of coordinates (kappa |x| 2^-24 phase),
-    the hardware sin/cos and FP32 accumulation over all sources;
+Tolerances (relative to the largest entry of the compared quantity), each
+within about 10x of what is seen and derived from the arithmetic where it is
+not FP64 rounding (tests/tolerances.py):
+  * setup matrices A~_m and S_m (FP64 on the device): MODAL_TOL = 2e-12 -- both
+    sides integrate the same exact integrals, the reference to its rounding
+    floor (5e-13), the device with a graded Gauss rule; 9e-14 to 3e-13 seen on
+    spheres and the small spheroid.  COARSE_SPHEROID_TOL = 5e-11 where a
+    spheroid has 5 or fewer panels: on the near panels of its pole-adjacent
+    targets (r ~ 0.01) the two rules differ by up to 2.5e-11 (both converged
+    under their own refinement; far entries agree to 4e-16);
+  * FP64 inter-body sum: FP64_TOL = 1e-13 (2e-15 to 3e-14 seen); with the
+    per-mode inverses in it (preconditioner, operator): FP64_OP_TOL = 1e-12
+    (1.2e-13 seen: the inverses' agreement);
+  * FP32 inter-body sum and operator: fp32_sum_bound = 2^-24 (kappa R_max + 64)
+    -- each pair's phase rounded as FP32 revolutions (kappa R 2^-24) plus the
+    rounding of 1/sqrt, the hardware sin/cos and the sums; 2^-20 more per
+    product for the FP16 multiply-accumulate; pairs far closer than the
+    bodies' sizes add the cancellation of |p|^2 - 2 y.p + |y|^2
+    (close_pair_bound);
   * solves to tol 1e-11: 1e-8 (condition number of the second-kind system times tol).
 """
 import math
@@ -17,6 +29,13 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+from tolerances import close_pair_bound, fp32_sum_bound  # noqa: E402
+
+MODAL_TOL = 2e-12
+COARSE_SPHEROID_TOL = 5e-11
+FP64_TOL = 1e-13
+FP64_OP_TOL = 1e-12
 
 
 def rel(a, b):
@@ -61,7 +80,7 @@ def test_modal_matrices_match_reference(small):
         e_a = rel(A_gpu, sh.modal_matrices())
         e_s = rel(S_gpu, sh.inverses())
         print(f"body {bid}: A~ rel err {e_a:.2e}, S rel err {e_s:.2e}")
-        assert e_a < 1e-9 and e_s < 1e-9
+        assert e_a < MODAL_TOL and e_s < MODAL_TOL
 
 
 def test_node_geometry_matches_reference(small):
@@ -84,8 +103,8 @@ def test_interbody_sum_fp64_and_fp32(small, nrhs):
     ref = S.apply_B(sig.T).T
     y64 = ctx.apply_interbody(_dev(sig), FP64).cpu().numpy()
     y32 = ctx.apply_interbody(_dev(sig), FP32).cpu().numpy()
-    assert rel(y64, ref) < 1e-12, rel(y64, ref)
-    assert rel(y32, ref) < 3e-5, rel(y32, ref)
+    assert rel(y64, ref) < FP64_TOL, rel(y64, ref)
+    assert rel(y32, ref) < fp32_sum_bound(wl), rel(y32, ref)
 
 
 def test_preconditioner_matches_reference(small):
@@ -95,8 +114,9 @@ def test_preconditioner_matches_reference(small):
     ref = S.apply_Dinv(x.T).T
     y64 = ctx.apply_precond(_dev(x), FP64).cpu().numpy()
     y32 = ctx.apply_precond(_dev(x), FP32).cpu().numpy()
-    assert rel(y64, ref) < 1e-11, rel(y64, ref)
-    assert rel(y32, ref) < 3e-5, rel(y32, ref)
+    print(f"preconditioner: FP64 {rel(y64, ref):.2e}, FP32 {rel(y32, ref):.2e}")
+    assert rel(y64, ref) < FP64_OP_TOL, rel(y64, ref)
+    assert rel(y32, ref) < fp32_sum_bound(wl), rel(y32, ref)
 
 
 @pytest.mark.parametrize("nrhs", [1, 4])
@@ -107,8 +127,9 @@ def test_preconditioned_operator(small, nrhs):
     ref = np.stack([S.matvec(s) for s in sig])
     y64 = ctx.apply_matvec(_dev(sig), FP64).cpu().numpy()
     y32 = ctx.apply_matvec(_dev(sig), FP32).cpu().numpy()
-    assert rel(y64, ref) < 1e-11, rel(y64, ref)
-    assert rel(y32, ref) < 3e-5, rel(y32, ref)
+    print(f"operator, {nrhs} rhs: FP64 {rel(y64, ref):.2e}, FP32 {rel(y32, ref):.2e}")
+    assert rel(y64, ref) < FP64_OP_TOL, rel(y64, ref)
+    assert rel(y32, ref) < fp32_sum_bound(wl), rel(y32, ref)
 
 
 def test_operator_is_bitwise_reproducible(small):
@@ -127,7 +148,7 @@ def test_interbody_launch_shapes_agree(small):
     wl, S, ctx = small
     x = _dev(_rand(S.N, 3, 43))
     ref = S.apply_B(x.cpu().numpy().T).T
-    for prec, tol in ((FP64, 1e-12), (FP32, 3e-5)):
+    for prec, tol in ((FP64, FP64_TOL), (FP32, fp32_sum_bound(wl))):
         for variant in (1, 2):
             for tpt, block, splits in ((1, 128, 1), (2, 256, 3), (4, 256, 7), (8, 256, 2), (4, 128, 16)):
                 ctx.set_interbody_config(prec, variant, tpt, block, splits)
@@ -153,7 +174,7 @@ def test_ring_order_at_the_tile_limit(M, fits128):
     ctx.precompute_scattering()
     x = _dev(_rand(S.N, 2, 47))
     ref = S.apply_B(x.cpu().numpy().T).T
-    for prec, tol in ((FP64, 1e-12), (FP32, 3e-5)):
+    for prec, tol in ((FP64, FP64_TOL), (FP32, fp32_sum_bound(wl))):
         for block in (128, 256):
             ctx.set_interbody_config(prec, 2, 1, block, 0)
             if block == 128 and not fits128:
@@ -322,6 +343,26 @@ def test_warm_start_is_used_and_bad_guess_is_dropped(small):
     assert np.linalg.norm((sol3 - sol).cpu().numpy()) <= 1e-8 * np.linalg.norm(sol.cpu().numpy())
 
 
+def test_mixed_solve_takes_the_guess_into_its_first_preconditioner_step(small):
+    """Mixed mode: a good guess enters the first flexible-preconditioner step
+    (kept, fewer FP32 iterations, the same FP64-certified answer); a guess whose
+    FP32 residual exceeds ||b|| is dropped and the solve is bit for bit the one
+    from zero."""
+    from paper_1406_0236_amd import SOLVE_FP64, SOLVE_MIXED
+    wl, S, ctx = small
+    vd = ctx.incident_plane_waves(wl.dirs)
+    sol, _ = ctx.solve(vd, mode=SOLVE_FP64, tol=1e-12)
+    zero, iz = ctx.solve(vd, mode=SOLVE_MIXED, tol=1e-9, certify=True)
+    warm, iw = ctx.solve(vd, sigma0=(sol * (1 + 1e-3)).contiguous(), mode=SOLVE_MIXED, tol=1e-9, certify=True)
+    print(f"mixed from zero: {iz[0]}; from the guess: {iw[0]}")
+    assert iw[0]["used_warm_start"] == 1 and iw[0]["converged"] and iw[0]["rel_residual"] <= 1e-9
+    assert iw[0]["inner_iterations"] < iz[0]["inner_iterations"]
+    assert np.linalg.norm((warm - sol).cpu().numpy()) <= 1e-7 * np.linalg.norm(sol.cpu().numpy())
+    bad, ib = ctx.solve(vd, sigma0=sol * 1e3, mode=SOLVE_MIXED, tol=1e-9, certify=True)
+    assert ib[0]["used_warm_start"] == 0
+    assert torch.equal(bad, zero)
+
+
 def test_not_converged_status(small):
     from paper_1406_0236_amd import SOLVE_FP64
     wl, S, ctx = small
@@ -422,7 +463,23 @@ def test_two_spheres_modal_matrices(c1):
     sh = S.bodies[0].shape
     e = rel(ctx.modal_matrices(0, 1, sh.M, sh.NG).cpu().numpy(), sh.inverses())
     print("S rel err", e)
-    assert e < 1e-9
+    assert e < MODAL_TOL
+
+
+def test_two_spheres_operator_fp32_and_fp64(c1):
+    """The benchmark's small case (two spheres, kappa = pi, N = 8,200): the whole
+    preconditioned operator in both precisions against the reference on two
+    random densities.  FP32 within 1e-6 (the FP32 phase error kappa R 2^-24 is
+    9e-7 at R_max = 5; the FP32 part is D^{-1} B sigma, about a third of the
+    largest entry), FP64 within 1e-12."""
+    from paper_1406_0236_amd import FP32, FP64
+    wl, S, ctx = c1
+    sig = _rand(S.N, 2, 101)
+    ref = np.stack([S.matvec(c) for c in sig])
+    for prec, tol in ((FP64, FP64_OP_TOL), (FP32, 1e-6)):
+        e = rel(ctx.apply_matvec(_dev(sig), prec).cpu().numpy(), ref)
+        print(f"two spheres, precision {prec}: operator rel err {e:.2e} (bound {tol:.1e})")
+        assert e < tol, e
 
 
 def test_two_spheres_solve_matches_reference(c1):
@@ -464,7 +521,8 @@ def test_mixed_bodies_modal_matrices(mixed):
         e = rel(ctx.modal_matrices(bid, 0, sh.M, sh.NG).cpu().numpy(), sh.modal_matrices())
         es = rel(ctx.modal_matrices(bid, 1, sh.M, sh.NG).cpu().numpy(), sh.inverses())
         print(f"body {bid} ({wl.bodies[bid].contour.kind}, NG={sh.NG}): A~ {e:.2e} S {es:.2e}")
-        assert e < 1e-9 and es < 1e-9
+        tol = COARSE_SPHEROID_TOL if wl.bodies[bid].contour.kind == "prolate" else MODAL_TOL
+        assert e < tol and es < tol
 
 
 def test_mixed_bodies_operator_64_rhs(mixed):
@@ -474,7 +532,7 @@ def test_mixed_bodies_operator_64_rhs(mixed):
     sig = _rand(S.N, 64, 61)
     picks = [0, 37, 63]
     ref = np.stack([S.matvec(sig[c]) for c in picks])
-    for prec, tol in ((FP64, 1e-11), (FP32, 3e-5)):
+    for prec, tol in ((FP64, FP64_TOL), (FP32, fp32_sum_bound(wl))):
         y = ctx.apply_matvec(_dev(sig), prec).cpu().numpy()[picks]
         e = rel(y, ref)
         print(f"prec {prec}: rel err {e:.2e}")
@@ -506,7 +564,7 @@ def test_autotuner_choice_is_valid(small, tmp_path):
     assert len(timings) >= 4 and all(t > 0 for t in timings.values())
     x = _rand(S.N, 2, 71)
     y = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
-    assert rel(y, S.apply_B(x.T).T) < 3e-5
+    assert rel(y, S.apply_B(x.T).T) < fp32_sum_bound(wl)
     # cached: a second call reuses the choice without timing
     cfg2, _ = autotune.tune(ctx, FP32, 2, ctx.max_nf, cache_path=str(tmp_path / "cache.json"))
     assert list(cfg2) == list(cfg)
@@ -524,7 +582,7 @@ def test_rhs_groups_fp32_rings(small):
         y = ctx.apply_interbody(_dev(sig), FP32).cpu().numpy()
         e = rel(y, ref)
         print(f"tpt {tpt}: rel err {e:.2e}")
-        assert e < 3e-5, e
+        assert e < fp32_sum_bound(wl), e
     ctx.set_interbody_config(FP32, 0, 0, 0, 0)
 
 
@@ -536,7 +594,7 @@ def test_mfma_source_order_matches_reference(small):
     wl, S, ctx = small
     x = _rand(S.N, 3, 91)
     ref = S.apply_B(x.T).T
-    for prec, tol in ((FP32, 3e-5), (FP64, 1e-12)):
+    for prec, tol in ((FP32, fp32_sum_bound(wl)), (FP64, FP64_TOL)):
         for g, splits in ((1, 1), (2, 3), (4, 0), (2, 16)):
             ctx.set_interbody_config(prec, 3, g, 256, splits)
             y = ctx.apply_interbody(_dev(x), prec).cpu().numpy()
@@ -554,7 +612,7 @@ def test_mfma_accumulation_16_wide(small):
     wl, S, ctx = small
     x = _rand(S.N, 37, 92)
     ref = S.apply_B(x.T).T
-    for prec, tol in ((FP32, 3e-5), (FP64, 1e-12)):
+    for prec, tol in ((FP32, fp32_sum_bound(wl)), (FP64, FP64_TOL)):
         for g in (1, 2, 4):
             ctx.set_interbody_config(prec, 3, g, 256, 0)
             y = ctx.apply_interbody(_dev(x), prec).cpu().numpy()
@@ -588,7 +646,7 @@ def test_fp16_multiply_accumulate_matches_reference(small):
         y = ctx.apply_interbody(_dev(x), FP32).cpu().numpy()
         e, e3 = rel(y, ref), rel(y, y3)
         print(f"G {g} splits {splits}: rel err {e:.2e}, vs FP32 MFMA order {e3:.2e}")
-        assert e < 3e-5 and e3 < 2e-6, (g, splits, e, e3)
+        assert e < fp32_sum_bound(wl, 16) and e3 < 2e-6, (g, splits, e, e3)
         assert np.array_equal(y, ctx.apply_interbody(_dev(x), FP32).cpu().numpy())
     ctx.set_interbody_config(FP32, 0, 0, 0, 0)
     ctx.set_interbody_config(FP64, 4, 2, 256, 0)
@@ -611,7 +669,7 @@ def test_fp16_multiply_accumulate_scales_each_rhs(small):
     assert np.all(y[7] == 0)
     worst = max(rel(y[c], ref[c]) for c in range(16) if c != 7)
     print(f"worst column rel err {worst:.2e}")
-    assert worst < 3e-5, worst
+    assert worst < fp32_sum_bound(wl, 16), worst
 
 
 def _edge_workload(tip_gap):
@@ -652,7 +710,7 @@ def test_fp16_multiply_accumulate_ragged_blocks():
                 e = max(rel(y[c], ref[c]) for c in range(nrhs))
                 e3 = max(rel(y[c], y3[c]) for c in range(nrhs))
                 print(f"{nrhs} rhs, G {g}: worst column rel err {e:.2e}, vs FP32 MFMA order {e3:.2e}")
-                assert e < 3e-5 and e3 < 2e-6, (nrhs, g, e, e3)
+                assert e < fp32_sum_bound(wl, 16) and e3 < 2e-6, (nrhs, g, e, e3)
     finally:
         ctx.set_interbody_config(FP32, 0, 0, 0, 0)
         ctx.close()
@@ -666,7 +724,7 @@ def test_fp16_multiply_accumulate_negative_scale_exponent():
     gaps: the MFMA and ring orders form R^2 as |p|^2 - 2 y.p + |y|^2 in the
     source body's frame, which loses about eps32 |p|^2 / R^2 in relative terms
     for pairs this close (the FP64 outer iteration of the mixed solver
-    absorbs it); that error is printed and bounded loosely."""
+    absorbs it); that error is printed and bounded by close_pair_bound."""
     from oracle.multibody import System
     from paper_1406_0236_amd import FP32
     wl = _edge_workload(0.01)
@@ -683,7 +741,9 @@ def test_fp16_multiply_accumulate_negative_scale_exponent():
         e = max(rel(y[c], ref[c]) for c in range(17))
         print(f"gap 0.01: FP16 vs FP32 MFMA order {e3:.2e}; vs FP64 reference {e:.2e}")
         assert e3 < 2e-6, e3
-        assert e < 1e-2, e
+        bound = close_pair_bound(wl) + fp32_sum_bound(wl, 16)
+        print(f"derived bound {bound:.2e}")
+        assert e < bound, (e, bound)
     finally:
         ctx.set_interbody_config(FP32, 0, 0, 0, 0)
         ctx.close()
@@ -714,7 +774,7 @@ def test_maximum_rhs_count():
         cols = [0, 1, 1000, 2047, 4095]
         ref = np.stack([S.matvec(x[c]) for c in cols])
         xd = _dev(x)
-        for prec, tol in ((FP64, 1e-11), (FP32, 3e-5)):
+        for prec, tol in ((FP64, FP64_TOL), (FP32, fp32_sum_bound(wl))):
             y = ctx.apply_matvec(xd, prec).cpu().numpy()
             e = rel(y[cols], ref)
             print(f"prec {prec}, 4096 rhs, launch shape {ctx.interbody_launch_shape(prec, 4096)}: "
@@ -742,11 +802,13 @@ def test_lowest_mode_counts():
         for bid, body in enumerate(S.bodies):
             sh = body.shape
             e = rel(ctx.modal_matrices(bid, 1, sh.M, sh.NG).cpu().numpy(), sh.inverses())
-            assert e < 1e-9, (bid, e)
+            print(f"body {bid} ({wl.bodies[bid].contour.kind}, NG={sh.NG}, M={sh.M}): S {e:.2e}")
+            tol = COARSE_SPHEROID_TOL if wl.bodies[bid].contour.kind == "prolate" else MODAL_TOL
+            assert e < tol, (bid, e)
         for nrhs, seed in ((1, 81), (17, 82)):
             x = _rand(S.N, nrhs, seed)
             ref = np.stack([S.matvec(x[c]) for c in range(nrhs)])
-            for prec, tol in ((FP64, 1e-11), (FP32, 3e-5)):
+            for prec, tol in ((FP64, 1e-11), (FP32, fp32_sum_bound(wl, 16))):
                 for variant in (0, 1, 2, 3):
                     ctx.set_interbody_config(prec, variant, 0, 0, 0)
                     y = ctx.apply_matvec(_dev(x), prec).cpu().numpy()
@@ -802,7 +864,7 @@ def test_target_body_range_is_one_gpus_share(mixed):
         e = rel(part[:2, lo:hi], ref[:, lo:hi])
         print(f"prec {prec}, {nrhs} rhs, launch shape {ctx.interbody_launch_shape(prec, nrhs)}: "
               f"rows of bodies 2-4 rel err {e:.2e}")
-        assert e < (1e-11 if prec == FP64 else 3e-5)
+        assert e < (FP64_TOL if prec == FP64 else fp32_sum_bound(wl, 16 if nrhs >= 16 else 0))
     assert np.array_equal(ctx.apply_interbody(x, FP32).cpu().numpy(), ctx.apply_interbody(x, FP32).cpu().numpy())
     with pytest.raises(AxsError, match="EINVAL"):
         ctx.set_target_bodies(7, 2)
@@ -821,5 +883,5 @@ def test_mfma_source_order_mixed_bodies_64_rhs(mixed):
         y = ctx.apply_interbody(_dev(sig), FP32).cpu().numpy()[picks]
         e = rel(y, ref)
         print(f"mixed bodies, MFMA order (variant {variant}), 64 rhs: rel err {e:.2e}")
-        assert e < 3e-5, (variant, e)
+        assert e < fp32_sum_bound(wl, 16), (variant, e)
     ctx.set_interbody_config(FP32, 0, 0, 0, 0)
