@@ -119,6 +119,26 @@ axs_status axs_modal_matrices(axs_ctx *ctx, int body_id, int which, void *out);
  * holds for axs_apply_interbody and axs_apply_precond below. */
 axs_status axs_apply_matvec(axs_ctx *ctx, const void *sigma, void *y, int nrhs, int precision);
 
+/* axs_apply_matvec without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and result as axs_apply_matvec (the same
+ * kernels); the library's scratch for the call -- staged densities, inter-body
+ * partial sums, DFT workspaces, and the work table where the launch shape's
+ * table is not cached yet -- is a file-scope device array of 256 MiB on each
+ * device (taken at axs_create, held until the process ends), so:
+ *  - sizes whose scratch exceeds 256 MiB are refused (AXS_EINVAL, the message
+ *    gives the bytes needed): nrhs x N x (splits + 3) x 16 bytes in FP64, half
+ *    that in FP32 (the 27-sphere workload: one rhs in either precision);
+ *  - only the point and ring orders of the inter-body sum run here (the
+ *    defaults below 16 right-hand sides); a context configured for the MFMA
+ *    orders gets AXS_EINVAL;
+ *  - every call on a device shares that device's array: calls that overlap
+ *    on one device (other streams, other contexts, other threads) race;
+ *  - no scan for NaN/Inf and no synchronisation, except on the first call
+ *    with a launch shape whose work table is not cached (one synchronous
+ *    host-to-device copy of the table into the array). */
+axs_status axs_apply_matvec_noalloc(axs_ctx *ctx, const void *sigma, void *y, int nrhs, int precision);
+
 /* Building blocks of the operator, same layouts as axs_apply_matvec:
  *   axs_apply_interbody : y = B sigma        (inter-body sum alone)
  *   axs_apply_precond   : y = D^{-1} x       (per-body DFT, S_m applies, inverse DFT) */

@@ -80,6 +80,8 @@ EXPORTS = {
     "axs_modal_matrices": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "axs_apply_matvec": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                           ctypes.c_int]),
+    "axs_apply_matvec_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                                  ctypes.c_int]),
     "axs_apply_interbody": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                              ctypes.c_int]),
     "axs_apply_precond": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
@@ -267,6 +269,11 @@ class Context:
 
     def apply_matvec(self, sigma, precision=FP64, out=None):
         return self._apply(self.lib.axs_apply_matvec, sigma, precision, out)
+
+    def apply_matvec_noalloc(self, sigma, precision=FP64, out=None):
+        """axs_apply_matvec_noalloc: the operator with the library's static scratch (out is
+        allocated here by torch unless given)."""
+        return self._apply(self.lib.axs_apply_matvec_noalloc, sigma, precision, out)
 
     def apply_interbody(self, sigma, precision=FP64, out=None):
         return self._apply(self.lib.axs_apply_interbody, sigma, precision, out)

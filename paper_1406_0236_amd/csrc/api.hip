@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 
 #include "axs_internal.h"
 
@@ -40,6 +41,15 @@ void Ctx::dfree(void *p) {
 }
 
 void *Ctx::scratch(int slot, size_t bytes) {
+    if (arena) {
+        if (arena_slot[slot] && bytes <= arena_slot_bytes[slot]) return arena_slot[slot];
+        const size_t need = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        AXS_REQUIRE(arena_top + need <= arena_cap, AXS_EINVAL, "static scratch exhausted");
+        arena_slot[slot] = arena + arena_top;
+        arena_slot_bytes[slot] = need;
+        arena_top += need;
+        return arena_slot[slot];
+    }
     Buffer &b = ws[slot];
     if (bytes > b.bytes) {
         if (b.ptr) {
@@ -290,6 +300,50 @@ void finish_precompute(Ctx &c) {
     c.precomputed = true;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the no-allocation operator (axs_apply_matvec_noalloc): a
+// file-scope device array, NOALLOC_BYTES on every device the library runs on,
+// held until the process ends.  Host code never uses the array's name as an
+// address: at set-up (axs_create, once per device, with that device current)
+// its device address is taken with hipGetSymbolAddress and kept per device.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// the device address of `scratch` on the current device `device`; hipSuccess or the error
+static hipError_t setup_static_scratch(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_ptr[device] = p;
+    return e;
+}
+
+static void *static_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return device >= 0 && device < MAX_DEVICES ? g_scratch_ptr[device] : nullptr;
+}
+
+// scratch() draws from the static array for the lifetime of this object
+struct ArenaScope {
+    Ctx &c;
+    ArenaScope(Ctx &c_, void *base, size_t cap) : c(c_) {
+        c.arena = (char *)base;
+        c.arena_cap = cap;
+        c.arena_top = 0;
+        for (int k = 0; k < 19; ++k) {
+            c.arena_slot[k] = nullptr;
+            c.arena_slot_bytes[k] = 0;
+        }
+    }
+    ~ArenaScope() { c.arena = nullptr; }
+};
+
 }  // namespace axs
 
 using axs::Ctx;
@@ -343,6 +397,10 @@ axs_status axs_create(axs_ctx **out, int device, void *hip_stream, axs_alloc_fn 
             delete ctx;
             return AXS_EHIP;
         }
+    }
+    if (axs::setup_static_scratch(device) != hipSuccess) {
+        delete ctx;
+        return AXS_EHIP;
     }
     *out = ctx;
     return AXS_OK;
@@ -514,6 +572,27 @@ axs_status axs_apply_matvec(axs_ctx *ctx, const void *sigma, void *y, int nrhs, 
         check_apply(c, sigma, y, nrhs, precision);
         require_all_targets(c);
         axs::require_finite(c, sigma, (int64_t)nrhs * c.N, "sigma");
+        axs::apply_operator(c, sigma, y, nrhs, precision);
+        return AXS_OK;
+    });
+}
+
+axs_status axs_apply_matvec_noalloc(axs_ctx *ctx, const void *sigma, void *y, int nrhs, int precision) {
+    return guarded(ctx, [&](Ctx &c) -> axs_status {
+        check_apply(c, sigma, y, nrhs, precision);
+        require_all_targets(c);
+        const int64_t ib = axs::interbody_scratch_bytes(c, precision, nrhs);
+        AXS_REQUIRE(ib >= 0, AXS_EINVAL,
+                    "the no-allocation operator runs the point and ring orders of the inter-body sum only "
+                    "(the defaults below 16 right-hand sides)");
+        const int64_t e = precision == AXS_FP32 ? 4 : 8, x = ((int64_t)nrhs * c.N * e + 255) / 256 * 256;
+        const int64_t need = ib + 4 * x;   // + the DFT workspaces (planar re and im, forward and back)
+        AXS_REQUIRE(need <= (int64_t)axs::NOALLOC_BYTES, AXS_EINVAL,
+                    "the operator needs " + std::to_string(need) + " bytes of scratch, beyond the static " +
+                        std::to_string(axs::NOALLOC_BYTES) + ": fewer right-hand sides per call");
+        void *base = axs::static_scratch(c.device);
+        AXS_REQUIRE(base, AXS_ESTATE, "static scratch not set up on this device");
+        axs::ArenaScope arena(c, base, axs::NOALLOC_BYTES);
         axs::apply_operator(c, sigma, y, nrhs, precision);
         return AXS_OK;
     });

@@ -197,6 +197,12 @@ struct Ctx {
     std::vector<void *> owned;
     // named scratch buffers (grow-only)
     Buffer ws[19];
+    // while `arena` is set, scratch() hands out slices of that caller-supplied
+    // region instead (one slice per slot, bump order) and allocates nothing
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_top = 0;
+    void *arena_slot[19] = {};
+    size_t arena_slot_bytes[19] = {};
 
     void *dalloc(size_t bytes);
     void dfree(void *p);
@@ -250,6 +256,10 @@ void modal_values(Ctx &c, double kappa, double gam_re, double gam_im, int M, int
 void finish_precompute(Ctx &c);
 // interbody.hip
 void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec);   // -> WS_PART
+// bytes of scratch the inter-body sum takes in `prec` with nrhs rhs (staged
+// densities, partial sums, and the work table where it is not cached), each
+// rounded up to 256; -1 for the MFMA orders (variants 3 and 4)
+int64_t interbody_scratch_bytes(Ctx &c, int prec, int nrhs);
 void interbody_reduce_to_c128(Ctx &c, void *y, int nrhs, int prec, bool add = false);  // WS_PART -> (+)y
 int interbody_splits(Ctx &c, int prec, int nrhs);
 void eval_field_launch(Ctx &c, const void *sigma, int nrhs, const double *tgt_dev, int nt,

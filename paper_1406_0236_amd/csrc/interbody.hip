@@ -1434,6 +1434,15 @@ static const IBWork *get_work(Ctx &c, int pi, int wi, const IBShape &s, Units un
         key[4] != c.tgt_first || key[5] != c.tgt_count) {
         // work tables are cached per launch shape; rebuilt only when it changes
         std::vector<IBWork> work = build_work(c, ib_tile(s), s.splits, units);
+        if (c.arena) {
+            // no allocation: the table goes to the caller's region for this call
+            // only (the cache is left as it is)
+            IBWork *t = (IBWork *)c.scratch(WS_WORK, work.size() * sizeof(IBWork));
+            AXS_HIP(hipMemcpyAsync(t, work.data(), work.size() * sizeof(IBWork), hipMemcpyHostToDevice, c.stream));
+            AXS_HIP(hipStreamSynchronize(c.stream));   // work is pageable host memory
+            nwork = (int)work.size();
+            return t;
+        }
         if (c.ib_work[pi][wi]) {
             AXS_HIP(hipStreamSynchronize(c.stream));
             c.dfree(c.ib_work[pi][wi]);
@@ -1497,6 +1506,22 @@ static void launch_mf16(Ctx &c, const IBShape &s, const float2 *q, int nrhs, flo
         else if (s.tpt == 2) launch_mf<float, 2>(c, work, nwork, q, nrhs, part, 16 * groups);
         else launch_mf<float, 4>(c, work, nwork, q, nrhs, part, 16 * groups);
     }
+}
+
+int64_t interbody_scratch_bytes(Ctx &c, int prec, int nrhs) {
+    const int pi = prec == AXS_FP32 ? 1 : 0;
+    const IBShape s = launch_shape(c, prec, nrhs);
+    if (s.variant != 1 && s.variant != 2) return -1;
+    auto r256 = [](int64_t b) { return (b + 255) / 256 * 256; };
+    const int64_t total = (int64_t)nrhs * c.N, e2 = prec == AXS_FP32 ? 8 : 16;
+    int64_t bytes = r256(total * e2) + r256((int64_t)s.splits * total * e2);
+    const int *key = c.ib_key[pi][0];
+    const bool cached = c.ib_work[pi][0] && key[0] == s.tpt && key[1] == s.bs && key[2] == s.splits &&
+                        key[3] == s.variant && key[4] == c.tgt_first && key[5] == c.tgt_count;
+    if (!cached)
+        bytes += r256((int64_t)build_work(c, ib_tile(s), s.splits, s.variant == 2 ? Units::rings : Units::nodes).size() *
+                      (int64_t)sizeof(IBWork));
+    return bytes;
 }
 
 void interbody_partials(Ctx &c, const void *sigma, int nrhs, int prec) {
