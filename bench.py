@@ -45,7 +45,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
 # source they were taken on (source_fingerprint: code, not comments).
 TRAFFIC_BYTES = 115.16e6
-TRAFFIC_SOURCE_SHA = "22e531a2bd90c94d"
+TRAFFIC_SOURCE_SHA = "4e659edad0dc3744"
 
 
 def source_fingerprint(path):
