@@ -300,8 +300,45 @@ axs_status axs_set_target_bodies(axs_ctx *ctx, int first_body, int count);
  * FP64 on the device; replaces an earlier skeleton system of the context. */
 axs_status axs_skeletonize(axs_ctx *ctx, double eps, double proxy_factor, int64_t *out_nskel);
 
-/* Skeleton rings k and contour nodes NG of a body's shape (host ints). */
+/* Point skeletons (Sec. 5 with index sets of single nodes; the remark of
+ * Sec. 5 on randomized sampling): the row ID runs over the N_G N_F nodes of a
+ * shape against the proxy matrix H[(i, l), (m, c)] = Hm[i, c] e^{i m theta_l},
+ * m = -M..M, Hm = [IN_|m| | OUT_|m|^T] (the proxy fields of the ring version,
+ * n_proxy polar points per proxy sphere), taken of the Gaussian sketch
+ * Psi H^* (Psi: ell x (2M+1) 3 n_proxy, complex Gaussian, entry (s, r) the
+ * conjugate of draw s (2M+1) 3 n_proxy + r of the generator below).  Nodes are
+ * chosen by Householder QR with randomized column pivoting of the sketch
+ * (blocks of 64 pivots); the rank k is the first pivot with |R_kk| < eps
+ * |R_00|; ell doubles from 256 until k <= ell - 16.  Then U_p = V_p = X
+ * (N_G N_F x k), S_p = X^T A_pp^{-1} X is dense k x k (FP64 and FP32 copies),
+ * B~ is the point-order inter-body sum over the skeleton nodes, and
+ * axs_solve_skeleton solves through it.
+ *  eps, proxy_factor : as for axs_skeletonize; every shape needs a proxy
+ *                 radius of at least 1.05 x its bounding radius (AXS_EINVAL).
+ *  n_proxy      : polar proxy points per sphere, 0 for 40 + ceil(1.25 kappa R_p).
+ *  seed         : the sketch's stream: uniform draw k is (splitmix64(seed *
+ *                 0x632BE59BD9B4E019 + k) >> 11 + 0.5) 2^-53, complex Gaussian
+ *                 draw e is sqrt(-2 ln u_2e) e^{2 pi i u_(2e+1)} (Box-Muller).
+ *  out_nskel    : host int64, number of skeleton nodes (may be NULL).
+ * FP64 on the device (rocBLAS / rocSOLVER for the dense factorizations and
+ * products); replaces an earlier skeleton system of the context. */
+axs_status axs_skeletonize_points(axs_ctx *ctx, double eps, double proxy_factor, int n_proxy, uint64_t seed,
+                                  int64_t *out_nskel);
+
+/* Skeleton rings k and contour nodes NG of a body's shape (host ints); for
+ * point skeletons the skeleton nodes k and the nodes N_G N_F of the shape. */
 axs_status axs_skeleton_rank(axs_ctx *ctx, int body_id, int *rings, int *contour_nodes);
+
+/* The skeleton nodes of a body as local node indices i N_F + l, ascending
+ * (ring skeletons: every azimuthal node of each skeleton ring).  count (host
+ * int) returns their number; nodes (host int array of *count entries on input,
+ * or NULL to query the number) receives them.  AXS_EINVAL if *count is too small. */
+axs_status axs_skeleton_nodes(axs_ctx *ctx, int body_id, int *count, int *nodes);
+
+/* Point skeletons only (AXS_ESTATE otherwise): copies X^T of the body's shape,
+ * k x N_G N_F column-major complex128 (column j = row j of X, rows in the order
+ * of axs_skeleton_nodes), into xt (device, caller-allocated). */
+axs_status axs_skeleton_interp(axs_ctx *ctx, int body_id, void *xt);
 
 /* Solve through the skeleton system; incident and sigma as for axs_solve
  * (device complex128 [nrhs][N], full-size).  mode: AXS_SOLVE_FP64 or

@@ -99,8 +99,13 @@ EXPORTS = {
     "axs_last_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "axs_skeletonize": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                          ctypes.POINTER(ctypes.c_int64)]),
+    "axs_skeletonize_points": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                ctypes.c_uint64, ctypes.POINTER(ctypes.c_int64)]),
     "axs_skeleton_rank": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                            ctypes.POINTER(ctypes.c_int)]),
+    "axs_skeleton_nodes": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                            ctypes.c_void_p]),
+    "axs_skeleton_interp": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "axs_solve_skeleton": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                             ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.POINTER(SolveInfo)]),
     "axs_interbody_launch_shape": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
@@ -305,8 +310,32 @@ class Context:
         self._check(self.lib.axs_skeletonize(self.h, float(eps), float(proxy_factor), ctypes.byref(n)))
         return n.value
 
+    def skeletonize_points(self, eps=1e-8, proxy_factor=2.0, n_proxy=0, seed=1):
+        """axs_skeletonize_points; returns the number of skeleton nodes."""
+        n = ctypes.c_int64()
+        self._check(self.lib.axs_skeletonize_points(self.h, float(eps), float(proxy_factor), int(n_proxy),
+                                                    int(seed) & ((1 << 64) - 1), ctypes.byref(n)))
+        return n.value
+
+    def skeleton_nodes(self, body_id):
+        """Ascending local node indices of a body's skeleton (numpy int32)."""
+        cnt = ctypes.c_int(0)
+        self._check(self.lib.axs_skeleton_nodes(self.h, int(body_id), ctypes.byref(cnt), None))
+        out = np.zeros(max(cnt.value, 1), dtype=np.int32)
+        self._check(self.lib.axs_skeleton_nodes(self.h, int(body_id), ctypes.byref(cnt), _ptr(out)))
+        return out[:cnt.value]
+
+    def skeleton_interp(self, body_id):
+        """X^T of a body's point skeleton: complex128 tensor (k, N_G N_F) on the device
+        (the transpose of the column-major k x n matrix the library returns)."""
+        k, n = self.skeleton_rank(body_id)
+        xt = self._torch.empty((n, k), dtype=self._torch.complex128, device=f"cuda:{self.device}")
+        self._check(self.lib.axs_skeleton_interp(self.h, int(body_id), ctypes.c_void_p(xt.data_ptr())))
+        return xt.T
+
     def skeleton_rank(self, body_id):
-        """(skeleton rings, contour nodes) of a body's shape."""
+        """(skeleton rings, contour nodes) of a body's shape; for point skeletons
+        (skeleton nodes, nodes)."""
         k, ng = ctypes.c_int(), ctypes.c_int()
         self._check(self.lib.axs_skeleton_rank(self.h, int(body_id), ctypes.byref(k), ctypes.byref(ng)))
         return k.value, ng.value

@@ -64,6 +64,8 @@ void *Ctx::scratch(int slot, size_t bytes) {
 
 Ctx::~Ctx() {
     if (stream) (void)hipStreamSynchronize(stream);
+    skel.reset();   // the child context first (it borrows this context's tables)
+    destroy_blas(*this);
     for (void *p : std::vector<void *>(owned)) dfree(p);
     for (auto &e : ev)
         if (e) (void)hipEventDestroy(e);
@@ -121,6 +123,10 @@ static void finish_timing(Ctx &c, bool with_ib) {
 }
 
 void apply_operator(Ctx &c, const void *sigma, void *y, int nrhs, int prec) {
+    if (c.pop) {   // the compressed system of point skeletons
+        point_operator(c, sigma, y, nrhs, prec);
+        return;
+    }
     rec(c, 0);
     interbody_partials(c, sigma, nrhs, prec);
     rec(c, 1);
@@ -761,6 +767,15 @@ axs_status axs_skeletonize(axs_ctx *ctx, double eps, double proxy_factor, int64_
     });
 }
 
+axs_status axs_skeletonize_points(axs_ctx *ctx, double eps, double proxy_factor, int n_proxy, uint64_t seed,
+                                  int64_t *out_nskel) {
+    return guarded(ctx, [&](Ctx &c) -> axs_status {
+        skeletonize_points(c, eps, proxy_factor, n_proxy, seed);
+        if (out_nskel) *out_nskel = c.skel->Ns;
+        return AXS_OK;
+    });
+}
+
 axs_status axs_skeleton_rank(axs_ctx *ctx, int body_id, int *rings, int *contour_nodes) {
     return guarded(ctx, [&](Ctx &c) -> axs_status {
         AXS_REQUIRE(c.skel, AXS_ESTATE, "call axs_skeletonize first");
@@ -769,7 +784,51 @@ axs_status axs_skeleton_rank(axs_ctx *ctx, int body_id, int *rings, int *contour
         AXS_REQUIRE(body_id >= 0 && body_id < (int)c.bodies.size(), AXS_EINVAL, "bad body id");
         const int sh = c.bodies[body_id].shape;
         *rings = c.skel->rank[sh];
-        *contour_nodes = c.shapes[sh].NG;
+        *contour_nodes = c.skel->kind == 1 ? c.skel->pts->n[sh] : c.shapes[sh].NG;
+        return AXS_OK;
+    });
+}
+
+axs_status axs_skeleton_nodes(axs_ctx *ctx, int body_id, int *count, int *nodes) {
+    return guarded(ctx, [&](Ctx &c) -> axs_status {
+        AXS_REQUIRE(c.skel, AXS_ESTATE, "call axs_skeletonize first");
+        AXS_REQUIRE(count, AXS_EINVAL, "null output");
+        AXS_REQUIRE(body_id >= 0 && body_id < (int)c.bodies.size(), AXS_EINVAL, "bad body id");
+        const int sh = c.bodies[body_id].shape;
+        std::vector<int> out;
+        if (c.skel->kind == 1) {
+            out = c.skel->pts->nodes[sh];
+        } else {
+            // whole rings: the ascending skeleton rings times every azimuthal node
+            const Ctx &ch = *c.skel->child;
+            const axs::Shape &s = c.shapes[sh], &t = ch.shapes[sh];
+            int ring = 0;
+            for (int i = 0; i < s.NG && ring < t.NG; ++i) {
+                if (s.r[i] != t.r[ring] || s.z[i] != t.z[ring]) continue;
+                for (int l = 0; l < s.NF; ++l) out.push_back(i * s.NF + l);
+                ++ring;
+            }
+        }
+        if (nodes) {
+            AXS_REQUIRE(*count >= (int)out.size(), AXS_EINVAL, "node array too small");
+            std::copy(out.begin(), out.end(), nodes);
+        }
+        *count = (int)out.size();
+        return AXS_OK;
+    });
+}
+
+axs_status axs_skeleton_interp(axs_ctx *ctx, int body_id, void *xt) {
+    return guarded(ctx, [&](Ctx &c) -> axs_status {
+        AXS_REQUIRE(c.skel, AXS_ESTATE, "call axs_skeletonize first");
+        AXS_REQUIRE(c.skel->kind == 1, AXS_ESTATE, "interpolation matrices are returned for point skeletons only");
+        AXS_REQUIRE(xt, AXS_EINVAL, "null output");
+        AXS_REQUIRE(body_id >= 0 && body_id < (int)c.bodies.size(), AXS_EINVAL, "bad body id");
+        const axs::PointSkel &P = *c.skel->pts;
+        const int sh = c.bodies[body_id].shape;
+        AXS_HIP(hipMemcpyAsync(xt, P.XT[sh], (size_t)P.k[sh] * P.n[sh] * sizeof(double2), hipMemcpyDeviceToDevice,
+                               c.stream));
+        AXS_HIP(hipStreamSynchronize(c.stream));
         return AXS_OK;
     });
 }

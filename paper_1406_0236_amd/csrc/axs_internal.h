@@ -108,6 +108,7 @@ struct SkelBody {
     int32_t NG, k, NF, pad;
 };
 struct Skeleton;
+struct PointSkel;
 
 struct Ctx {
     int device = 0;
@@ -185,8 +186,13 @@ struct Ctx {
     // stays inside the hardware sin/cos input range (ring and MFMA orders rely on it)
     bool near_phase_ok = false;
 
-    // ring skeletonization (Sec. 5): the compressed system and its factors
+    // skeletonization (Sec. 5): the compressed system and its factors
     std::unique_ptr<Skeleton> skel;
+    // set in the child context of point skeletons: its operator is
+    // s~ + S B~ s~ with dense S_p (the parent's skeleton owns the factors)
+    const PointSkel *pop = nullptr;
+    // rocBLAS handle bound to the stream (dense products of the point skeletons)
+    void *blas = nullptr;
 
     // timing
     bool timing = false;
@@ -232,13 +238,34 @@ enum ScratchSlot {
     WS_FLAG = 18,    // one int: set when an input vector holds NaN or Inf
 };
 
+// Point skeletons: per shape k skeleton nodes of its n = NG NF nodes, the
+// interpolation matrix as X^T (k x n, column-major: column j holds row j of X,
+// columns of X in ascending skeleton node order) and S_p = X^T A_pp^{-1} X
+// (k x k, column-major) in FP64 and FP32; bodies grouped in runs of
+// consecutive bodies of one shape (one batched product per run)
+struct PointRun {
+    int shape, first, nb, k, n;
+    int64_t o0, s0;                      // first full node and first skeleton node of the run
+};
+struct PointSkel {
+    std::vector<int> k, n, ell;          // per shape: skeleton nodes, nodes, sketch width used
+    std::vector<double> R_p;             // per shape: proxy radius
+    std::vector<std::vector<int>> nodes; // per shape: ascending local node indices
+    std::vector<double2 *> XT;           // per shape (device)
+    std::vector<double2 *> S64;
+    std::vector<float2 *> S32;
+    std::vector<PointRun> runs;
+};
+
 struct Skeleton {
-    std::unique_ptr<Ctx> child;          // skeleton rings of every body, S~_m = X^T S_m X
-    double2 *X = nullptr;                // per shape NG x k (row-major, columns by ascending ring)
-    SkelBody *desc = nullptr;            // [bodies]
-    std::vector<int> rank;               // skeleton rings per shape
+    int kind = 0;                        // 0: whole rings, 1: single nodes
+    std::unique_ptr<Ctx> child;          // skeleton of every body: rings with S~_m = X^T S_m X, or nodes
+    double2 *X = nullptr;                // rings: per shape NG x k (row-major, columns by ascending ring)
+    SkelBody *desc = nullptr;            // rings: [bodies]
+    std::vector<int> rank;               // skeleton rings (nodes) per shape
     int64_t Ns = 0;                      // skeleton nodes
     double eps = 0;
+    std::unique_ptr<PointSkel> pts;      // nodes: the factors
 };
 
 // ---------------------------------------------------------------------------
@@ -278,6 +305,12 @@ void dft_inverse(Ctx &c, int prec, const void *sigma, double alpha, double beta,
                  int nrhs);
 // skeleton.hip
 void skeletonize(Ctx &c, double eps, double proxy_factor);
+// point skeletons: n_proxy polar proxy points per sphere (0: 40 + ceil(1.25 kappa R_p)),
+// seed of the Gaussian sketch
+void skeletonize_points(Ctx &c, double eps, double proxy_factor, int n_proxy, uint64_t seed);
+void point_operator(Ctx &c, const void *sigma, void *y, int nrhs, int prec);   // child: y = s + S B~ s
+void release_skeleton(Ctx &c);           // frees the parent-side factors of c.skel
+void destroy_blas(Ctx &c);
 void skel_restrict(Ctx &c, const void *y, void *out, int nrhs, double alpha);      // out = alpha (X^T (x) I) y
 void skel_prolong(Ctx &c, const void *w, const void *add, void *out, int nrhs);   // out = add + (X (x) I) w
 double skel_sumsq(Ctx &c, const double2 *a, int64_t n);

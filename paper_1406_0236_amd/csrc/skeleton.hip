@@ -24,7 +24,11 @@
 // child context built from the skeleton rings with S~_m in place of S_m.
 #include "axs_internal.h"
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include <algorithm>
+#include <cmath>
 #include <numeric>
 
 namespace axs {
@@ -320,9 +324,15 @@ static void proxy_rings(double R, int n, std::vector<double> &r, std::vector<dou
     }
 }
 
-// row ID of one shape: skeleton rings (ascending) and X (device, NG x k)
-static void ring_id(Ctx &c, const Shape &s, double R_p, double eps, std::vector<int> &rings, double2 *&X) {
-    const int NG = s.NG, M = s.M, n_in = NG, n_o = 2 * NG;
+// k^G_m w of the proxy configuration of one shape (Sec. 5, first item):
+// kin [NG n_in][M+1] -- target contour node i, source proxy node j on the
+// sphere of radius R_p with its normal and weight (every field the body can
+// receive); kout [(2 n_out) NG][M+1] -- target proxy node j on the spheres of
+// radii R_p, then 1.25 R_p, source contour node i with its area weight (every
+// field it sends out).  s_in, s_out: 1 / the Frobenius norms of the two.
+static void proxy_fields(Ctx &c, const Shape &s, double R_p, int n_in, int n_out, double2 *&kin, double2 *&kout,
+                         double &s_in, double &s_out) {
+    const int NG = s.NG, M = s.M;
     double need = 4.0 * s.kappa * 1.25 * R_p + 64.0;
     int Nt = 64;
     while (Nt < need) Nt += 64;
@@ -334,7 +344,6 @@ static void ring_id(Ctx &c, const Shape &s, double R_p, double eps, std::vector<
         aw[i] = s.r[i] * sp * s.gw[i];
     }
     const double gr = s.kappa > 0 ? 0.0 : s.eta, gi = s.kappa > 0 ? s.eta : 0.0;
-    // incoming: target contour node i, source proxy node j (its normal and weight)
     std::vector<double> pr, pz, pnr, pnz, pw;
     proxy_rings(R_p, n_in, pr, pz, pnr, pnz, pw);
     const int64_t Pin = (int64_t)NG * n_in;
@@ -350,16 +359,15 @@ static void ring_id(Ctx &c, const Shape &s, double R_p, double eps, std::vector<
             h[5 * Pin + q] = pnz[j];
             h[6 * Pin + q] = pw[j];
         }
-    double2 *kin = (double2 *)c.dalloc((size_t)Pin * (M + 1) * sizeof(double2));
+    kin = (double2 *)c.dalloc((size_t)Pin * (M + 1) * sizeof(double2));
     modal_values(c, s.kappa, gr, gi, M, Nt, h, Pin, kin);
-    // outgoing: target proxy node j on radii R_p, 1.25 R_p, source contour node i
-    const int64_t Pout = (int64_t)n_o * NG;
+    const int64_t Pout = (int64_t)2 * n_out * NG;
     std::vector<double> g(7 * Pout);
     for (int rr = 0; rr < 2; ++rr) {
-        proxy_rings(rr == 0 ? R_p : 1.25 * R_p, NG, pr, pz, pnr, pnz, pw);
-        for (int j = 0; j < NG; ++j)
+        proxy_rings(rr == 0 ? R_p : 1.25 * R_p, n_out, pr, pz, pnr, pnz, pw);
+        for (int j = 0; j < n_out; ++j)
             for (int i = 0; i < NG; ++i) {
-                const int64_t q = ((int64_t)(rr * NG + j)) * NG + i;
+                const int64_t q = ((int64_t)(rr * n_out + j)) * NG + i;
                 g[q] = pr[j];
                 g[Pout + q] = s.r[i];
                 g[2 * Pout + q] = s.r[i] - pr[j];
@@ -369,11 +377,19 @@ static void ring_id(Ctx &c, const Shape &s, double R_p, double eps, std::vector<
                 g[6 * Pout + q] = aw[i] * pw[j];
             }
     }
-    double2 *kout = (double2 *)c.dalloc((size_t)Pout * (M + 1) * sizeof(double2));
+    kout = (double2 *)c.dalloc((size_t)Pout * (M + 1) * sizeof(double2));
     modal_values(c, s.kappa, gr, gi, M, Nt, g, Pout, kout);
+    s_in = 1.0 / std::sqrt(sumsq(c, kin, Pin * (M + 1)));
+    s_out = 1.0 / std::sqrt(sumsq(c, kout, Pout * (M + 1)));
+}
+
+// row ID of one shape: skeleton rings (ascending) and X (device, NG x k)
+static void ring_id(Ctx &c, const Shape &s, double R_p, double eps, std::vector<int> &rings, double2 *&X) {
+    const int NG = s.NG, M = s.M, n_in = NG, n_o = 2 * NG;
+    double2 *kin = nullptr, *kout = nullptr;
+    double s_in = 0, s_out = 0;
+    proxy_fields(c, s, R_p, NG, NG, kin, kout, s_in, s_out);
     // H with each block scaled to unit Frobenius norm
-    const double s_in = 1.0 / std::sqrt(sumsq(c, kin, Pin * (M + 1)));
-    const double s_out = 1.0 / std::sqrt(sumsq(c, kout, Pout * (M + 1)));
     const int64_t C = (int64_t)(M + 1) * (n_in + n_o);
     double2 *H = (double2 *)c.dalloc((size_t)NG * C * sizeof(double2));
     hipLaunchKernelGGL(build_h_kernel, dim3(ceil_div((int64_t)NG * C, 256)), dim3(256), 0, c.stream, kin, kout, NG,
@@ -573,15 +589,29 @@ void skeletonize(Ctx &c, double eps, double factor) {
     AXS_HIP(hipMemcpy(sk->desc, desc.data(), desc.size() * sizeof(SkelBody), hipMemcpyHostToDevice));
     sk->Ns = ch.N;
     sk->eps = eps;
-    if (c.skel) {
-        if (c.skel->X) c.dfree(c.skel->X);
-        if (c.skel->desc) c.dfree(c.skel->desc);
-    }
+    release_skeleton(c);
     c.skel = std::move(sk);
 }
 
+void release_skeleton(Ctx &c) {
+    if (!c.skel) return;
+    AXS_HIP(hipStreamSynchronize(c.stream));
+    if (c.skel->X) c.dfree(c.skel->X);
+    if (c.skel->desc) c.dfree(c.skel->desc);
+    if (c.skel->pts) {
+        for (auto *p : c.skel->pts->XT) c.dfree(p);
+        for (auto *p : c.skel->pts->S64) c.dfree(p);
+        for (auto *p : c.skel->pts->S32) c.dfree(p);
+    }
+    c.skel.reset();
+}
+
+static void point_restrict(Ctx &c, const void *y, void *out, int nrhs, double alpha);
+static void point_prolong(Ctx &c, const void *w, const void *add, void *out, int nrhs);
+
 // restrict / prolong between the full and the skeleton vectors
 void skel_restrict(Ctx &c, const void *y, void *out, int nrhs, double alpha) {
+    if (c.skel->kind == 1) return point_restrict(c, y, out, nrhs, alpha);
     const Skeleton &sk = *c.skel;
     const int64_t tot = sk.Ns * nrhs;
     hipLaunchKernelGGL(restrict_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, sk.desc,
@@ -590,12 +620,604 @@ void skel_restrict(Ctx &c, const void *y, void *out, int nrhs, double alpha) {
 }
 
 void skel_prolong(Ctx &c, const void *w, const void *add, void *out, int nrhs) {
+    if (c.skel->kind == 1) return point_prolong(c, w, add, out, nrhs);
     const Skeleton &sk = *c.skel;
     const int64_t tot = c.N * nrhs;
     hipLaunchKernelGGL(prolong_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, sk.desc,
                        (int)c.bodies.size(), sk.X, (const double2 *)w, (const double2 *)add, c.N, sk.Ns, nrhs,
                        (double2 *)out);
     AXS_HIP(hipGetLastError());
+}
+
+// ===========================================================================
+// Point skeletons (Sec. 5 with single-node index sets I_p)
+// ===========================================================================
+// The row ID runs over the N_G N_F nodes (i, l) of a shape against the proxy
+// matrix  H[(i, l), (m, c)] = Hm[i, c] e^{i m theta_l},  m = -M..M,
+// Hm = [IN_|m| | OUT_|m|^T] (the proxy fields above with n_proxy polar points
+// per sphere): a proxy ring with the azimuthal profile e^{i m phi} makes the
+// field IN_|m|[i, c] e^{i m theta_l} at node (i, l), and a node's field along an
+// outgoing proxy ring has the coefficient OUT_|m|[c, i] e^{-i m theta_l}.  By
+// the remark of Sec. 5 on randomized sampling the ID is taken of a sketch:
+//     A = Psi H^*  (ell x n),  Psi complex Gaussian (ell x (2M+1) C'),
+// so A[s, (i, l)] = sum_m e^{-i m theta_l} W_m[s, i],  W_m = Psi_m conj(H_|m|)^T:
+// 2M+1 GEMMs of ell x C' x NG and one DFT GEMM per contour node.  The columns
+// of A (= nodes) are chosen by Householder QR with randomized column pivoting
+// (blocks of 64 pivots chosen by pivoted Gram-Schmidt on a 80-row Gaussian
+// sketch of the trailing matrix, then one panel QR and one block update of
+// the trailing matrix: Martinsson, Quintana-Orti, Heavner and van de Geijn's
+// HQRRP), which keeps the pivot quality of column-pivoted QR with the dense
+// work in GEMMs; the rank k is the first pivot with |R_kk| < eps |R_00|, and
+// X(J, :) = (R_11^{-1} R_12)^* as in the ring version.  The sketch width ell
+// doubles from 256 until k <= ell - 16.  Then
+//   S_p = X^T A_pp^{-1} X  (k x k, dense) from per-mode products with S_m,
+//   B~ the point-order inter-body sum over the skeleton nodes,
+// and the compressed system runs in a child context whose operator is
+// s~ + S B~ s~ (S_p applied by one batched GEMM per run of bodies of a shape).
+#define AXS_BLAS(call)                                                                                      \
+    do {                                                                                                    \
+        rocblas_status st_ = (call);                                                                        \
+        if (st_ != rocblas_status_success)                                                                  \
+            throw ::axs::Error{AXS_EHIP, std::string(#call) + ": " + rocblas_status_to_string(st_)};        \
+    } while (0)
+
+static rocblas_handle blas_of(Ctx &c) {
+    if (!c.blas) {
+        rocblas_handle h = nullptr;
+        AXS_BLAS(rocblas_create_handle(&h));
+        c.blas = h;
+    }
+    rocblas_handle h = (rocblas_handle)c.blas;
+    AXS_BLAS(rocblas_set_stream(h, c.stream));
+    return h;
+}
+
+void destroy_blas(Ctx &c) {
+    if (c.blas) (void)rocblas_destroy_handle((rocblas_handle)c.blas);
+    c.blas = nullptr;
+}
+
+static inline rocblas_double_complex *zc(double2 *p) { return (rocblas_double_complex *)p; }
+static inline const rocblas_double_complex *zc(const double2 *p) { return (const rocblas_double_complex *)p; }
+static inline rocblas_float_complex *cc(float2 *p) { return (rocblas_float_complex *)p; }
+static inline const rocblas_float_complex *cc(const float2 *p) { return (const rocblas_float_complex *)p; }
+
+// the counter-based generator of the sketch: SplitMix64 (Steele, Lea and
+// Flood) of seed * 0x632BE59BD9B4E019 + counter, top 53 bits centred in their
+// interval; complex Gaussian by Box-Muller, sqrt(-2 ln u1) e^{2 pi i u2}
+__device__ __forceinline__ uint64_t sk_splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+}
+__device__ __forceinline__ double sk_uniform01(uint64_t seed, uint64_t k) {
+    return ((double)(sk_splitmix64(seed * 0x632BE59BD9B4E019ULL + k) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+__device__ __forceinline__ double2 sk_gauss(uint64_t seed, uint64_t e) {
+    const double u1 = sk_uniform01(seed, 2 * e), u2 = sk_uniform01(seed, 2 * e + 1);
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    return make_double2(rad * cs, rad * sn);
+}
+
+// G (rows x cols, column-major): G[r + q rows] = conj(gauss(seed, q_total_rows... )):
+// entry (r, q) from draw e = r * stride_r + q * stride_q, conjugated if conj
+__global__ void gauss_fill_kernel(double2 *__restrict__ G, int rows, int64_t cols, uint64_t seed, int64_t stride_r,
+                                  int64_t stride_q, int conj) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * cols) return;
+    const int r = (int)(t % rows);
+    const int64_t q = t / rows;
+    double2 v = sk_gauss(seed, (uint64_t)(r * stride_r + q * stride_q));
+    if (conj) v.y = -v.y;
+    G[t] = v;
+}
+
+__global__ void conj_kernel(double2 *__restrict__ a, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t].y = -a[t].y;
+}
+
+__global__ void ones_kernel(int *__restrict__ a, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t] = 1;
+}
+
+// diagonal entries A[j0 + t, j0 + t], t < b (column-major, leading dimension ld)
+__global__ void diag_kernel(const double2 *__restrict__ A, int64_t ld, int j0, int b, double2 *__restrict__ d) {
+    const int t = threadIdx.x;
+    if (t < b) d[t] = A[(int64_t)(j0 + t) + (int64_t)(j0 + t) * ld];
+}
+
+// column moves of A (rows x cols, leading dimension ld): phase 0 copies the
+// source columns to tmp, phase 1 tmp to the destination columns
+__global__ void move_cols_kernel(double2 *__restrict__ A, int64_t ld, int rows, const int2 *__restrict__ mv,
+                                 int cnt, double2 *__restrict__ tmp, int phase) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * cnt) return;
+    const int r = (int)(t % rows), j = (int)(t / rows);
+    if (phase == 0)
+        tmp[t] = A[(int64_t)mv[j].y * ld + r];
+    else
+        A[(int64_t)mv[j].x * ld + r] = tmp[t];
+}
+
+// X^T (k x n, column-major, rows in ascending skeleton order colof[t]):
+// column perm[q] = e_colof[q] for q < k, conj(T[:, q]) for q >= k, where T =
+// R_11^{-1} R_12 sits in A[0:k, k:n] (leading dimension ld)
+__global__ void assemble_xt_kernel(const double2 *__restrict__ A, int64_t ld, const int *__restrict__ perm,
+                                   const int *__restrict__ colof, int k, int64_t n, double2 *__restrict__ XT) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)k * n) return;
+    const int a = (int)(t % k);
+    const int64_t q = t / k;
+    const int64_t node = perm[q];
+    double2 v;
+    if (q < k) {
+        v = make_double2(a == (int)q ? 1.0 : 0.0, 0.0);
+    } else {
+        const double2 tv = A[(int64_t)a + q * ld];
+        v = make_double2(tv.x, -tv.y);
+    }
+    XT[(int64_t)colof[a] + node * k] = v;
+}
+
+__global__ void to_c64_kernel(const double2 *__restrict__ a, int64_t n, float2 *__restrict__ b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) b[t] = make_float2((float)a[t].x, (float)a[t].y);
+}
+
+__global__ void add_c64_kernel(double2 *__restrict__ y, const float2 *__restrict__ a, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        y[t].x += (double)a[t].x;
+        y[t].y += (double)a[t].y;
+    }
+}
+
+// node arrays of the skeleton: rows of the parent's [7][N] FP64 arrays
+__global__ void gather_geo_kernel(const double *__restrict__ g, int64_t N, const int64_t *__restrict__ idx,
+                                  int64_t Ns, double *__restrict__ g64, float *__restrict__ g32) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 7 * Ns) return;
+    const int a = (int)(t / Ns);
+    const int64_t j = t % Ns;
+    const double v = g[a * N + idx[j]];
+    g64[t] = v;
+    if (a < 6) g32[t] = (float)v;
+}
+
+// e^{sign i (m' - M) 2 pi l / NF} * scale as a column-major matrix: rows m'
+// (2M+1) x cols l (NF) if mode_rows, else rows l x cols m'
+static std::vector<double2> dft_matrix(int M, int NF, double sign, double scale, bool mode_rows) {
+    const int nm = 2 * M + 1;
+    std::vector<double2> E((size_t)nm * NF);
+    for (int mp = 0; mp < nm; ++mp)
+        for (int l = 0; l < NF; ++l) {
+            // the angle reduced to (-pi, pi] before the sine and cosine
+            const int64_t r = ((int64_t)(mp - M) * l) % NF;
+            const double a = sign * 2.0 * M_PI * (double)r / NF;
+            const double2 v = make_double2(scale * std::cos(a), scale * std::sin(a));
+            if (mode_rows)
+                E[(size_t)mp + (size_t)l * nm] = v;
+            else
+                E[(size_t)l + (size_t)mp * NF] = v;
+        }
+    return E;
+}
+
+static double2 *upload(Ctx &c, const std::vector<double2> &h) {
+    double2 *d = (double2 *)c.dalloc(h.size() * sizeof(double2));
+    AXS_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice));
+    return d;
+}
+
+// Householder QR with randomized column pivoting of A (ell x n, leading
+// dimension ell) until |R_kk| < eps |R_00|; returns k and the column order perm
+// (perm[q] = original column at position q).  Rows 0..k-1 of A then hold R_11
+// and R_12 of the pivoted factorization.
+static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, int ell, int64_t n, double eps, uint64_t seed,
+                 std::vector<int> &perm) {
+    constexpr int BMAX = 64, P = 16;
+    const int kmax = (int)std::min<int64_t>(ell, n);
+    perm.resize(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    double2 *tau = (double2 *)c.dalloc(BMAX * sizeof(double2));
+    double2 *Om = (double2 *)c.dalloc((size_t)(BMAX + P) * ell * sizeof(double2));
+    double2 *G = (double2 *)c.dalloc((size_t)(BMAX + P) * n * sizeof(double2));
+    int *active = (int *)c.dalloc(n * sizeof(int));
+    double *nrm = (double *)c.dalloc(n * sizeof(double));
+    double2 *coef = (double2 *)c.dalloc(n * sizeof(double2));
+    double2 *rdummy = (double2 *)c.dalloc(n * sizeof(double2));
+    double2 *tmp = (double2 *)c.dalloc((size_t)ell * 2 * BMAX * sizeof(double2));
+    int2 *mv = (int2 *)c.dalloc(2 * BMAX * sizeof(int2));
+    double2 *dg = (double2 *)c.dalloc(BMAX * sizeof(double2));
+    const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+    std::vector<double> hn(n);
+    std::vector<double2> hd(BMAX);
+    double d0 = 0.0;
+    int k = -1, blk = 0;
+    for (int j0 = 0; j0 < kmax && k < 0; ++blk) {
+        const int b = std::min(BMAX, kmax - j0), rows = b + P;
+        const int lrem = ell - j0;
+        const int64_t nrem = n - j0;
+        double2 *Arem = A + j0 + (int64_t)j0 * ell;
+        // Gaussian sketch of the trailing matrix: G = Om A[j0:ell, j0:n]
+        hipLaunchKernelGGL(gauss_fill_kernel, dim3(ceil_div((int64_t)rows * lrem, 256)), dim3(256), 0, c.stream,
+                           Om, rows, (int64_t)lrem, seed + 0x5851F42D4C957F2DULL * (uint64_t)(blk + 1), (int64_t)1,
+                           (int64_t)rows, 0);
+        AXS_HIP(hipGetLastError());
+        AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, rows, (rocblas_int)nrem, lrem, &one,
+                               zc(Om), rows, zc(Arem), ell, &zero, zc(G), rows));
+        // b pivots by pivoted Gram-Schmidt over the columns of G (rows of G^T)
+        hipLaunchKernelGGL(ones_kernel, dim3(ceil_div(nrem, 256)), dim3(256), 0, c.stream, active, nrem);
+        std::vector<int> loc;
+        std::vector<char> used(nrem, 0);
+        for (int t = 0; t < b; ++t) {
+            hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)nrem), dim3(256), 0, c.stream, G, (int64_t)rows,
+                               active, nrm);
+            AXS_HIP(hipGetLastError());
+            AXS_HIP(hipMemcpyAsync(hn.data(), nrm, nrem * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            AXS_HIP(hipStreamSynchronize(c.stream));
+            int pv = -1;
+            for (int64_t i = 0; i < nrem; ++i)
+                if (!used[i] && (pv < 0 || hn[i] > hn[pv])) pv = (int)i;
+            AXS_REQUIRE(pv >= 0 && std::isfinite(hn[pv]), AXS_ENONFINITE, "non-finite proxy sketch");
+            const double nu = std::sqrt(std::max(hn[pv], 0.0));
+            loc.push_back(pv);
+            used[pv] = 1;
+            hipLaunchKernelGGL(set_entry_kernel, dim3(1), dim3(1), 0, c.stream, rdummy, (int64_t)pv, 0.0, active, pv);
+            if (!(nu > 0.0)) continue;   // the sketch of the rest is zero: the order no longer matters
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(row_dots_kernel, dim3((unsigned)nrem), dim3(256), 0, c.stream, G, (int64_t)rows,
+                                   pv, active, nu, coef, rdummy);
+                hipLaunchKernelGGL(row_update_kernel, dim3(ceil_div(nrem * rows, 256)), dim3(256), 0, c.stream, G,
+                                   (int64_t)rows, (int)nrem, pv, active, coef, 1.0 / (nu * nu));
+                AXS_HIP(hipGetLastError());
+            }
+        }
+        // move the chosen columns to positions j0 .. j0 + b - 1 (all ell rows)
+        std::vector<int> dst_of(b, -1);
+        std::vector<int2> moves;
+        std::vector<char> taken(b, 0);
+        for (int t = 0; t < b; ++t)
+            if (loc[t] < b) taken[loc[t]] = 1;
+        std::vector<int> free_src;   // positions < b whose column is not chosen
+        for (int t = 0; t < b; ++t)
+            if (!taken[t]) free_src.push_back(t);
+        size_t fs = 0;
+        for (int t = 0; t < b; ++t) {
+            if (loc[t] == t) continue;
+            moves.push_back(make_int2(j0 + t, j0 + loc[t]));
+            if (loc[t] >= b) moves.push_back(make_int2(j0 + loc[t], j0 + free_src[fs++]));
+        }
+        if (!moves.empty()) {
+            std::vector<int> np(perm);
+            for (const int2 &m2 : moves) np[m2.x] = perm[m2.y];
+            perm.swap(np);
+            AXS_HIP(hipMemcpyAsync(mv, moves.data(), moves.size() * sizeof(int2), hipMemcpyHostToDevice, c.stream));
+            const int cnt = (int)moves.size();
+            for (int ph = 0; ph < 2; ++ph)
+                hipLaunchKernelGGL(move_cols_kernel, dim3(ceil_div((int64_t)ell * cnt, 256)), dim3(256), 0, c.stream,
+                                   A, (int64_t)ell, ell, mv, cnt, tmp, ph);
+            AXS_HIP(hipGetLastError());
+            AXS_HIP(hipStreamSynchronize(c.stream));   // moves is pageable host memory
+        }
+        // panel QR and block update of the trailing matrix
+        AXS_BLAS(rocsolver_zgeqrf(h, lrem, b, zc(Arem), ell, zc(tau)));
+        if (nrem > b)
+            AXS_BLAS(rocsolver_zunmqr(h, rocblas_side_left, rocblas_operation_conjugate_transpose, lrem,
+                                      (rocblas_int)(nrem - b), b, zc(Arem), ell, zc(tau),
+                                      zc(A + j0 + (int64_t)(j0 + b) * ell), ell));
+        hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(BMAX), 0, c.stream, A, (int64_t)ell, j0, b, dg);
+        AXS_HIP(hipMemcpyAsync(hd.data(), dg, b * sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        for (int t = 0; t < b; ++t) {
+            const double d = std::hypot(hd[t].x, hd[t].y);
+            AXS_REQUIRE(std::isfinite(d), AXS_ENONFINITE, "non-finite proxy sketch");
+            if (j0 + t == 0) d0 = d;
+            if (!(d > eps * d0)) {
+                k = j0 + t;
+                break;
+            }
+        }
+        j0 += b;
+    }
+    if (k < 0) k = kmax;
+    for (void *q : {(void *)tau, (void *)Om, (void *)G, (void *)active, (void *)nrm, (void *)coef, (void *)rdummy,
+                    (void *)tmp, (void *)mv, (void *)dg})
+        c.dfree(q);
+    return k;
+}
+
+// point ID of one shape: ascending skeleton nodes and X^T (device, k x n)
+static void point_id(Ctx &c, const Shape &s, double R_p, double eps, int npx, uint64_t seed,
+                     std::vector<int> &nodes, double2 *&XT, int &ell_used) {
+    rocblas_handle h = blas_of(c);
+    const int NG = s.NG, M = s.M, NF = s.NF, nm = 2 * M + 1;
+    const int64_t n = (int64_t)NG * NF;
+    double2 *kin = nullptr, *kout = nullptr;
+    double s_in = 0, s_out = 0;
+    proxy_fields(c, s, R_p, npx, npx, kin, kout, s_in, s_out);
+    const int Cp = 3 * npx;
+    const int64_t C = (int64_t)(M + 1) * Cp, Cpm = (int64_t)nm * Cp;
+    // conj(H_m) for m = 0..M, row-major NG x C (= column-major C x NG)
+    double2 *Bc = (double2 *)c.dalloc((size_t)NG * C * sizeof(double2));
+    hipLaunchKernelGGL(build_h_kernel, dim3(ceil_div((int64_t)NG * C, 256)), dim3(256), 0, c.stream, kin, kout, NG,
+                       npx, 2 * npx, M, s_in, s_out, Bc);
+    hipLaunchKernelGGL(conj_kernel, dim3(ceil_div((int64_t)NG * C, 256)), dim3(256), 0, c.stream, Bc,
+                       (int64_t)NG * C);
+    AXS_HIP(hipGetLastError());
+    c.dfree(kin);
+    c.dfree(kout);
+    double2 *Es = upload(c, dft_matrix(M, NF, -1.0, 1.0, true));    // (2M+1) x NF: e^{-i m theta_l}
+    const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+    const int64_t cap = std::min<int64_t>(n, Cpm);
+    int ell = (int)std::min<int64_t>(256, cap);
+    double2 *A = nullptr;
+    std::vector<int> perm;
+    int k = 0;
+    for (;;) {
+        // Psi = Omega^* (ell x Cpm): entry (s, r) = conj(gauss(seed, s Cpm + r))
+        double2 *Psi = (double2 *)c.dalloc((size_t)ell * Cpm * sizeof(double2));
+        hipLaunchKernelGGL(gauss_fill_kernel, dim3(ceil_div((int64_t)ell * Cpm, 256)), dim3(256), 0, c.stream, Psi,
+                           ell, Cpm, seed, Cpm, (int64_t)1, 1);
+        AXS_HIP(hipGetLastError());
+        // W_m = Psi_m conj(H_|m|)^T, stored as column (i (2M+1) + m + M) of W (ell x NG (2M+1))
+        double2 *W = (double2 *)c.dalloc((size_t)ell * NG * nm * sizeof(double2));
+        for (int m = -M; m <= M; ++m)
+            AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, ell, NG, Cp, &one,
+                                   zc(Psi + (int64_t)(m + M) * Cp * ell), ell, zc(Bc + (int64_t)std::abs(m) * Cp),
+                                   (rocblas_int)C, &zero, zc(W + (int64_t)(m + M) * ell), ell * nm));
+        c.dfree(Psi);
+        // A[:, i NF + l] = sum_m W[:, i (2M+1) + m + M] e^{-i m theta_l}
+        A = (double2 *)c.dalloc((size_t)ell * n * sizeof(double2));
+        AXS_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, ell, NF, nm, &one,
+                                               zc(W), ell, (rocblas_stride)ell * nm, zc(Es), nm, 0, &zero, zc(A), ell,
+                                               (rocblas_stride)ell * NF, NG));
+        c.dfree(W);
+        k = hqrrp(c, h, A, ell, n, eps, seed, perm);
+        if (k <= ell - 16 || ell == cap) break;
+        c.dfree(A);
+        ell = (int)std::min<int64_t>(2 * (int64_t)ell, cap);
+    }
+    c.dfree(Es);
+    c.dfree(Bc);
+    AXS_REQUIRE(k >= 1, AXS_EINVAL, "the proxy matrix of a shape is zero");
+    ell_used = ell;
+    // T = R_11^{-1} R_12 in place of R_12
+    if (n > k)
+        AXS_BLAS(rocblas_ztrsm(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
+                               rocblas_diagonal_non_unit, k, (rocblas_int)(n - k), &one, zc(A), ell,
+                               zc(A + (int64_t)k * ell), ell));
+    nodes.assign(perm.begin(), perm.begin() + k);
+    std::sort(nodes.begin(), nodes.end());
+    std::vector<int> colof(k);
+    for (int t = 0; t < k; ++t)
+        colof[t] = (int)(std::lower_bound(nodes.begin(), nodes.end(), perm[t]) - nodes.begin());
+    int *d_perm = (int *)c.dalloc((n + k) * sizeof(int));
+    AXS_HIP(hipMemcpy(d_perm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    AXS_HIP(hipMemcpy(d_perm + n, colof.data(), k * sizeof(int), hipMemcpyHostToDevice));
+    XT = (double2 *)c.dalloc((size_t)k * n * sizeof(double2));
+    hipLaunchKernelGGL(assemble_xt_kernel, dim3(ceil_div((int64_t)k * n, 256)), dim3(256), 0, c.stream, A,
+                       (int64_t)ell, d_perm, d_perm + n, k, n, XT);
+    AXS_HIP(hipGetLastError());
+    AXS_HIP(hipStreamSynchronize(c.stream));
+    c.dfree(d_perm);
+    c.dfree(A);
+}
+
+// S_p = X^T A_pp^{-1} X (k x k, column-major) for one shape: the columns of X
+// through the per-mode inverses (forward DFT over the azimuth, S_|m|, inverse
+// DFT), all as GEMMs on X^T
+static void point_sp(Ctx &c, const Shape &s, int k, const double2 *XT, double2 *&S64, float2 *&S32) {
+    rocblas_handle h = blas_of(c);
+    const int NG = s.NG, M = s.M, NF = s.NF, nm = 2 * M + 1;
+    const int64_t n = (int64_t)NG * NF;
+    const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+    double2 *Ef = upload(c, dft_matrix(M, NF, -1.0, 1.0, false));          // NF x (2M+1)
+    double2 *Ei = upload(c, dft_matrix(M, NF, 1.0, 1.0 / NF, true));       // (2M+1) x NF
+    double2 *Xh = (double2 *)c.dalloc((size_t)k * NG * nm * sizeof(double2));
+    AXS_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, k, nm, NF, &one, zc(XT),
+                                           k, (rocblas_stride)k * NF, zc(Ef), NF, 0, &zero, zc(Xh), k,
+                                           (rocblas_stride)k * nm, NG));
+    double2 *Yh = (double2 *)c.dalloc((size_t)k * NG * nm * sizeof(double2));
+    // S_|m| is stored row-major, i.e. column-major S_|m|^T: Yh_m = Xh_m S_|m|^T
+    for (int m = -M; m <= M; ++m)
+        AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, k, NG, NG, &one,
+                               zc(Xh + (int64_t)(m + M) * k), k * nm, zc((const double2 *)s.S64 + (int64_t)std::abs(m) * NG * NG),
+                               NG, &zero, zc(Yh + (int64_t)(m + M) * k), k * nm));
+    c.dfree(Xh);
+    double2 *YT = (double2 *)c.dalloc((size_t)k * n * sizeof(double2));
+    AXS_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, k, NF, nm, &one, zc(Yh),
+                                           k, (rocblas_stride)k * nm, zc(Ei), nm, 0, &zero, zc(YT), k,
+                                           (rocblas_stride)k * NF, NG));
+    c.dfree(Yh);
+    S64 = (double2 *)c.dalloc((size_t)k * k * sizeof(double2));
+    AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_transpose, k, k, (rocblas_int)n, &one, zc(XT),
+                           k, zc(YT), k, &zero, zc(S64), k));
+    S32 = (float2 *)c.dalloc((size_t)k * k * sizeof(float2));
+    hipLaunchKernelGGL(to_c64_kernel, dim3(ceil_div((int64_t)k * k, 256)), dim3(256), 0, c.stream, S64,
+                       (int64_t)k * k, S32);
+    AXS_HIP(hipGetLastError());
+    AXS_HIP(hipStreamSynchronize(c.stream));
+    c.dfree(YT);
+    c.dfree(Ef);
+    c.dfree(Ei);
+}
+
+void skeletonize_points(Ctx &c, double eps, double factor, int n_proxy, uint64_t seed) {
+    AXS_REQUIRE(c.precomputed, AXS_ESTATE, "call axs_precompute_scattering first");
+    AXS_REQUIRE(eps > 0 && eps < 1 && factor > 1, AXS_EINVAL, "need 0 < eps < 1 and proxy factor > 1");
+    AXS_REQUIRE(n_proxy >= 0 && n_proxy <= 4096, AXS_EINVAL, "n_proxy must be in [0, 4096]");
+    const size_t nsh = c.shapes.size(), nb = c.bodies.size();
+    AXS_REQUIRE(nb >= 2, AXS_EINVAL, "skeletonization needs at least two bodies");
+    std::vector<double> Rp(nsh, 1e300), rb(nsh, 0.0);
+    for (size_t b = 0; b < nb; ++b) {
+        const Body &B = c.bodies[b];
+        double gap = 1e300;
+        for (size_t q = 0; q < nb; ++q) {
+            if (q == b) continue;
+            const Body &Q = c.bodies[q];
+            const double d = std::sqrt((B.centre[0] - Q.centre[0]) * (B.centre[0] - Q.centre[0]) +
+                                       (B.centre[1] - Q.centre[1]) * (B.centre[1] - Q.centre[1]) +
+                                       (B.centre[2] - Q.centre[2]) * (B.centre[2] - Q.centre[2]));
+            gap = std::min(gap, d - Q.bound_radius);
+        }
+        Rp[B.shape] = std::min(Rp[B.shape], std::min(factor * B.bound_radius, gap));
+        rb[B.shape] = std::max(rb[B.shape], B.bound_radius);
+    }
+    for (size_t k = 0; k < nsh; ++k)
+        AXS_REQUIRE(Rp[k] >= 1.05 * rb[k], AXS_EINVAL,
+                    "point skeletons need a proxy sphere of 1.05 x the bounding radius around every body");
+    auto sk = std::make_unique<Skeleton>();
+    sk->kind = 1;
+    sk->pts = std::make_unique<PointSkel>();
+    PointSkel &P = *sk->pts;
+    P.k.resize(nsh);
+    P.n.resize(nsh);
+    P.ell.resize(nsh);
+    P.R_p = Rp;
+    P.nodes.resize(nsh);
+    P.XT.assign(nsh, nullptr);
+    P.S64.assign(nsh, nullptr);
+    P.S32.assign(nsh, nullptr);
+    try {
+        for (size_t k = 0; k < nsh; ++k) {
+            const Shape &s = c.shapes[k];
+            const int npx = n_proxy > 0 ? n_proxy : 40 + (int)std::ceil(1.25 * s.kappa * Rp[k]);
+            point_id(c, s, Rp[k], eps, npx, seed, P.nodes[k], P.XT[k], P.ell[k]);
+            P.k[k] = (int)P.nodes[k].size();
+            P.n[k] = s.NG * s.NF;
+            point_sp(c, s, P.k[k], P.XT[k], P.S64[k], P.S32[k]);
+            sk->rank.push_back(P.k[k]);
+        }
+    } catch (...) {
+        for (auto *p : P.XT) c.dfree(p);
+        for (auto *p : P.S64) c.dfree(p);
+        for (auto *p : P.S32) c.dfree(p);
+        throw;
+    }
+    // runs of consecutive bodies of one shape, skeleton offsets, node list
+    std::vector<int64_t> gidx;
+    int64_t off = 0;
+    for (size_t b = 0; b < nb; ++b) {
+        const Body &B = c.bodies[b];
+        const int sh = B.shape;
+        if (P.runs.empty() || P.runs.back().shape != sh ||
+            P.runs.back().o0 + (int64_t)P.runs.back().nb * P.n[sh] != B.offset) {
+            PointRun r{sh, (int)b, 0, P.k[sh], P.n[sh], B.offset, off};
+            P.runs.push_back(r);
+        }
+        P.runs.back().nb += 1;
+        for (int j : P.nodes[sh]) gidx.push_back(B.offset + j);
+        off += P.k[sh];
+    }
+    const int64_t Ns = off;
+    // the child context: the skeleton nodes of every body, point-order sum
+    sk->child = std::make_unique<Ctx>();
+    Ctx &ch = *sk->child;
+    ch.device = c.device;
+    ch.stream = c.stream;
+    ch.alloc = c.alloc;
+    ch.free_fn = c.free_fn;
+    ch.user = c.user;
+    ch.have_k = true;
+    ch.kappa = c.kappa;
+    ch.eta = c.eta;
+    ch.gam_re = c.gam_re;
+    ch.gam_im = c.gam_im;
+    ch.N = Ns;
+    off = 0;
+    for (size_t b = 0; b < nb; ++b) {
+        Body B = c.bodies[b];
+        B.offset = off;
+        B.n = P.k[B.shape];
+        off += B.n;
+        ch.bodies.push_back(B);
+    }
+    int64_t *d_idx = (int64_t *)ch.dalloc(Ns * sizeof(int64_t));
+    AXS_HIP(hipMemcpy(d_idx, gidx.data(), Ns * sizeof(int64_t), hipMemcpyHostToDevice));
+    ch.g64 = (double *)ch.dalloc(7 * Ns * sizeof(double));
+    ch.g32 = (float *)ch.dalloc(6 * Ns * sizeof(float));
+    hipLaunchKernelGGL(gather_geo_kernel, dim3(ceil_div(7 * Ns, 256)), dim3(256), 0, c.stream, c.g64, c.N, d_idx, Ns,
+                       ch.g64, ch.g32);
+    AXS_HIP(hipGetLastError());
+    AXS_HIP(hipStreamSynchronize(c.stream));
+    ch.dfree(d_idx);
+    ch.sctab = c.sctab;            // the parent's table (it outlives the child)
+    ch.ib_variant[0] = ch.ib_variant[1] = 1;
+    ch.pop = sk->pts.get();
+    ch.precomputed = true;
+    sk->Ns = Ns;
+    sk->eps = eps;
+    release_skeleton(c);
+    c.skel = std::move(sk);
+}
+
+// child of point skeletons: y = s + S (B~ s), B~ in `prec`, S_p in the same precision
+void point_operator(Ctx &c, const void *sigma, void *y, int nrhs, int prec) {
+    const PointSkel &P = *c.pop;
+    const int64_t Ns = c.N, tot = Ns * nrhs;
+    interbody_partials(c, sigma, nrhs, prec);
+    double2 *w = (double2 *)c.scratch(WS_XR, tot * sizeof(double2));
+    interbody_reduce_to_c128(c, w, nrhs, prec);
+    if (y != sigma) AXS_HIP(hipMemcpyAsync(y, sigma, tot * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
+    rocblas_handle h = blas_of(c);
+    double2 *yy = (double2 *)y;
+    if (prec == AXS_FP64) {
+        const rocblas_double_complex one = {1.0, 0.0};
+        for (const PointRun &r : P.runs)
+            AXS_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, r.k, r.nb, r.k,
+                                                   &one, zc(P.S64[r.shape]), r.k, 0, zc(w + r.s0), r.k,
+                                                   (rocblas_stride)Ns, &one, zc(yy + r.s0), r.k, (rocblas_stride)Ns,
+                                                   nrhs));
+    } else {
+        float2 *w32 = (float2 *)c.scratch(WS_XI, 2 * tot * sizeof(float2));
+        float2 *t32 = w32 + tot;
+        hipLaunchKernelGGL(to_c64_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, w, tot, w32);
+        AXS_HIP(hipGetLastError());
+        const rocblas_float_complex one = {1.0f, 0.0f}, zero = {0.0f, 0.0f};
+        for (const PointRun &r : P.runs)
+            AXS_BLAS(rocblas_cgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, r.k, r.nb, r.k,
+                                                   &one, cc(P.S32[r.shape]), r.k, 0, cc(w32 + r.s0), r.k,
+                                                   (rocblas_stride)Ns, &zero, cc(t32 + r.s0), r.k, (rocblas_stride)Ns,
+                                                   nrhs));
+        hipLaunchKernelGGL(add_c64_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, yy, t32, tot);
+        AXS_HIP(hipGetLastError());
+    }
+}
+
+// out = alpha X^T y per body (full [nrhs][N] -> skeleton [nrhs][Ns])
+static void point_restrict(Ctx &c, const void *y, void *out, int nrhs, double alpha) {
+    const PointSkel &P = *c.skel->pts;
+    const int64_t N = c.N, Ns = c.skel->Ns;
+    rocblas_handle h = blas_of(c);
+    const rocblas_double_complex a = {alpha, 0.0}, zero = {0.0, 0.0};
+    for (const PointRun &r : P.runs)
+        AXS_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, r.k, r.nb, r.n, &a,
+                                               zc(P.XT[r.shape]), r.k, 0, zc((const double2 *)y + r.o0), r.n,
+                                               (rocblas_stride)N, &zero, zc((double2 *)out + r.s0), r.k,
+                                               (rocblas_stride)Ns, nrhs));
+}
+
+// out = add + X w per body (skeleton -> full)
+static void point_prolong(Ctx &c, const void *w, const void *add, void *out, int nrhs) {
+    const PointSkel &P = *c.skel->pts;
+    const int64_t N = c.N, Ns = c.skel->Ns;
+    if (add)
+        AXS_HIP(hipMemcpyAsync(out, add, (size_t)N * nrhs * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
+    else
+        AXS_HIP(hipMemsetAsync(out, 0, (size_t)N * nrhs * sizeof(double2), c.stream));
+    rocblas_handle h = blas_of(c);
+    const rocblas_double_complex one = {1.0, 0.0};
+    for (const PointRun &r : P.runs)
+        AXS_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_transpose, rocblas_operation_none, r.n, r.nb, r.k,
+                                               &one, zc(P.XT[r.shape]), r.k, 0, zc((const double2 *)w + r.s0), r.k,
+                                               (rocblas_stride)Ns, &one, zc((double2 *)out + r.o0), r.n,
+                                               (rocblas_stride)N, nrhs));
 }
 
 }  // namespace axs

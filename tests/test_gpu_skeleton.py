@@ -72,8 +72,9 @@ def test_skeleton_solve_matches_full_and_reference(which, c1_system, small_syste
 
 
 def test_skeleton_without_room_for_a_proxy_is_the_full_system():
-    """Two unit spheres 0.3 apart: no proxy sphere clears the neighbour, so every
-    ring is kept and the skeleton solve returns the full solution."""
+    """Two unit spheres 0.3 apart: the largest proxy sphere that clears the
+    neighbour (radius 1.3) lies so close to the body that the ID at 1e-8 keeps
+    every ring, and the skeleton solve returns the full solution."""
     from paper_1406_0236_amd import SOLVE_FP64
     from workloads import configs
     wl = configs.two_spheres()

@@ -1,0 +1,159 @@
+"""Point skeletons (Sec. 5 with single-node index sets, randomized sketch)
+through the C ABI against the FP64 reference (oracle/skeleton.py).
+
+Several skeletons are correct (the pivots of the randomized QR differ from
+those of the reference's QRCP where near-ties fall otherwise), so the tests
+compare what is unique and check that the rest is valid:
+  - the number of skeleton nodes within 10 % of the reference's QRCP rank;
+  - the skeleton nodes are distinct, ascending, and X(I, :) is the identity;
+  - X interpolates the reference's proxy matrix H to 10 eps (relative
+    Frobenius norm), and unseen incoming and outgoing fields to 1e-6;
+  - the compressed solve, lifted back, agrees with the full solution and with
+    the reference's own randomized point-skeleton solve to 1e-7 at eps = 1e-8
+    (the reference reaches 4e-9), with a certified full-system residual below
+    1e-7, in FP64 and in mixed precision, for one and for three plane waves.
+Workloads: two unit spheres (6 x 8 Gauss nodes, |m| <= 12, N = 2,400), a
+sphere and a rotated spheroid (N = 1,530), and three spheres in a row and a
+spheroid (runs of bodies of one shape)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _ctx(wl):
+    from paper_1406_0236_amd import Context
+    ctx = Context(0).add_workload(wl)
+    ctx.precompute_scattering()
+    return ctx
+
+
+def _exterior_points(rng, n, r0, r1):
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return d * rng.uniform(r0, r1, n)[:, None]
+
+
+def _two_small():
+    from oracle.multibody import System
+    from workloads import configs
+    wl = configs.two_spheres(n_panels=6, p=8, M=12)
+    return wl, System.from_workload(wl)
+
+
+def _row_of_spheres():
+    from oracle.multibody import System
+    from workloads import configs, geometry as geo
+    k = 2.0
+    s = geo.sphere(1.0, 4, 8)
+    pr = geo.prolate(0.7, 1.2, 4, 8)
+    rot = geo.random_rotation(np.random.default_rng(3))
+    bodies = [configs.BodySpec(s, np.array([3.0 * i, 0.0, 0.0]), np.eye(3), 8) for i in range(3)]
+    bodies.append(configs.BodySpec(pr, np.array([1.5, 3.2, 0.4]), rot, 8))
+    dirs = np.array([[0.0, 0.0, 1.0], [0.6, 0.0, 0.8], [0.0, -0.8, 0.6]])
+    wl = configs.Workload("row3_prolate", k, k, bodies, dirs)
+    return wl, System.from_workload(wl)
+
+
+def test_point_skeleton_of_two_spheres_is_a_valid_id():
+    from oracle.skeleton import default_n_proxy, point_id, point_matrix, proxy_radius
+    wl, S = _two_small()
+    print(f"[gpu] point skeleton {wl.name} N={wl.N}", flush=True)
+    ctx = _ctx(wl)
+    eps = 1e-8
+    ns = ctx.skeletonize_points(eps, 2.0, 0, 11)
+    body = S.bodies[0]
+    sh = body.shape
+    R_p, _ = proxy_radius(S, 0, 2.0)
+    npx = default_n_proxy(sh.kappa, R_p)
+    Iq, _ = point_id(sh, R_p, eps, npx)
+    k, n = ctx.skeleton_rank(0)
+    nodes = ctx.skeleton_nodes(0)
+    print(f"skeleton nodes {k} of {n} per body ({ns} in all); reference QRCP {Iq.size}", flush=True)
+    assert n == sh.NG * sh.NF and nodes.size == k and ns == 2 * k
+    assert abs(k - Iq.size) <= 0.1 * Iq.size
+    assert np.all(np.diff(nodes) > 0) and nodes[0] >= 0 and nodes[-1] < n
+    XT = ctx.skeleton_interp(0).cpu().numpy()                      # k x n
+    X = XT.T
+    assert np.array_equal(X[nodes], np.eye(k))
+    H = point_matrix(sh, R_p, npx)
+    e_h = np.linalg.norm(H - X @ H[nodes]) / np.linalg.norm(H)
+    # unseen fields
+    rng = np.random.default_rng(29)
+    loc = body.x - body.centre
+    src = _exterior_points(rng, 12, 1.1 * R_p, 2.0 * R_p)
+    d = loc[:, None, :] - src[None, :, :]
+    R = np.linalg.norm(d, axis=-1)
+    u = (np.exp(1j * S.kappa * R) / (4 * np.pi * R)) @ rng.standard_normal(12)
+    e_in = _rel(X @ u[nodes], u)
+    tg = _exterior_points(rng, 20, 1.1 * R_p, 3.0 * R_p)
+    sig = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    G = S.kernel(tg + body.centre, body.x, body.n) * S.w[:n][None, :]
+    e_out = _rel(G[:, nodes] @ (XT @ sig), G @ sig)
+    print(f"interpolation of H {e_h:.2e}, unseen incoming {e_in:.2e}, outgoing {e_out:.2e}", flush=True)
+    assert e_h < 10 * eps and e_in < 1e-6 and e_out < 1e-6
+    ctx.close()
+
+
+@pytest.mark.parametrize("which", ["two_spheres", "sphere_spheroid", "row3_prolate"])
+def test_point_skeleton_solve_matches_full_and_reference(which, small_system):
+    from oracle.multibody import gmres
+    from oracle.skeleton import PointSkeletonSystem
+    from paper_1406_0236_amd import SOLVE_FP64, SOLVE_MIXED
+    wl, S = {"two_spheres": _two_small, "sphere_spheroid": lambda: small_system,
+             "row3_prolate": _row_of_spheres}[which]()
+    print(f"[gpu] point skeleton solve {wl.name} N={wl.N}", flush=True)
+    ctx = _ctx(wl)
+    ns = ctx.skeletonize_points(1e-8, 2.0, 0, 5)
+    nd = len(wl.dirs)
+    V = S.plane_waves(wl.dirs)
+    xf = np.stack([gmres(S.matvec, S.rhs(V[:, c]), tol=1e-13)[0] for c in range(nd)])
+    K = PointSkeletonSystem(S, eps=1e-8, method="randomized", seed=5)
+    xr = np.stack([K.solve(V[:, c], tol=1e-13)[0] for c in range(nd)])
+    print(f"skeleton nodes {ns} (reference {K.Ns}) of {S.N}; reference vs full {_rel(xr, xf):.2e}", flush=True)
+    assert abs(ns - K.Ns) <= 0.1 * K.Ns and ns < S.N
+    vd = ctx.incident_plane_waves(wl.dirs)
+    for mode, tol in ((SOLVE_FP64, 1e-12), (SOLVE_MIXED, 1e-11)):
+        sol, info = ctx.solve_skeleton(vd, mode=mode, tol=tol, max_iters=100, certify=True)
+        x = sol.cpu().numpy()
+        e, er = _rel(x, xf), _rel(x, xr)
+        res = max(i["rel_residual"] for i in info)
+        print(f"mode {mode}: {info[0]['iterations']} iterations (inner {info[0]['inner_iterations']}), "
+              f"full-system residual {res:.2e}, vs full {e:.2e}, vs reference {er:.2e}", flush=True)
+        assert e < 1e-7 and er < 1e-7 and res < 1e-7
+    ctx.close()
+
+
+def test_point_skeleton_needs_room_for_a_proxy():
+    """A proxy factor of 1.04 leaves no proxy sphere of 1.05 x the bounding
+    radius: the point version refuses (the ring version keeps every ring
+    instead)."""
+    from paper_1406_0236_amd import AxsError
+    wl, _ = _two_small()
+    ctx = _ctx(wl)
+    with pytest.raises(AxsError, match="proxy sphere"):
+        ctx.skeletonize_points(1e-8, 1.04)
+    ctx.close()
+
+
+def test_ring_skeleton_nodes_are_whole_rings(small_system):
+    wl, S = small_system
+    ctx = _ctx(wl)
+    ctx.skeletonize(1e-8, 2.0)
+    for b, body in enumerate(S.bodies):
+        k, ng = ctx.skeleton_rank(b)
+        nodes = ctx.skeleton_nodes(b)
+        nf = body.shape.NF
+        assert nodes.size == k * nf
+        rings = nodes.reshape(k, nf)
+        assert np.array_equal(rings % nf, np.tile(np.arange(nf), (k, 1)))
+        assert np.all(np.diff(rings[:, 0]) > 0)
+    from paper_1406_0236_amd import AxsError
+    with pytest.raises(AxsError, match="point skeletons only"):
+        ctx.skeleton_interp(0)
+    ctx.close()
