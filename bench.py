@@ -13,7 +13,8 @@ Prints one JSON line.  The roofline object is for the dominant kernel, the
 FP32 inter-body sum: 39 flop per (target, source) pair on different bodies,
 timed with HIP events on the library's stream.  Beside the step the line
 carries
-  - `skeleton`: the same problem through the ring skeletonization of Sec. 5;
+  - `skeleton`: the same problem through the ring skeletonization of Sec. 5
+    (and, in `skeleton.points`, through point skeletons from the randomized ID);
   - `c5`: the largest workload (64 mixed bodies in a 24^3 box, kappa = 4 pi,
     N = 1,351,890, 16 plane waves): one mixed and one FP64 batched solve to
     1e-7, iterations and explicit FP64 residuals;
@@ -324,6 +325,9 @@ def main():
                 "mixed_s": t_sk, "outer": info_sk[0]["iterations"], "inner": info_sk[0]["inner_iterations"],
                 "full_rel_residual": res_sk}
         log(f"skeleton: {skel}")
+        # point skeletons (the randomized ID of single nodes); eps 1e-10 keeps the
+        # lifted density's full-system residual below the 1e-7 target
+        skel["points"] = point_skeleton_leg(ctx, v, args.tol, 1e-10, sol)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -954,7 +958,7 @@ def skeleton(args, eps=1e-8):
         log(f"{name}: {runs[name]}")
     ref, info_ref = ctx.solve(v, mode=SOLVE_MIXED, tol=args.tol)
     diff = float(torch.linalg.norm(sol - ref) / torch.linalg.norm(ref))
-    points = point_skeleton_leg(ctx, v, args.tol, eps, ref)
+    points = [point_skeleton_leg(ctx, v, args.tol, e, ref) for e in (1e-8, 1e-9, 1e-10)]
     out = {
         "metric": "s to 1e-7 residual of the compressed system (Sec. 5 skeletonization), 27 spheres",
         "value": runs["mixed"]["s"], "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": 1,

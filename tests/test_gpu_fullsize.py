@@ -169,6 +169,32 @@ def test_fullsize_skeleton_solve(lattice):
     assert d < 1e-6
 
 
+def test_fullsize_point_skeleton_solve(lattice):
+    """The benchmark problem through point skeletons (the randomized ID of single
+    nodes, eps = 1e-10): fewer than a fifth of the nodes stay, and the lifted
+    density of a mixed solve to 1e-7 has a full-system residual below 1e-7, by
+    the library's FP64 certificate on every row and by the reference's own
+    residual on the rows of body 13 (relative to the library's ||b||), and
+    agrees with the uncompressed mixed solution to 1e-6."""
+    from paper_1406_0236_amd import SOLVE_MIXED
+    wl, S, ctx = lattice
+    ns = ctx.skeletonize_points(1e-10, 2.0, 0, 1)
+    k, n = ctx.skeleton_rank(0)
+    print(f"point skeletons: {k} of {n} nodes per body, {ns} of {wl.N} unknowns", flush=True)
+    assert ns == 27 * k and k < 0.2 * n
+    v = ctx.incident_plane_waves(wl.dirs)
+    sol, info = ctx.solve_skeleton(v, mode=SOLVE_MIXED, tol=1e-7, certify=True)
+    ref, _ = ctx.solve(v, mode=SOLVE_MIXED, tol=1e-7)
+    d = float(torch.linalg.norm(sol - ref) / torch.linalg.norm(ref))
+    rn, _ = _certified_residual(S, wl, sol.cpu().numpy()[0], [13])
+    e = rn / float(torch.linalg.norm(ctx.apply_precond(v)))
+    print(f"point skeleton solve: {info[0]['iterations']} outer, {info[0]['inner_iterations']} inner, "
+          f"full residual {info[0]['rel_residual']:.2e}, body 13 by the reference {e:.2e}, "
+          f"vs uncompressed {d:.2e}", flush=True)
+    assert info[0]["rel_residual"] < 1e-7 and e < 1e-7
+    assert d < 1e-6
+
+
 def test_fullsize_reciprocity(lattice):
     """At the benchmark's full size (27 spheres, N = 437,400, kappa = 4 pi): two
     incident directions d1, d2 solved in one batched mixed solve to 1e-9;

@@ -14,7 +14,9 @@ compare what is unique and check that the rest is valid:
     1e-7, in FP64 and in mixed precision, for one and for three plane waves.
 Workloads: two unit spheres (6 x 8 Gauss nodes, |m| <= 12, N = 2,400), a
 sphere and a rotated spheroid (N = 1,530), and three spheres in a row and a
-spheroid (runs of bodies of one shape)."""
+spheroid (runs of bodies of one shape).  The counts of skeleton nodes are
+also set against the ones the paper prints for its ellipsoids and bowls
+(tests/golden/skeleton_counts_table.txt)."""
 import numpy as np
 import pytest
 
@@ -157,3 +159,52 @@ def test_ring_skeleton_nodes_are_whole_rings(small_system):
     with pytest.raises(AxsError, match="point skeletons only"):
         ctx.skeleton_interp(0)
     ctx.close()
+
+
+def _paper_counts():
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "skeleton_counts_table.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                ex, kern, shape, ng, nf, k = line.split()
+                rows.append((int(ex), kern, shape, int(ng), int(nf), int(k)))
+    return rows
+
+
+def test_point_skeleton_counts_bracket_the_papers():
+    """The paper's skeleton counts per body (Sec. 6.2, examples 5-7, n = 100 x
+    101; tests/golden/skeleton_counts_table.txt) against the point skeletons of
+    the same bodies (ellipsoid with axes 2 and 1, the bowl reading of the
+    figures; two bodies 6 apart, proxy radius 2 r_b): the paper does not print
+    its tolerance, and each of its counts lies between the counts here at
+    eps = 1e-6 and eps = 1e-10.  The ring skeletons keep at least three times
+    as many nodes at eps = 1e-8."""
+    import math
+    from workloads import configs, geometry as geo
+    shapes = {"ellipsoid": geo.prolate(0.5, 1.0, 10, 10), "bowl": geo.bowl(4, 2, 4, 10)}
+    kern = {"laplace": (0.0, 1.0), "helmholtz_2wl": (2 * math.pi, 2 * math.pi),
+            "helmholtz_5wl": (5 * math.pi, 5 * math.pi)}
+    for ex, kname, sname, ng, nf, kp in _paper_counts():
+        c = shapes[sname]
+        kappa, eta = kern[kname]
+        M = (nf - 1) // 2
+        bodies = [configs.BodySpec(c, np.array([0.0, 0.0, 0.0]), np.eye(3), M),
+                  configs.BodySpec(c, np.array([6.0, 0.0, 0.0]), np.eye(3), M)]
+        wl = configs.Workload(f"pair_{kname}_{sname}", kappa, eta, bodies, np.array([[0.0, 0.0, 1.0]]))
+        print(f"[gpu] example {ex}: {kname} {sname}", flush=True)
+        ctx = _ctx(wl)
+        try:
+            assert c.NG == ng and wl.N == 2 * ng * nf
+            k = {}
+            for eps in (1e-6, 1e-8, 1e-10):
+                ctx.skeletonize_points(eps, 2.0, 0, 1)
+                k[eps] = ctx.skeleton_rank(0)[0]
+            ctx.skeletonize(1e-8, 2.0)
+            rings = ctx.skeleton_rank(0)[0]
+            print(f"example {ex} {kname} {sname}: paper {kp}; here {k[1e-6]} / {k[1e-8]} / {k[1e-10]} "
+                  f"at eps 1e-6 / 1e-8 / 1e-10; rings {rings} x {nf} = {rings * nf} nodes at 1e-8", flush=True)
+            assert k[1e-6] <= kp <= k[1e-10]
+            assert rings * nf >= 3 * k[1e-8]
+        finally:
+            ctx.close()
