@@ -643,8 +643,8 @@ void skel_prolong(Ctx &c, const void *w, const void *add, void *out, int nrhs) {
 // so A[s, (i, l)] = sum_m e^{-i m theta_l} W_m[s, i],  W_m = Psi_m conj(H_|m|)^T:
 // 2M+1 GEMMs of ell x C' x NG and one DFT GEMM per contour node.  The columns
 // of A (= nodes) are chosen by Householder QR with randomized column pivoting
-// (blocks of 64 pivots chosen by pivoted Gram-Schmidt on a 80-row Gaussian
-// sketch of the trailing matrix, then one panel QR and one block update of
+// (blocks of 64 pivots chosen by pivoted Gram-Schmidt, on the device, on an
+// 80-row Gaussian sketch of the trailing matrix, then one panel QR and one block update of
 // the trailing matrix: Martinsson, Quintana-Orti, Heavner and van de Geijn's
 // HQRRP), which keeps the pivot quality of column-pivoted QR with the dense
 // work in GEMMs; the rank k is the first pivot with |R_kk| < eps |R_00|, and
@@ -718,11 +718,6 @@ __global__ void gauss_fill_kernel(double2 *__restrict__ G, int rows, int64_t col
 __global__ void conj_kernel(double2 *__restrict__ a, int64_t n) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) a[t].y = -a[t].y;
-}
-
-__global__ void ones_kernel(int *__restrict__ a, int64_t n) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) a[t] = 1;
 }
 
 // diagonal entries A[j0 + t, j0 + t], t < b (column-major, leading dimension ld)
@@ -814,6 +809,99 @@ static double2 *upload(Ctx &c, const std::vector<double2> &h) {
     return d;
 }
 
+// Column selection on a small sketch G (rows x n, column-major) by pivoted
+// Gram-Schmidt, one wavefront per column and the pivot chosen on the device:
+// no host round trip per pivot.  nrm[j] < 0 marks a column already chosen.
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void gcol_norms_kernel(const double2 *__restrict__ G, int rows, int64_t n, double *__restrict__ nrm) {
+    const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (col >= n) return;   // the same for the whole wavefront
+    const double2 *g = G + col * rows;
+    double a = 0.0;
+    for (int r = lane; r < rows; r += 64) a = fma(g[r].x, g[r].x, fma(g[r].y, g[r].y, a));
+    a = wave_sum64(a);
+    if (lane == 0) nrm[col] = a;
+}
+
+// the largest squared norm among the unchosen columns (ties to the smaller
+// index; NaN never wins): piv[t], nu2[t], and the column is marked chosen.
+// piv[t] = -1 if every remaining norm is NaN.
+__global__ void gcol_argmax_kernel(double *__restrict__ nrm, int64_t n, int *__restrict__ piv,
+                                   double *__restrict__ nu2, int t) {
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    double bv = -1.0;
+    int bi = -1;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const double v = nrm[i];
+        if (v > bv) {   // indices rise within a thread: the first maximum stays
+            bv = v;
+            bi = (int)i;
+        }
+    }
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double v2 = sv[threadIdx.x + o];
+            const int i2 = si[threadIdx.x + o];
+            const double v1 = sv[threadIdx.x];
+            const int i1 = si[threadIdx.x];
+            if (i2 >= 0 && (i1 < 0 || v2 > v1 || (v2 == v1 && i2 < i1))) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        piv[t] = si[0];
+        nu2[t] = sv[0];
+        if (si[0] >= 0) nrm[si[0]] = -1.0;
+    }
+}
+
+// one Gram-Schmidt step against the pivot column piv[t] (two projections),
+// then the new squared norms; chosen columns (nrm < 0) are left alone
+__global__ void gcol_step_kernel(double2 *__restrict__ G, int rows, int64_t n, const int *__restrict__ piv,
+                                 const double *__restrict__ nu2, int t, double *__restrict__ nrm) {
+    const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (col >= n) return;
+    const int p = piv[t];
+    const double s = nu2[t];
+    if (p < 0 || nrm[col] < 0.0) return;   // uniform across the wavefront
+    double2 *g = G + col * rows;
+    const double2 *u = G + (int64_t)p * rows;
+    if (s > 0.0) {
+        for (int pass = 0; pass < 2; ++pass) {
+            double dr = 0.0, di = 0.0;   // <g, u> = sum g conj(u)
+            for (int r = lane; r < rows; r += 64) {
+                dr = fma(g[r].x, u[r].x, fma(g[r].y, u[r].y, dr));
+                di = fma(g[r].y, u[r].x, fma(-g[r].x, u[r].y, di));
+            }
+            dr = wave_sum64(dr) / s;
+            di = wave_sum64(di) / s;
+            for (int r = lane; r < rows; r += 64) {
+                const double2 w = u[r];
+                g[r].x -= dr * w.x - di * w.y;
+                g[r].y -= dr * w.y + di * w.x;
+            }
+        }
+    }
+    double a = 0.0;
+    for (int r = lane; r < rows; r += 64) a = fma(g[r].x, g[r].x, fma(g[r].y, g[r].y, a));
+    a = wave_sum64(a);
+    if (lane == 0) nrm[col] = a;
+}
+
 // Householder QR with randomized column pivoting of A (ell x n, leading
 // dimension ell) until |R_kk| < eps |R_00|; returns k and the column order perm
 // (perm[q] = original column at position q).  Rows 0..k-1 of A then hold R_11
@@ -827,15 +915,13 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, int ell, int64_t n, doubl
     double2 *tau = (double2 *)c.dalloc(BMAX * sizeof(double2));
     double2 *Om = (double2 *)c.dalloc((size_t)(BMAX + P) * ell * sizeof(double2));
     double2 *G = (double2 *)c.dalloc((size_t)(BMAX + P) * n * sizeof(double2));
-    int *active = (int *)c.dalloc(n * sizeof(int));
     double *nrm = (double *)c.dalloc(n * sizeof(double));
-    double2 *coef = (double2 *)c.dalloc(n * sizeof(double2));
-    double2 *rdummy = (double2 *)c.dalloc(n * sizeof(double2));
+    int *dpiv = (int *)c.dalloc(BMAX * sizeof(int));
+    double *dnu2 = (double *)c.dalloc(BMAX * sizeof(double));
     double2 *tmp = (double2 *)c.dalloc((size_t)ell * 2 * BMAX * sizeof(double2));
     int2 *mv = (int2 *)c.dalloc(2 * BMAX * sizeof(int2));
     double2 *dg = (double2 *)c.dalloc(BMAX * sizeof(double2));
     const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
-    std::vector<double> hn(n);
     std::vector<double2> hd(BMAX);
     double d0 = 0.0;
     int k = -1, blk = 0;
@@ -851,31 +937,26 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, int ell, int64_t n, doubl
         AXS_HIP(hipGetLastError());
         AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, rows, (rocblas_int)nrem, lrem, &one,
                                zc(Om), rows, zc(Arem), ell, &zero, zc(G), rows));
-        // b pivots by pivoted Gram-Schmidt over the columns of G (rows of G^T)
-        hipLaunchKernelGGL(ones_kernel, dim3(ceil_div(nrem, 256)), dim3(256), 0, c.stream, active, nrem);
-        std::vector<int> loc;
-        std::vector<char> used(nrem, 0);
+        // b pivots by pivoted Gram-Schmidt over the columns of G, chosen on the device
+        const unsigned gblk = (unsigned)ceil_div(nrem, (int64_t)4);
+        hipLaunchKernelGGL(gcol_norms_kernel, dim3(gblk), dim3(256), 0, c.stream, G, rows, nrem, nrm);
+        hipLaunchKernelGGL(gcol_argmax_kernel, dim3(1), dim3(1024), 0, c.stream, nrm, nrem, dpiv, dnu2, 0);
         for (int t = 0; t < b; ++t) {
-            hipLaunchKernelGGL(row_norms_kernel, dim3((unsigned)nrem), dim3(256), 0, c.stream, G, (int64_t)rows,
-                               active, nrm);
-            AXS_HIP(hipGetLastError());
-            AXS_HIP(hipMemcpyAsync(hn.data(), nrm, nrem * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-            AXS_HIP(hipStreamSynchronize(c.stream));
-            int pv = -1;
-            for (int64_t i = 0; i < nrem; ++i)
-                if (!used[i] && (pv < 0 || hn[i] > hn[pv])) pv = (int)i;
-            AXS_REQUIRE(pv >= 0 && std::isfinite(hn[pv]), AXS_ENONFINITE, "non-finite proxy sketch");
-            const double nu = std::sqrt(std::max(hn[pv], 0.0));
-            loc.push_back(pv);
-            used[pv] = 1;
-            hipLaunchKernelGGL(set_entry_kernel, dim3(1), dim3(1), 0, c.stream, rdummy, (int64_t)pv, 0.0, active, pv);
-            if (!(nu > 0.0)) continue;   // the sketch of the rest is zero: the order no longer matters
-            for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL(row_dots_kernel, dim3((unsigned)nrem), dim3(256), 0, c.stream, G, (int64_t)rows,
-                                   pv, active, nu, coef, rdummy);
-                hipLaunchKernelGGL(row_update_kernel, dim3(ceil_div(nrem * rows, 256)), dim3(256), 0, c.stream, G,
-                                   (int64_t)rows, (int)nrem, pv, active, coef, 1.0 / (nu * nu));
-                AXS_HIP(hipGetLastError());
+            hipLaunchKernelGGL(gcol_step_kernel, dim3(gblk), dim3(256), 0, c.stream, G, rows, nrem, dpiv, dnu2, t,
+                               nrm);
+            if (t + 1 < b)
+                hipLaunchKernelGGL(gcol_argmax_kernel, dim3(1), dim3(1024), 0, c.stream, nrm, nrem, dpiv, dnu2,
+                                   t + 1);
+        }
+        AXS_HIP(hipGetLastError());
+        std::vector<int> loc(b);
+        AXS_HIP(hipMemcpyAsync(loc.data(), dpiv, b * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        {
+            std::vector<char> seen(nrem, 0);
+            for (int t = 0; t < b; ++t) {
+                AXS_REQUIRE(loc[t] >= 0 && loc[t] < nrem && !seen[loc[t]], AXS_ENONFINITE, "non-finite proxy sketch");
+                seen[loc[t]] = 1;
             }
         }
         // move the chosen columns to positions j0 .. j0 + b - 1 (all ell rows)
@@ -926,8 +1007,8 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, int ell, int64_t n, doubl
         j0 += b;
     }
     if (k < 0) k = kmax;
-    for (void *q : {(void *)tau, (void *)Om, (void *)G, (void *)active, (void *)nrm, (void *)coef, (void *)rdummy,
-                    (void *)tmp, (void *)mv, (void *)dg})
+    for (void *q : {(void *)tau, (void *)Om, (void *)G, (void *)nrm, (void *)dpiv, (void *)dnu2, (void *)tmp,
+                    (void *)mv, (void *)dg})
         c.dfree(q);
     return k;
 }
