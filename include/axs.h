@@ -307,8 +307,9 @@ axs_status axs_skeletonize(axs_ctx *ctx, double eps, double proxy_factor, int64_
  * n_proxy polar points per proxy sphere), taken of the Gaussian sketch
  * Psi H^* (Psi: ell x (2M+1) 3 n_proxy, complex Gaussian, entry (s, r) the
  * conjugate of draw s (2M+1) 3 n_proxy + r of the generator below).  Nodes are
- * chosen by Householder QR with randomized column pivoting of the sketch
- * (blocks of 64 pivots); the rank k is the first pivot with |R_kk| < eps
+ * chosen by QR with randomized column pivoting of the sketch (blocks of 64
+ * pivots, each block orthonormalised by CholeskyQR2 and projected out of the
+ * rest twice); the rank k is the first pivot with |R_kk| < eps
  * |R_00|; ell doubles from 256 until k <= ell - 16.  Then U_p = V_p = X
  * (N_G N_F x k), S_p = X^T A_pp^{-1} X is dense k x k (FP64 and FP32 copies),
  * B~ is the point-order inter-body sum over the skeleton nodes, and
@@ -320,8 +321,8 @@ axs_status axs_skeletonize(axs_ctx *ctx, double eps, double proxy_factor, int64_
  *                 0x632BE59BD9B4E019 + k) >> 11 + 0.5) 2^-53, complex Gaussian
  *                 draw e is sqrt(-2 ln u_2e) e^{2 pi i u_(2e+1)} (Box-Muller).
  *  out_nskel    : host int64, number of skeleton nodes (may be NULL).
- * FP64 on the device (rocBLAS / rocSOLVER for the dense factorizations and
- * products); replaces an earlier skeleton system of the context. */
+ * FP64 on the device (rocBLAS for the dense products); replaces an earlier
+ * skeleton system of the context. */
 axs_status axs_skeletonize_points(axs_ctx *ctx, double eps, double proxy_factor, int n_proxy, uint64_t seed,
                                   int64_t *out_nskel);
 

@@ -43,7 +43,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
     tmp = LIB + ".tmp"
     subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
-                           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas"])
+                           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas"])
     os.replace(tmp, LIB)
     return LIB
 

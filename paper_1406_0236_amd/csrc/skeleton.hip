@@ -25,7 +25,6 @@
 #include "axs_internal.h"
 
 #include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <cmath>
@@ -642,12 +641,12 @@ void skel_prolong(Ctx &c, const void *w, const void *add, void *out, int nrhs) {
 //     A = Psi H^*  (ell x n),  Psi complex Gaussian (ell x (2M+1) C'),
 // so A[s, (i, l)] = sum_m e^{-i m theta_l} W_m[s, i],  W_m = Psi_m conj(H_|m|)^T:
 // 2M+1 GEMMs of ell x C' x NG and one DFT GEMM per contour node.  The columns
-// of A (= nodes) are chosen by Householder QR with randomized column pivoting
-// (blocks of 64 pivots chosen by pivoted Gram-Schmidt, on the device, on an
-// 80-row Gaussian sketch of the trailing matrix, then one panel QR and one block update of
-// the trailing matrix: Martinsson, Quintana-Orti, Heavner and van de Geijn's
-// HQRRP), which keeps the pivot quality of column-pivoted QR with the dense
-// work in GEMMs; the rank k is the first pivot with |R_kk| < eps |R_00|, and
+// of A (= nodes) are chosen by QR with randomized column pivoting in blocks
+// of 64 (as in Martinsson, Quintana-Orti, Heavner and van de Geijn's HQRRP:
+// per block, pivoted Gram-Schmidt on the device on an 80-row Gaussian sketch
+// of the trailing columns), each block orthonormalised by CholeskyQR2 and the
+// trailing columns projected against it twice, so that the dense work is
+// GEMMs; the rank k is the first pivot with |R_kk| < eps |R_00|, and
 // X(J, :) = (R_11^{-1} R_12)^* as in the ring version.  The sketch width ell
 // doubles from 256 until k <= ell - 16.  Then
 //   S_p = X^T A_pp^{-1} X  (k x k, dense) from per-mode products with S_m,
@@ -902,41 +901,94 @@ __global__ void gcol_step_kernel(double2 *__restrict__ G, int rows, int64_t n, c
     if (lane == 0) nrm[col] = a;
 }
 
-// Householder QR with randomized column pivoting of A (ell x n, leading
-// dimension ell) until |R_kk| < eps |R_00|; returns k and the column order perm
-// (perm[q] = original column at position q).  Rows 0..k-1 of A then hold R_11
-// and R_12 of the pivoted factorization.
-static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, int ell, int64_t n, double eps, uint64_t seed,
+// Cholesky factor of a small Hermitian positive definite W (b x b, column-major,
+// b <= 64): W = R^H R with R upper triangular (lower part set to zero), one
+// workgroup, thread t owning column t.  info[0] = the first column whose pivot
+// is not positive (or not finite), b if none; R is valid in the columns before it.
+__global__ void chol_small_kernel(const double2 *__restrict__ W, int b, double2 *__restrict__ R, int *__restrict__ info) {
+    __shared__ int fail;
+    const int t = threadIdx.x;
+    if (t == 0) fail = b;
+    for (int i = t; i < b * b; i += blockDim.x) R[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int j = 0; j < b; ++j) {
+        if (t == j && fail == b) {
+            double d = W[j + j * b].x;
+            for (int i = 0; i < j; ++i) d -= R[i + j * b].x * R[i + j * b].x + R[i + j * b].y * R[i + j * b].y;
+            if (d > 0.0 && d < INFINITY) R[j + j * b] = make_double2(sqrt(d), 0.0);
+            else fail = j;
+        }
+        __syncthreads();
+        if (fail <= j) break;
+        if (t > j && t < b) {
+            // R[j][t] = (W[j][t] - sum_{i<j} conj(R[i][j]) R[i][t]) / R[j][j]
+            double2 a = W[j + t * b];
+            for (int i = 0; i < j; ++i) {
+                const double2 u = R[i + j * b], v = R[i + t * b];
+                a.x -= u.x * v.x + u.y * v.y;
+                a.y -= u.x * v.y - u.y * v.x;
+            }
+            const double r = R[j + j * b].x;
+            R[j + t * b] = make_double2(a.x / r, a.y / r);
+        }
+        __syncthreads();
+    }
+    if (t == 0) info[0] = fail;
+}
+
+// y += x elementwise (complex)
+__global__ void cadd_kernel(double2 *__restrict__ y, const double2 *__restrict__ x, int rows, int64_t cols,
+                            int64_t ldy, int64_t ldx) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * cols) return;
+    const int r = (int)(t % rows);
+    const int64_t q = t / rows;
+    y[r + q * ldy].x += x[r + q * ldx].x;
+    y[r + q * ldy].y += x[r + q * ldx].y;
+}
+
+// QR with randomized column pivoting of A (ell x n, leading dimension ell),
+// blocks of 64 pivots, until |R_kk| < eps |R_00|; returns k and the column
+// order perm (perm[q] = original column at position q).  Rm (ell x n, leading
+// dimension ell) then holds R_11 and R_12 in its rows 0..k-1.  Per block: a
+// Gaussian sketch of the trailing columns (80 rows, one GEMM) chooses the
+// pivots (device-side pivoted Gram-Schmidt on the sketch); the chosen panel
+// is orthonormalised by CholeskyQR2 (Gram matrix, Cholesky, triangular solve,
+// twice) and the trailing columns are projected against it twice (block
+// classical Gram-Schmidt with reorthogonalisation): every step a GEMM.
+static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int64_t n, double eps, uint64_t seed,
                  std::vector<int> &perm) {
     constexpr int BMAX = 64, P = 16;
     const int kmax = (int)std::min<int64_t>(ell, n);
     perm.resize(n);
     std::iota(perm.begin(), perm.end(), 0);
-    double2 *tau = (double2 *)c.dalloc(BMAX * sizeof(double2));
     double2 *Om = (double2 *)c.dalloc((size_t)(BMAX + P) * ell * sizeof(double2));
     double2 *G = (double2 *)c.dalloc((size_t)(BMAX + P) * n * sizeof(double2));
     double *nrm = (double *)c.dalloc(n * sizeof(double));
-    int *dpiv = (int *)c.dalloc(BMAX * sizeof(int));
+    int *dpiv = (int *)c.dalloc((BMAX + 2) * sizeof(int));
+    int *dinfo = dpiv + BMAX;
     double *dnu2 = (double *)c.dalloc(BMAX * sizeof(double));
     double2 *tmp = (double2 *)c.dalloc((size_t)ell * 2 * BMAX * sizeof(double2));
     int2 *mv = (int2 *)c.dalloc(2 * BMAX * sizeof(int2));
-    double2 *dg = (double2 *)c.dalloc(BMAX * sizeof(double2));
-    const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+    double2 *W = (double2 *)c.dalloc(4 * BMAX * BMAX * sizeof(double2));
+    double2 *R1 = W + BMAX * BMAX, *R2 = R1 + BMAX * BMAX, *Rp = R2 + BMAX * BMAX;
+    double2 *S = (double2 *)c.dalloc((size_t)BMAX * n * sizeof(double2));
+    const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0}, mone = {-1.0, 0.0};
     std::vector<double2> hd(BMAX);
     double d0 = 0.0;
     int k = -1, blk = 0;
     for (int j0 = 0; j0 < kmax && k < 0; ++blk) {
-        const int b = std::min(BMAX, kmax - j0), rows = b + P;
-        const int lrem = ell - j0;
+        int b = std::min(BMAX, kmax - j0);
+        const int rows = b + P;
         const int64_t nrem = n - j0;
-        double2 *Arem = A + j0 + (int64_t)j0 * ell;
-        // Gaussian sketch of the trailing matrix: G = Om A[j0:ell, j0:n]
-        hipLaunchKernelGGL(gauss_fill_kernel, dim3(ceil_div((int64_t)rows * lrem, 256)), dim3(256), 0, c.stream,
-                           Om, rows, (int64_t)lrem, seed + 0x5851F42D4C957F2DULL * (uint64_t)(blk + 1), (int64_t)1,
+        double2 *Atr = A + (int64_t)j0 * ell;
+        // Gaussian sketch of the trailing columns: G = Om A[:, j0:n]
+        hipLaunchKernelGGL(gauss_fill_kernel, dim3(ceil_div((int64_t)rows * ell, 256)), dim3(256), 0, c.stream,
+                           Om, rows, (int64_t)ell, seed + 0x5851F42D4C957F2DULL * (uint64_t)(blk + 1), (int64_t)1,
                            (int64_t)rows, 0);
         AXS_HIP(hipGetLastError());
-        AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, rows, (rocblas_int)nrem, lrem, &one,
-                               zc(Om), rows, zc(Arem), ell, &zero, zc(G), rows));
+        AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, rows, (rocblas_int)nrem, ell, &one,
+                               zc(Om), rows, zc(Atr), ell, &zero, zc(G), rows));
         // b pivots by pivoted Gram-Schmidt over the columns of G, chosen on the device
         const unsigned gblk = (unsigned)ceil_div(nrem, (int64_t)4);
         hipLaunchKernelGGL(gcol_norms_kernel, dim3(gblk), dim3(256), 0, c.stream, G, rows, nrem, nrm);
@@ -980,20 +1032,74 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, int ell, int64_t n, doubl
             perm.swap(np);
             AXS_HIP(hipMemcpyAsync(mv, moves.data(), moves.size() * sizeof(int2), hipMemcpyHostToDevice, c.stream));
             const int cnt = (int)moves.size();
-            for (int ph = 0; ph < 2; ++ph)
-                hipLaunchKernelGGL(move_cols_kernel, dim3(ceil_div((int64_t)ell * cnt, 256)), dim3(256), 0, c.stream,
-                                   A, (int64_t)ell, ell, mv, cnt, tmp, ph);
+            for (double2 *M : {A, Rm})
+                for (int ph = 0; ph < 2; ++ph)
+                    hipLaunchKernelGGL(move_cols_kernel, dim3(ceil_div((int64_t)ell * cnt, 256)), dim3(256), 0,
+                                       c.stream, M, (int64_t)ell, ell, mv, cnt, tmp, ph);
             AXS_HIP(hipGetLastError());
             AXS_HIP(hipStreamSynchronize(c.stream));   // moves is pageable host memory
         }
-        // panel QR and block update of the trailing matrix
-        AXS_BLAS(rocsolver_zgeqrf(h, lrem, b, zc(Arem), ell, zc(tau)));
-        if (nrem > b)
-            AXS_BLAS(rocsolver_zunmqr(h, rocblas_side_left, rocblas_operation_conjugate_transpose, lrem,
-                                      (rocblas_int)(nrem - b), b, zc(Arem), ell, zc(tau),
-                                      zc(A + j0 + (int64_t)(j0 + b) * ell), ell));
-        hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(BMAX), 0, c.stream, A, (int64_t)ell, j0, b, dg);
-        AXS_HIP(hipMemcpyAsync(hd.data(), dg, b * sizeof(double2), hipMemcpyDeviceToHost, c.stream));
+        // CholeskyQR2 of the panel Pn = A[:, j0:j0+b]: Pn = Q Rp, Q in place of Pn.
+        // A Cholesky that finds less rank than b columns shortens the panel to
+        // that rank (the rest stay in the trailing matrix) and starts again from
+        // a copy of the panel.
+        double2 *Pn = Atr;
+        AXS_HIP(hipMemcpy2DAsync(tmp, ell * sizeof(double2), Pn, ell * sizeof(double2), ell * sizeof(double2), b,
+                                 hipMemcpyDeviceToDevice, c.stream));
+        for (int pass = 0; pass < 2;) {
+            double2 *Rk = pass == 0 ? R1 : R2;
+            AXS_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, b, b, ell, &one,
+                                   zc(Pn), ell, zc(Pn), ell, &zero, zc(W), b));
+            hipLaunchKernelGGL(chol_small_kernel, dim3(1), dim3(64), 0, c.stream, W, b, Rk, dinfo);
+            AXS_HIP(hipGetLastError());
+            int info = 0;
+            AXS_HIP(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+            AXS_HIP(hipStreamSynchronize(c.stream));
+            if (info < b) {
+                if (info == 0) {   // no rank left in the trailing matrix
+                    AXS_REQUIRE(j0 > 0, AXS_ENONFINITE, "non-finite or zero proxy sketch");
+                    k = j0;
+                    break;
+                }
+                b = info;
+                AXS_HIP(hipMemcpy2DAsync(Pn, ell * sizeof(double2), tmp, ell * sizeof(double2),
+                                         ell * sizeof(double2), b, hipMemcpyDeviceToDevice, c.stream));
+                pass = 0;
+                continue;
+            }
+            AXS_BLAS(rocblas_ztrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                                   rocblas_diagonal_non_unit, ell, b, &one, zc(Rk), b, zc(Pn), ell));
+            ++pass;
+        }
+        if (k >= 0) break;
+        // Rp = R2 R1 (upper triangular), into rows j0.. of Rm
+        AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, b, b, b, &one, zc(R2), b, zc(R1), b,
+                               &zero, zc(Rp), b));
+        AXS_HIP(hipMemcpy2DAsync(Rm + j0 + (int64_t)j0 * ell, ell * sizeof(double2), Rp, b * sizeof(double2),
+                                 b * sizeof(double2), b, hipMemcpyDeviceToDevice, c.stream));
+        // project the trailing columns against Q twice; R12 rows = Q^H A (both passes)
+        const int64_t nt = nrem - b;
+        if (nt > 0) {
+            double2 *Ct = Atr + (int64_t)b * ell;
+            double2 *R12 = Rm + j0 + (int64_t)(j0 + b) * ell;
+            for (int pass = 0; pass < 2; ++pass) {
+                AXS_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, b,
+                                       (rocblas_int)nt, ell, &one, zc(Pn), ell, zc(Ct), ell, &zero, zc(S), b));
+                AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, ell, (rocblas_int)nt, b,
+                                       &mone, zc(Pn), ell, zc(S), b, &one, zc(Ct), ell));
+                if (pass == 0) {
+                    AXS_HIP(hipMemcpy2DAsync(R12, ell * sizeof(double2), S, b * sizeof(double2), b * sizeof(double2),
+                                             nt, hipMemcpyDeviceToDevice, c.stream));
+                } else {
+                    hipLaunchKernelGGL(cadd_kernel, dim3(ceil_div((int64_t)b * nt, 256)), dim3(256), 0, c.stream, R12,
+                                       S, b, nt, (int64_t)ell, (int64_t)b);
+                    AXS_HIP(hipGetLastError());
+                }
+            }
+        }
+        hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(BMAX), 0, c.stream, Rm, (int64_t)ell, j0, b, W);
+        AXS_HIP(hipGetLastError());
+        AXS_HIP(hipMemcpyAsync(hd.data(), W, b * sizeof(double2), hipMemcpyDeviceToHost, c.stream));
         AXS_HIP(hipStreamSynchronize(c.stream));
         for (int t = 0; t < b; ++t) {
             const double d = std::hypot(hd[t].x, hd[t].y);
@@ -1007,8 +1113,8 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, int ell, int64_t n, doubl
         j0 += b;
     }
     if (k < 0) k = kmax;
-    for (void *q : {(void *)tau, (void *)Om, (void *)G, (void *)nrm, (void *)dpiv, (void *)dnu2, (void *)tmp,
-                    (void *)mv, (void *)dg})
+    for (void *q : {(void *)Om, (void *)G, (void *)nrm, (void *)dpiv, (void *)dnu2, (void *)tmp, (void *)mv, (void *)W,
+                    (void *)S})
         c.dfree(q);
     return k;
 }
@@ -1037,7 +1143,7 @@ static void point_id(Ctx &c, const Shape &s, double R_p, double eps, int npx, ui
     const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
     const int64_t cap = std::min<int64_t>(n, Cpm);
     int ell = (int)std::min<int64_t>(256, cap);
-    double2 *A = nullptr;
+    double2 *Rm = nullptr;
     std::vector<int> perm;
     int k = 0;
     for (;;) {
@@ -1054,14 +1160,16 @@ static void point_id(Ctx &c, const Shape &s, double R_p, double eps, int npx, ui
                                    (rocblas_int)C, &zero, zc(W + (int64_t)(m + M) * ell), ell * nm));
         c.dfree(Psi);
         // A[:, i NF + l] = sum_m W[:, i (2M+1) + m + M] e^{-i m theta_l}
-        A = (double2 *)c.dalloc((size_t)ell * n * sizeof(double2));
+        double2 *A = (double2 *)c.dalloc((size_t)ell * n * sizeof(double2));
         AXS_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, ell, NF, nm, &one,
                                                zc(W), ell, (rocblas_stride)ell * nm, zc(Es), nm, 0, &zero, zc(A), ell,
                                                (rocblas_stride)ell * NF, NG));
         c.dfree(W);
-        k = hqrrp(c, h, A, ell, n, eps, seed, perm);
-        if (k <= ell - 16 || ell == cap) break;
+        Rm = (double2 *)c.dalloc((size_t)ell * n * sizeof(double2));
+        k = hqrrp(c, h, A, Rm, ell, n, eps, seed, perm);
         c.dfree(A);
+        if (k <= ell - 16 || ell == cap) break;
+        c.dfree(Rm);
         ell = (int)std::min<int64_t>(2 * (int64_t)ell, cap);
     }
     c.dfree(Es);
@@ -1071,8 +1179,8 @@ static void point_id(Ctx &c, const Shape &s, double R_p, double eps, int npx, ui
     // T = R_11^{-1} R_12 in place of R_12
     if (n > k)
         AXS_BLAS(rocblas_ztrsm(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                               rocblas_diagonal_non_unit, k, (rocblas_int)(n - k), &one, zc(A), ell,
-                               zc(A + (int64_t)k * ell), ell));
+                               rocblas_diagonal_non_unit, k, (rocblas_int)(n - k), &one, zc(Rm), ell,
+                               zc(Rm + (int64_t)k * ell), ell));
     nodes.assign(perm.begin(), perm.begin() + k);
     std::sort(nodes.begin(), nodes.end());
     std::vector<int> colof(k);
@@ -1082,12 +1190,12 @@ static void point_id(Ctx &c, const Shape &s, double R_p, double eps, int npx, ui
     AXS_HIP(hipMemcpy(d_perm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice));
     AXS_HIP(hipMemcpy(d_perm + n, colof.data(), k * sizeof(int), hipMemcpyHostToDevice));
     XT = (double2 *)c.dalloc((size_t)k * n * sizeof(double2));
-    hipLaunchKernelGGL(assemble_xt_kernel, dim3(ceil_div((int64_t)k * n, 256)), dim3(256), 0, c.stream, A,
+    hipLaunchKernelGGL(assemble_xt_kernel, dim3(ceil_div((int64_t)k * n, 256)), dim3(256), 0, c.stream, Rm,
                        (int64_t)ell, d_perm, d_perm + n, k, n, XT);
     AXS_HIP(hipGetLastError());
     AXS_HIP(hipStreamSynchronize(c.stream));
     c.dfree(d_perm);
-    c.dfree(A);
+    c.dfree(Rm);
 }
 
 // S_p = X^T A_pp^{-1} X (k x k, column-major) for one shape: the columns of X
