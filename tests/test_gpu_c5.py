@@ -69,6 +69,18 @@ def test_c5_interbody_sampled_rows_16_rhs(many):
     e3 = rel(y3, ref)
     print(f"FP32 MFMA order: rel err {e3:.2e}; FP16 vs FP32 multiply-accumulate {rel(y16, y3):.2e}", flush=True)
     assert e3 < 2 * fp32_sum_bound(wl, 16), e3
+    # the ring order (variant 2): the same FP32 geometry and phase with one
+    # FP32 complex product per pair on the VALU, so its error is that of the
+    # geometry and phase alone; the FP16 multiply-accumulate adds nothing
+    # measurable to it
+    ctx.set_interbody_config(FP32, 2, 0, 0, 0)
+    try:
+        y2 = ctx.apply_interbody(x, FP32).cpu().numpy()[:, rows]
+    finally:
+        ctx.set_interbody_config(FP32, 0, 0, 0, 0)
+    e2 = rel(y2, ref)
+    print(f"FP32 ring order: rel err {e2:.2e}; FP16 multiply-accumulate vs ring order {rel(y16, y2):.2e}", flush=True)
+    assert e2 < fp32_sum_bound(wl), e2
 
 
 def test_c5_modal_matrix_rows(many):
