@@ -800,14 +800,9 @@ axs_status axs_skeleton_nodes(axs_ctx *ctx, int body_id, int *count, int *nodes)
             out = c.skel->pts->nodes[sh];
         } else {
             // whole rings: the ascending skeleton rings times every azimuthal node
-            const Ctx &ch = *c.skel->child;
-            const axs::Shape &s = c.shapes[sh], &t = ch.shapes[sh];
-            int ring = 0;
-            for (int i = 0; i < s.NG && ring < t.NG; ++i) {
-                if (s.r[i] != t.r[ring] || s.z[i] != t.z[ring]) continue;
-                for (int l = 0; l < s.NF; ++l) out.push_back(i * s.NF + l);
-                ++ring;
-            }
+            const int NF = c.shapes[sh].NF;
+            for (int i : c.skel->rings[sh])
+                for (int l = 0; l < NF; ++l) out.push_back(i * NF + l);
         }
         if (nodes) {
             AXS_REQUIRE(*count >= (int)out.size(), AXS_EINVAL, "node array too small");

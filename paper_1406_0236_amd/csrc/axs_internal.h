@@ -263,6 +263,7 @@ struct Skeleton {
     double2 *X = nullptr;                // rings: per shape NG x k (row-major, columns by ascending ring)
     SkelBody *desc = nullptr;            // rings: [bodies]
     std::vector<int> rank;               // skeleton rings (nodes) per shape
+    std::vector<std::vector<int>> rings; // rings: ascending skeleton rings per shape
     int64_t Ns = 0;                      // skeleton nodes
     double eps = 0;
     std::unique_ptr<PointSkel> pts;      // nodes: the factors

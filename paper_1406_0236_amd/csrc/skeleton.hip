@@ -557,6 +557,7 @@ void skeletonize(Ctx &c, double eps, double factor) {
         t.A64 = nullptr;
         ch.shapes.push_back(t);
         sk->rank.push_back(t.NG);
+        sk->rings.push_back(rings[k]);
     }
     std::vector<SkelBody> desc;
     int64_t off = 0;
