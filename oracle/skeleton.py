@@ -19,8 +19,9 @@ V_p^* = X^T (x) I with one NG x k matrix X per shape acting on the contour
 index.  X is the row interpolative decomposition over the contour index of
 the modal blocks, stacked over all modes m = 0..M,
     H = [ IN_m  |  OUT_m^T ]_m ,
-IN_m: the field at the body's contour nodes of combined-field sources on a
-proxy sphere of radius R_p (incoming), OUT_m: the field of the body's nodes
+IN_m: the field at the body's contour nodes of combined-field sources D + i eta S
+on a proxy sphere of radius R_p (incoming; the coupling i eta at every
+frequency, also at kappa = 0 where the system's own coupling is real), OUT_m: the field of the body's nodes
 (weights included) at contour nodes of proxy spheres of radii R_p and 1.25 R_p
 (outgoing); a ring that interpolates every mode interpolates every azimuthal
 node.  The row ID comes from QR with column pivoting of H^*:
@@ -65,8 +66,14 @@ def modal_blocks(shape, R_p: float, n_in: int, n_out: int):
     # incoming: target body node i, source proxy node j (its normal, its weight)
     ti, sj = np.meshgrid(np.arange(sh.NG), np.arange(n_in), indexing="ij")
     ti, sj = ti.ravel(), sj.ravel()
-    _, _, kG = modal_kernels(sh.r[ti], r_[sj], r_[sj] - sh.r[ti], z_[sj] - sh.z[ti], nr_[sj], nz_[sj],
-                             sh.kappa, sh.eta, sh.M, Nt)
+    # the proxy's own sources carry the coupling i eta at every frequency: at
+    # kappa = 0 the system's real coupling eta would make D + eta S blind to
+    # the incoming fields of degree l with eta R_p = l + 1 (on a sphere of
+    # radius R_p the interior field of that layer with density Y_l is
+    # (eta R_p - (l + 1)) / (2l + 1) (r / R_p)^l Y_l)
+    kS, kD, _ = modal_kernels(sh.r[ti], r_[sj], r_[sj] - sh.r[ti], z_[sj] - sh.z[ti], nr_[sj], nz_[sj],
+                              sh.kappa, sh.eta, sh.M, Nt)
+    kG = (kD + 1j * sh.eta * kS) / (4.0 * math.pi)
     IN = (kG.reshape(sh.NG, n_in, sh.M + 1) * w_[None, :, None]).transpose(2, 0, 1)
     outs = []
     for R_o in (R_p, 1.25 * R_p):

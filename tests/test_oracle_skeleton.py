@@ -227,3 +227,30 @@ def test_point_skeleton_interpolates_unseen_fields(two_small):
     e_out = np.linalg.norm(red - full) / np.linalg.norm(full)
     print(f"k = {I.size}: incoming {e_in:.2e}, outgoing {e_out:.2e}")
     assert e_in < 1e-6 and e_out < 1e-6
+
+
+def test_zero_frequency_proxy_sees_every_degree():
+    """At kappa = 0 the system's coupling is real (D + eta S); on a proxy sphere
+    of radius R_p that layer has no interior field of degree l = eta R_p - 1
+    (its factor is eta R_p - (l + 1)), so proxy sources with the system's
+    coupling at eta = 1, R_p = 2 would miss every incoming dipole field.  The
+    proxy sources carry i eta instead: the point ID of a sphere interpolates
+    the fields of exterior point sources and of exterior dipoles."""
+    from workloads import geometry as geo
+    s = geo.sphere(1.0, 4, 10)
+    bodies = [configs.BodySpec(s, np.array([0.0, 0.0, 0.0]), np.eye(3), 8),
+              configs.BodySpec(s, np.array([5.0, 0.0, 0.0]), np.eye(3), 8)]
+    S = System.from_workload(configs.Workload("laplace_pair", 0.0, 1.0, bodies, np.zeros((1, 3))))
+    body = S.bodies[0]
+    I, X = point_id(body.shape, 2.0, 1e-8)
+    rng = np.random.default_rng(3)
+    src = _exterior_points(rng, 12, 2.2, 4.0)
+    d = (body.x - body.centre)[:, None, :] - src[None, :, :]
+    R = np.linalg.norm(d, axis=-1)
+    mono = (1.0 / (4 * np.pi * R)) @ rng.standard_normal(12)
+    pdir = rng.standard_normal((12, 3))
+    dip = (np.einsum("njc,jc->nj", d, pdir) / (4 * np.pi * R ** 3)) @ rng.standard_normal(12)
+    for name, u in (("point sources", mono), ("dipoles", dip)):
+        e = np.linalg.norm(X @ u[I] - u) / np.linalg.norm(u)
+        print(f"kappa = 0, {name}: k = {I.size}, interpolation error {e:.2e}")
+        assert e < 1e-7
