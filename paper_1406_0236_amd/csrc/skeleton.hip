@@ -342,6 +342,10 @@ static void proxy_fields(Ctx &c, const Shape &s, double R_p, int n_in, int n_out
         nz[i] = s.dr[i] / sp;
         aw[i] = s.r[i] * sp * s.gw[i];
     }
+    // the body's own kernel (real coupling eta at kappa = 0) for its outgoing
+    // fields; the proxy's sources use i eta at every frequency, since at kappa = 0
+    // the layer D + eta S on a sphere of radius R_p has no interior field of
+    // degree l = eta R_p - 1 (its factor is eta R_p - (l + 1))
     const double gr = s.kappa > 0 ? 0.0 : s.eta, gi = s.kappa > 0 ? s.eta : 0.0;
     std::vector<double> pr, pz, pnr, pnz, pw;
     proxy_rings(R_p, n_in, pr, pz, pnr, pnz, pw);
@@ -359,7 +363,7 @@ static void proxy_fields(Ctx &c, const Shape &s, double R_p, int n_in, int n_out
             h[6 * Pin + q] = pw[j];
         }
     kin = (double2 *)c.dalloc((size_t)Pin * (M + 1) * sizeof(double2));
-    modal_values(c, s.kappa, gr, gi, M, Nt, h, Pin, kin);
+    modal_values(c, s.kappa, 0.0, s.eta, M, Nt, h, Pin, kin);
     const int64_t Pout = (int64_t)2 * n_out * NG;
     std::vector<double> g(7 * Pout);
     for (int rr = 0; rr < 2; ++rr) {
