@@ -310,7 +310,8 @@ axs_status axs_skeletonize(axs_ctx *ctx, double eps, double proxy_factor, int64_
  * chosen by QR with randomized column pivoting of the sketch (blocks of 64
  * pivots, each block orthonormalised by CholeskyQR2 and projected out of the
  * rest twice); the rank k is the first pivot with |R_kk| < eps
- * |R_00|; ell doubles from 256 until k <= ell - 16.  Then U_p = V_p = X
+ * |R_00|; ell starts at 256 and grows, by the decay of |R_jj| seen, until
+ * k <= ell - 16.  Then U_p = V_p = X
  * (N_G N_F x k), S_p = X^T A_pp^{-1} X is dense k x k (FP64 and FP32 copies),
  * B~ is the point-order inter-body sum over the skeleton nodes, and
  * axs_solve_skeleton solves through it.

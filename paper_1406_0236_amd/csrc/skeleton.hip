@@ -653,7 +653,8 @@ void skel_prolong(Ctx &c, const void *w, const void *add, void *out, int nrhs) {
 // trailing columns projected against it twice, so that the dense work is
 // GEMMs; the rank k is the first pivot with |R_kk| < eps |R_00|, and
 // X(J, :) = (R_11^{-1} R_12)^* as in the ring version.  The sketch width ell
-// doubles from 256 until k <= ell - 16.  Then
+// starts at 256 and grows (by the decay of |R_jj| seen so far) until
+// k <= ell - 16.  Then
 //   S_p = X^T A_pp^{-1} X  (k x k, dense) from per-mode products with S_m,
 //   B~ the point-order inter-body sum over the skeleton nodes,
 // and the compressed system runs in a child context whose operator is
@@ -908,36 +909,48 @@ __global__ void gcol_step_kernel(double2 *__restrict__ G, int rows, int64_t n, c
 
 // Cholesky factor of a small Hermitian positive definite W (b x b, column-major,
 // b <= 64): W = R^H R with R upper triangular (lower part set to zero), one
-// workgroup, thread t owning column t.  info[0] = the first column whose pivot
-// is not positive (or not finite), b if none; R is valid in the columns before it.
-__global__ void chol_small_kernel(const double2 *__restrict__ W, int b, double2 *__restrict__ R, int *__restrict__ info) {
+// wavefront, the upper triangle held packed in LDS (entry (i, t), i <= t, at
+// t (t + 1) / 2 + i).  Step j: the pivot from a wavefront reduction of
+// |R(i, j)|^2 over i < j, then row j by lane t > j.  info[0] = the first
+// column whose pivot is not positive (or not finite), b if none; R is valid
+// in the columns before it.
+__global__ __launch_bounds__(64) void chol_small_kernel(const double2 *__restrict__ W, int b,
+                                                        double2 *__restrict__ R, int *__restrict__ info) {
+    __shared__ double2 U[64 * 65 / 2];
     __shared__ int fail;
     const int t = threadIdx.x;
     if (t == 0) fail = b;
-    for (int i = t; i < b * b; i += blockDim.x) R[i] = make_double2(0.0, 0.0);
+    if (t < b)
+        for (int i = 0; i <= t; ++i) U[t * (t + 1) / 2 + i] = W[i + t * b];
     __syncthreads();
     for (int j = 0; j < b; ++j) {
-        if (t == j && fail == b) {
-            double d = W[j + j * b].x;
-            for (int i = 0; i < j; ++i) d -= R[i + j * b].x * R[i + j * b].x + R[i + j * b].y * R[i + j * b].y;
-            if (d > 0.0 && d < INFINITY) R[j + j * b] = make_double2(sqrt(d), 0.0);
+        const int cj = j * (j + 1) / 2;
+        double part = 0.0;
+        if (t < j) part = U[cj + t].x * U[cj + t].x + U[cj + t].y * U[cj + t].y;
+        part = wave_sum64(part);
+        if (t == 0) {
+            const double d = U[cj + j].x - part;
+            if (d > 0.0 && d < INFINITY) U[cj + j] = make_double2(sqrt(d), 0.0);
             else fail = j;
         }
         __syncthreads();
         if (fail <= j) break;
         if (t > j && t < b) {
-            // R[j][t] = (W[j][t] - sum_{i<j} conj(R[i][j]) R[i][t]) / R[j][j]
-            double2 a = W[j + t * b];
+            // R(j, t) = (W(j, t) - sum_{i<j} conj(R(i, j)) R(i, t)) / R(j, j)
+            const int ct = t * (t + 1) / 2;
+            double2 a = U[ct + j];
             for (int i = 0; i < j; ++i) {
-                const double2 u = R[i + j * b], v = R[i + t * b];
+                const double2 u = U[cj + i], v = U[ct + i];
                 a.x -= u.x * v.x + u.y * v.y;
                 a.y -= u.x * v.y - u.y * v.x;
             }
-            const double r = R[j + j * b].x;
-            R[j + t * b] = make_double2(a.x / r, a.y / r);
+            const double r = U[cj + j].x;
+            U[ct + j] = make_double2(a.x / r, a.y / r);
         }
         __syncthreads();
     }
+    if (t < b)
+        for (int i = 0; i < b; ++i) R[i + t * b] = i <= t ? U[t * (t + 1) / 2 + i] : make_double2(0.0, 0.0);
     if (t == 0) info[0] = fail;
 }
 
@@ -962,11 +975,12 @@ __global__ void cadd_kernel(double2 *__restrict__ y, const double2 *__restrict__
 // twice) and the trailing columns are projected against it twice (block
 // classical Gram-Schmidt with reorthogonalisation): every step a GEMM.
 static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int64_t n, double eps, uint64_t seed,
-                 std::vector<int> &perm) {
+                 std::vector<int> &perm, std::vector<double> &diag) {
     constexpr int BMAX = 64, P = 16;
     const int kmax = (int)std::min<int64_t>(ell, n);
     perm.resize(n);
     std::iota(perm.begin(), perm.end(), 0);
+    diag.clear();
     double2 *Om = (double2 *)c.dalloc((size_t)(BMAX + P) * ell * sizeof(double2));
     double2 *G = (double2 *)c.dalloc((size_t)(BMAX + P) * n * sizeof(double2));
     double *nrm = (double *)c.dalloc(n * sizeof(double));
@@ -1109,6 +1123,7 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
         for (int t = 0; t < b; ++t) {
             const double d = std::hypot(hd[t].x, hd[t].y);
             AXS_REQUIRE(std::isfinite(d), AXS_ENONFINITE, "non-finite proxy sketch");
+            diag.push_back(d);
             if (j0 + t == 0) d0 = d;
             if (!(d > eps * d0)) {
                 k = j0 + t;
@@ -1122,6 +1137,24 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
                     (void *)S})
         c.dfree(q);
     return k;
+}
+
+// The next sketch width after one that ran out of rows before |R_jj| fell
+// below eps |R_00|: the decay of log |R_jj| over the second half of the pivots
+// seen, extrapolated to eps |R_00|, with a margin of 25 % + 64; at least 1.5x
+// and at most 8x the width tried (2x where the decay cannot be read).
+static int64_t next_sketch_width(const std::vector<double> &diag, double eps, int ell) {
+    const int64_t lo = (3 * (int64_t)ell + 1) / 2, hi = 8 * (int64_t)ell;
+    const size_t m = diag.size();
+    if (m < 32 || !(diag[0] > 0.0)) return 2 * (int64_t)ell;
+    const size_t a = m / 2, b = m - 1;
+    if (!(diag[a] > 0.0) || !(diag[b] > 0.0)) return 2 * (int64_t)ell;
+    const double slope = (std::log(diag[b]) - std::log(diag[a])) / (double)(b - a);
+    if (!(slope < 0.0)) return hi;
+    const double need = (std::log(eps * diag[0]) - std::log(diag[b])) / slope;   // pivots still to go
+    const double est = (double)b + std::max(need, 0.0);
+    const int64_t want = (int64_t)(1.25 * est) + 64;
+    return std::max(lo, std::min(hi, want));
 }
 
 // point ID of one shape: ascending skeleton nodes and X^T (device, k x n)
@@ -1171,11 +1204,12 @@ static void point_id(Ctx &c, const Shape &s, double R_p, double eps, int npx, ui
                                                (rocblas_stride)ell * NF, NG));
         c.dfree(W);
         Rm = (double2 *)c.dalloc((size_t)ell * n * sizeof(double2));
-        k = hqrrp(c, h, A, Rm, ell, n, eps, seed, perm);
+        std::vector<double> diag;
+        k = hqrrp(c, h, A, Rm, ell, n, eps, seed, perm, diag);
         c.dfree(A);
         if (k <= ell - 16 || ell == cap) break;
         c.dfree(Rm);
-        ell = (int)std::min<int64_t>(2 * (int64_t)ell, cap);
+        ell = (int)std::min<int64_t>(next_sketch_width(diag, eps, ell), cap);
     }
     c.dfree(Es);
     c.dfree(Bc);
