@@ -185,6 +185,9 @@ struct Ctx {
     // per-(wavefront, source body) whole revolutions floor(min (|p| - r_b) k/2pi)
     // stays inside the hardware sin/cos input range (ring and MFMA orders rely on it)
     bool near_phase_ok = false;
+    // every node pair is under 255 wavelengths apart (the point order then
+    // passes FP32 phases to the hardware sin/cos without a fraction step)
+    bool scene_phase_ok = false;
 
     // skeletonization (Sec. 5): the compressed system and its factors
     std::unique_ptr<Skeleton> skel;

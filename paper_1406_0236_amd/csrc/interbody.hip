@@ -18,7 +18,9 @@
 //   - FP64 path: the same structure with sin/cos from a 256-entry LDS table
 //     and short polynomials, and a Newton-refined hardware 1/sqrt.
 // Two source orders ("variants") compute the same sum:
-//   - points: each staged source carries x, y, z, n and q;
+//   - points: each staged source carries x, y, z, n and q (with one
+//     right-hand side: x and n scaled by powers of kappa / 2 pi, and the
+//     six density terms of the ring order's one-rhs form);
 //   - rings: a body's N_F nodes on one contour node form a ring; per target
 //     and ring the constants p (target in the source body's frame), |p|^2 + r^2,
 //     r p_x, r p_y, n_r p_x, n_r p_y are formed once, after which R^2 and n.d
@@ -127,20 +129,53 @@ __device__ __forceinline__ double rsq(double x) {
 }
 
 // LDS stride (in elements) of one staged source: x y z nx ny nz + NR complex q,
-// rounded up to 16 bytes so the compiler can use 128-bit LDS reads.
-template <typename R, int NR> struct SrcStride {
-    static constexpr int raw = 6 + 2 * NR;
+// or with one right-hand side (FOLD) the scaled position, the scaled normal
+// and the six density terms of ring_term1; rounded up to 16 bytes so the
+// compiler can use 128-bit LDS reads.
+template <typename R, int NR, bool FOLD> struct SrcStride {
+    static constexpr int raw = FOLD ? 12 : 6 + 2 * NR;
     static constexpr int per16 = 16 / sizeof(R);
     static constexpr int value = (raw + per16 - 1) / per16 * per16;
 };
 
+// One pair of the point order with one right-hand side, as ring_term1: r2 =
+// R'^2 and nd = nd' in revolutions, qv the staged density terms.  near: every
+// phase of the launch is under 255 revolutions, so the FP32 hardware sin/cos
+// take it without the fraction step; FP64 uses the table form, good for any
+// phase below 2^40 revolutions.
+template <typename R>
+__device__ __forceinline__ void point_term1(R r2, R nd, int near, const double2 *s_tab, const R *qv, R &ar,
+                                            R &ai) {
+    const R u = rsq(r2);
+    R sn, cs_;
+    if constexpr (sizeof(R) == 4) {
+        const R ph = r2 * u;
+        if (near)
+            sincos_rev_near(ph, sn, cs_);
+        else
+            sincos_rev(ph, sn, cs_);
+    } else {
+        sincos_phase(r2, u, R(0), s_tab, sn, cs_);
+    }
+    const R w = nd * u;
+    const R zr = fma(w, fma(u, qv[0], qv[2]), qv[4]);
+    const R zi = fma(w, fma(u, qv[1], qv[3]), qv[5]);
+    const R er = cs_ * u, ei = sn * u;
+    ar = fma(er, zr, fma(-ei, zi, ar));
+    ai = fma(er, zi, fma(ei, zr, ai));
+}
+
 template <typename R, int TPT, int NR, int BS, bool LAP>
 __global__ __launch_bounds__(BS) void interbody_kernel(
     const IBWork *__restrict__ work, const R *__restrict__ geo, const typename C2T<R>::T *__restrict__ q,
-    int64_t N, int nrhs, int c0, R kappa, R k2pi, R eta, const double2 *__restrict__ sctab,
+    int64_t N, int nrhs, int c0, R kappa, R k2pi, R eta, const double2 *__restrict__ sctab, int near,
     typename C2T<R>::T *__restrict__ part) {
     using R2 = typename C2T<R>::T;
-    constexpr int ST = SrcStride<R, NR>::value;
+    // one right-hand side: positions scaled by k/2pi, so R'^2 = |d'|^2 and
+    // nd' = (k/2pi)^2 n.d' (= n.d (k/2pi)^3) as in the ring order, and the
+    // density terms staged with the source (ring_term1)
+    constexpr bool FOLD = NR == 1 && !LAP;
+    constexpr int ST = SrcStride<R, NR, FOLD>::value;
     __shared__ __align__(16) R tile[BS * ST];
     __shared__ double2 s_tab[sizeof(R) == 8 ? 256 : 1];
     load_sctab<R, BS>(s_tab, sctab);
@@ -160,9 +195,15 @@ __global__ __launch_bounds__(BS) void interbody_kernel(
         tx[k] = gx[gi];
         ty[k] = gy[gi];
         tz[k] = gz[gi];
+        if constexpr (FOLD) {
+            tx[k] *= k2pi;
+            ty[k] *= k2pi;
+            tz[k] *= k2pi;
+        }
 #pragma unroll
         for (int c = 0; c < NR; ++c) ar[k][c] = ai[k][c] = R(0);
     }
+    const R s2 = k2pi * k2pi, etap = eta * k2pi;
 
 #pragma unroll 1
     for (int rng = 0; rng < 2; ++rng) {
@@ -172,7 +213,19 @@ __global__ __launch_bounds__(BS) void interbody_kernel(
         for (int base = lo; base < hi; base += BS) {
             const int cnt = min(BS, hi - base);
             __syncthreads();
-            if (tid < cnt) {
+            if (FOLD && tid < cnt) {
+                const int64_t j = base + tid;
+                R *d = tile + tid * ST;
+                const R2 v = q[(int64_t)cb * N + j];
+                const R tp = R(6.283185307179586476925287);
+                d[0] = gx[j] * k2pi;
+                d[1] = gy[j] * k2pi;
+                d[2] = gz[j] * k2pi;
+                d[3] = gnx[j] * s2;
+                d[4] = gny[j] * s2;
+                d[5] = gnz[j] * s2;
+                d[6] = v.x, d[7] = v.y, d[8] = tp * v.y, d[9] = -tp * v.x, d[10] = -etap * v.y, d[11] = etap * v.x;
+            } else if (!FOLD && tid < cnt) {
                 const int64_t j = base + tid;
                 R *d = tile + tid * ST;
                 d[0] = gx[j];
@@ -189,6 +242,24 @@ __global__ __launch_bounds__(BS) void interbody_kernel(
                 }
             }
             __syncthreads();
+            if constexpr (FOLD) {
+#pragma unroll 2
+                for (int js = 0; js < cnt; ++js) {
+                    const R *s = tile + js * ST;
+                    const R sx = s[0], sy = s[1], sz = s[2], snx = s[3], sny = s[4], snz = s[5];
+                    R qv[6];
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) qv[i] = s[6 + i];
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) {
+                        const R dx = tx[k] - sx, dy = ty[k] - sy, dz = tz[k] - sz;
+                        const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                        const R nd = fma(snx, dx, fma(sny, dy, snz * dz));
+                        point_term1<R>(r2, nd, near, s_tab, qv, ar[k][0], ai[k][0]);
+                    }
+                }
+                continue;
+            }
 #pragma unroll 2
             for (int js = 0; js < cnt; ++js) {
                 const R *s = tile + js * ST;
@@ -1213,6 +1284,16 @@ void build_ring_tables(Ctx &c) {
     double rmax = 0;
     for (auto &b : c.bodies) rmax = std::max(rmax, b.bound_radius);
     c.near_phase_ok = 4.0 * rmax * c.kappa / (2.0 * M_PI) + 2.0 < 256.0;
+    // every pair of nodes closer than 255 wavelengths: the point order's FP32
+    // phase stays inside the hardware sin/cos input range
+    double dmax = 0;
+    for (size_t a = 0; a < c.bodies.size(); ++a)
+        for (size_t b = a; b < c.bodies.size(); ++b) {
+            const auto &A = c.bodies[a], &B = c.bodies[b];
+            const double dx = A.centre[0] - B.centre[0], dy = A.centre[1] - B.centre[1], dz = A.centre[2] - B.centre[2];
+            dmax = std::max(dmax, std::sqrt(dx * dx + dy * dy + dz * dz) + A.bound_radius + B.bound_radius);
+        }
+    c.scene_phase_ok = dmax * c.kappa / (2.0 * M_PI) < 255.0;
     std::vector<int32_t> off(nr), nf(nr), body(nr), eoff(nr + 1, 0);
     std::vector<int2> pairs;
     std::vector<double> g(5 * (size_t)nr);
@@ -1355,7 +1436,8 @@ static void launch_ib(Ctx &c, int variant, const IBWork *work, int nwork, const 
                                c.sctab, part);                                                             \
         else                                                                                               \
             hipLaunchKernelGGL((interbody_kernel<R, TPT, NR_, BS, LAP>), dim3(nwork, groups), dim3(BS), 0, \
-                               c.stream, work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, c.sctab, part);    \
+                               c.stream, work, geo, q, c.N, nrhs, c0, kappa, k2pi, eta, c.sctab,        \
+                               c.scene_phase_ok ? 1 : 0, part);                                       \
     }
         AXS_IB_NR(8)
         AXS_IB_NR(4)

@@ -1376,6 +1376,7 @@ void skeletonize_points(Ctx &c, double eps, double factor, int n_proxy, uint64_t
     AXS_HIP(hipStreamSynchronize(c.stream));
     ch.dfree(d_idx);
     ch.sctab = c.sctab;            // the parent's table (it outlives the child)
+    ch.scene_phase_ok = c.scene_phase_ok;   // the skeleton nodes are a subset of the parent's
     ch.ib_variant[0] = ch.ib_variant[1] = 1;
     ch.pop = sk->pts.get();
     ch.precomputed = true;
