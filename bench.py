@@ -973,7 +973,8 @@ def skeleton(args, eps=1e-8):
 
 
 def batched(args):
-    """One batched solve of 64 right-hand sides on 8 bodies of three shapes."""
+    """One batched solve of 64 right-hand sides on 8 bodies of three shapes (and
+    the same through point skeletons at eps 1e-10)."""
     import numpy as np
     import torch
     from paper_1406_0236_amd import FP32, FP64, SOLVE_FP64, SOLVE_MIXED, Context, autotune
@@ -1018,6 +1019,7 @@ def batched(args):
     achieved = flops / t_ib / 1e12
     log(f"interbody fp32, {r} rhs: {t_ib*1e3:.2f} ms, {wl.pairs * r / t_ib / 1e9:.1f} G pair-rhs/s, "
         f"{achieved:.1f} TFLOP/s")
+    points = point_skeleton_leg(ctx, v, args.tol, 1e-10, sol)
     out = {
         "metric": "s to 1e-7 residual, 64 rhs batched (mixed vs FP64 GMRES); far-field TFLOP/s",
         "value": t_mixed, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -1033,6 +1035,7 @@ def batched(args):
         "speedup_mixed_vs_fp64": t64 / t_mixed,
         "precompute_s": t_pre,
         "autotuned": tuned,
+        "point_skeleton": points,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "kernel": f"FP32 inter-body sum, {r} rhs, launch shape "
