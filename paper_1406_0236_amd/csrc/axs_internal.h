@@ -185,6 +185,9 @@ struct Ctx {
     // per-(wavefront, source body) whole revolutions floor(min (|p| - r_b) k/2pi)
     // stays inside the hardware sin/cos input range (ring and MFMA orders rely on it)
     bool near_phase_ok = false;
+    // no ring tables (the child context of point skeletons): the ring order
+    // is never chosen
+    bool no_rings = false;
     // every node pair is under 255 wavelengths apart (the point order then
     // passes FP32 phases to the hardware sin/cos without a fraction step)
     bool scene_phase_ok = false;

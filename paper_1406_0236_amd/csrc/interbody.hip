@@ -1186,7 +1186,7 @@ static IBShape launch_shape(Ctx &c, int prec, int nrhs) {
     // FP16 multiply-accumulate where the kernel values have a bound; 4 groups
     // in FP64); the point order where neither applies.
     s.bs = c.ib_block[pi] > 0 ? c.ib_block[pi] : 256;
-    const bool ring_ok = c.max_nf / 2 + 1 <= s.bs && (c.kappa == 0 || c.near_phase_ok);
+    const bool ring_ok = !c.no_rings && c.max_nf / 2 + 1 <= s.bs && (c.kappa == 0 || c.near_phase_ok);
     const bool mf_ok = c.kappa > 0 && c.mf_src && c.near_phase_ok && s.bs == 256 &&
                        (c.ib_tpt[pi] == 0 || c.ib_tpt[pi] <= 4);
     const bool mf16_ok = mf_ok && prec == AXS_FP32 && c.mf16_ok;

@@ -789,6 +789,18 @@ __global__ void gather_geo_kernel(const double *__restrict__ g, int64_t N, const
     if (a < 6) g32[t] = (float)v;
 }
 
+// MFMA source operands of the skeleton nodes: entries 4 idx[j] + c of the
+// parent's two [4 N] halves
+__global__ void gather_mf_kernel(const double *__restrict__ src, int64_t N, const int64_t *__restrict__ idx,
+                                 int64_t Ns, double *__restrict__ dst64, float *__restrict__ dst32) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 8 * Ns) return;
+    const int64_t half = t / (4 * Ns), rem = t % (4 * Ns), j = rem / 4, comp = rem % 4;
+    const double v = src[half * 4 * N + 4 * idx[j] + comp];
+    dst64[t] = v;
+    dst32[t] = (float)v;
+}
+
 // e^{sign i (m' - M) 2 pi l / NF} * scale as a column-major matrix: rows m'
 // (2M+1) x cols l (NF) if mode_rows, else rows l x cols m'
 static std::vector<double2> dft_matrix(int M, int NF, double sign, double scale, bool mode_rows) {
@@ -1377,7 +1389,40 @@ void skeletonize_points(Ctx &c, double eps, double factor, int n_proxy, uint64_t
     ch.dfree(d_idx);
     ch.sctab = c.sctab;            // the parent's table (it outlives the child)
     ch.scene_phase_ok = c.scene_phase_ok;   // the skeleton nodes are a subset of the parent's
-    ch.ib_variant[0] = ch.ib_variant[1] = 1;
+    // no rings: the point order below 16 rhs; from 16 rhs the MFMA orders, with
+    // the parent's body frames and bounds, the skeleton nodes' MFMA operands
+    // gathered from the parent's and 32-node blocks of the skeleton bodies
+    ch.no_rings = true;
+    ch.near_phase_ok = c.near_phase_ok;
+    ch.mf16_ok = c.mf16_ok;
+    ch.mf16_gexp = c.mf16_gexp;
+    ch.frame32 = c.frame32;
+    ch.frame64 = c.frame64;
+    {
+        std::vector<int64_t> bo;
+        std::vector<int32_t> bk(1, 0);
+        for (const Body &B : ch.bodies) {
+            bo.push_back(B.offset);
+            bk.push_back(bk.back() + (int32_t)ceil_div(B.n, (int64_t)32));
+        }
+        bo.push_back(Ns);
+        ch.nblk = bk.back();
+        ch.body_off = (int64_t *)ch.dalloc(bo.size() * sizeof(int64_t));
+        AXS_HIP(hipMemcpy(ch.body_off, bo.data(), bo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        ch.blk_off = (int32_t *)ch.dalloc(bk.size() * sizeof(int32_t));
+        AXS_HIP(hipMemcpy(ch.blk_off, bk.data(), bk.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    if (c.mf_src64) {
+        int64_t *d_gi = (int64_t *)ch.dalloc(Ns * sizeof(int64_t));
+        AXS_HIP(hipMemcpy(d_gi, gidx.data(), Ns * sizeof(int64_t), hipMemcpyHostToDevice));
+        ch.mf_src64 = (double *)ch.dalloc(8 * Ns * sizeof(double));
+        ch.mf_src = (float *)ch.dalloc(8 * Ns * sizeof(float));
+        hipLaunchKernelGGL(gather_mf_kernel, dim3(ceil_div(8 * Ns, 256)), dim3(256), 0, c.stream, c.mf_src64, c.N,
+                           d_gi, Ns, ch.mf_src64, ch.mf_src);
+        AXS_HIP(hipGetLastError());
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        ch.dfree(d_gi);
+    }
     ch.pop = sk->pts.get();
     ch.precomputed = true;
     sk->Ns = Ns;
