@@ -46,7 +46,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
 # source they were taken on (source_fingerprint: code, not comments).
 TRAFFIC_BYTES = 115.16e6
-TRAFFIC_SOURCE_SHA = "3f9a468d504e82c7"
+TRAFFIC_SOURCE_SHA = "b694b1ce76a9af15"
 
 
 def source_fingerprint(path):
