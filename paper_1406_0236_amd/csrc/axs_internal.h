@@ -253,6 +253,16 @@ struct PointRun {
     int shape, first, nb, k, n;
     int64_t o0, s0;                      // first full node and first skeleton node of the run
 };
+// 256 rows of one body's dense m x K block (column-major, ld m) times the
+// body's K-vector of every rhs: the work item of the per-body products of
+// point skeletons (S_p in the skeleton system, X^T in the restriction)
+struct BodyMatItem {
+    const float2 *A32;                   // complex64 copy of the block, or null
+    const double2 *A64;                  // complex128
+    int64_t in0, out0;                   // the body's first entry in the input and output vectors
+    int m, K, row0, pad;
+};
+
 struct PointSkel {
     std::vector<int> k, n, ell;          // per shape: skeleton nodes, nodes, sketch width used
     std::vector<double> R_p;             // per shape: proxy radius
@@ -261,6 +271,9 @@ struct PointSkel {
     std::vector<double2 *> S64;
     std::vector<float2 *> S32;
     std::vector<PointRun> runs;
+    BodyMatItem *sp_items = nullptr;     // device: S_p per skeleton body
+    BodyMatItem *rs_items = nullptr;     // device: X^T per body (full -> skeleton)
+    int n_sp = 0, n_rs = 0;
 };
 
 struct Skeleton {

@@ -606,11 +606,14 @@ void release_skeleton(Ctx &c) {
         for (auto *p : c.skel->pts->XT) c.dfree(p);
         for (auto *p : c.skel->pts->S64) c.dfree(p);
         for (auto *p : c.skel->pts->S32) c.dfree(p);
+        if (c.skel->pts->sp_items) c.dfree(c.skel->pts->sp_items);
+        if (c.skel->pts->rs_items) c.dfree(c.skel->pts->rs_items);
     }
     c.skel.reset();
 }
 
 static void point_restrict(Ctx &c, const void *y, void *out, int nrhs, double alpha);
+static BodyMatItem *upload_items(Ctx &c, const std::vector<BodyMatItem> &bodies, int &count);
 static void point_prolong(Ctx &c, const void *w, const void *add, void *out, int nrhs);
 
 // restrict / prolong between the full and the skeleton vectors
@@ -1425,6 +1428,18 @@ void skeletonize_points(Ctx &c, double eps, double factor, int n_proxy, uint64_t
     }
     ch.pop = sk->pts.get();
     ch.precomputed = true;
+    {
+        std::vector<BodyMatItem> sp, rs;
+        for (size_t b = 0; b < nb; ++b) {
+            const Body &B = c.bodies[b];
+            const int sh = B.shape;
+            const int64_t s0 = ch.bodies[b].offset;
+            sp.push_back(BodyMatItem{P.S32[sh], P.S64[sh], s0, s0, P.k[sh], P.k[sh], 0, 0});
+            rs.push_back(BodyMatItem{nullptr, P.XT[sh], B.offset, s0, P.k[sh], P.n[sh], 0, 0});
+        }
+        P.sp_items = upload_items(c, sp, P.n_sp);
+        P.rs_items = upload_items(c, rs, P.n_rs);
+    }
     sk->Ns = Ns;
     sk->eps = eps;
     release_skeleton(c);
@@ -1432,6 +1447,156 @@ void skeletonize_points(Ctx &c, double eps, double factor, int n_proxy, uint64_t
 }
 
 // child of point skeletons: y = s + S (B~ s), B~ in `prec`, S_p in the same precision
+// C = alpha op(A) B + beta C for every body of a run and every rhs, A shared.
+// B holds a body's kk-vector per (body j, rhs c) at j bk + c bN, C its
+// m-vector at j ck + c cN.  With at least as many rhs as bodies: one GEMM per
+// body whose columns are the rhs (ld = the rhs stride); else one GEMM per rhs
+// whose columns are the bodies.  Either way A is streamed min(nb, nrhs) times,
+// not once per (body, rhs) column.
+template <typename T, typename Gemm>
+static void run_gemm(rocblas_handle h, Gemm gemm, rocblas_operation op, int m, int kk, int nb, int nrhs, const T *alpha,
+                     const T *A, int lda, const T *B, int64_t bk, int64_t bN, const T *beta, T *C, int64_t ck,
+                     int64_t cN) {
+    if (nrhs >= nb)
+        AXS_BLAS(gemm(h, op, rocblas_operation_none, m, nrhs, kk, alpha, A, lda, 0, B, (rocblas_int)bN,
+                      (rocblas_stride)bk, beta, C, (rocblas_int)cN, (rocblas_stride)ck, nb));
+    else
+        AXS_BLAS(gemm(h, op, rocblas_operation_none, m, nb, kk, alpha, A, lda, 0, B, (rocblas_int)bk,
+                      (rocblas_stride)bN, beta, C, (rocblas_int)ck, (rocblas_stride)cN, nrhs));
+}
+
+// out_b = alpha A_b in_b (+ out_b) for every body b of a work list and every
+// rhs: one workgroup per 256 rows of a body's block and NR rhs, one row per
+// thread, NR complex accumulators per thread.  The input rows of a 64-column
+// chunk (NR rhs) are staged in LDS and read back as broadcasts; A is read
+// once per (row, column) and rhs group, down its columns, so a wavefront's
+// load covers 64 consecutive rows.  With one body per launch of a GEMM
+// library the same product fills a few dozen workgroups; here every body of
+// every shape is in one launch.  In FP32 (R = float) the complex64 copy of A
+// is used and the input is rounded to FP32 as it is staged.
+template <typename R> struct CplxOf;
+template <> struct CplxOf<float> { using T = float2; };
+template <> struct CplxOf<double> { using T = double2; };
+constexpr int BM_KC = 64;
+
+template <typename R, int NR>
+__global__ __launch_bounds__(256) void body_matvec_kernel(const BodyMatItem *__restrict__ items,
+                                                          const double2 *__restrict__ in, int64_t inN, int nrhs,
+                                                          double2 *__restrict__ out, int64_t outN, double alpha,
+                                                          int accumulate) {
+    using C = typename CplxOf<R>::T;
+    __shared__ C sw[BM_KC * NR];
+    const BodyMatItem it = items[blockIdx.x];
+    const int c0 = blockIdx.y * NR;
+    const int i = it.row0 + (int)threadIdx.x;
+    const bool row_ok = i < it.m;
+    const C *A = sizeof(R) == 4 ? (const C *)(const void *)it.A32 : (const C *)(const void *)it.A64;
+    R ar[NR], ai[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) ar[q] = ai[q] = R(0);
+    for (int j0 = 0; j0 < it.K; j0 += BM_KC) {
+        const int kc = min(BM_KC, it.K - j0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < BM_KC * NR; t += 256) {
+            const int j = t % BM_KC, q = t / BM_KC;
+            C v;
+            v.x = R(0);
+            v.y = R(0);
+            if (j < kc && c0 + q < nrhs) {
+                const double2 x = in[(int64_t)(c0 + q) * inN + it.in0 + j0 + j];
+                v.x = (R)x.x;
+                v.y = (R)x.y;
+            }
+            sw[j * NR + q] = v;
+        }
+        __syncthreads();
+        if (row_ok) {
+            const C *col = A + (int64_t)j0 * it.m + i;
+            int j = 0;
+            for (; j + 8 <= kc; j += 8) {
+                C a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = col[(int64_t)(j + u) * it.m];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) {
+                        const C x = sw[(j + u) * NR + q];
+                        ar[q] = fma(a[u].x, x.x, fma(-a[u].y, x.y, ar[q]));
+                        ai[q] = fma(a[u].x, x.y, fma(a[u].y, x.x, ai[q]));
+                    }
+            }
+            for (; j < kc; ++j) {
+                const C a = col[(int64_t)j * it.m];
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    const C x = sw[j * NR + q];
+                    ar[q] = fma(a.x, x.x, fma(-a.y, x.y, ar[q]));
+                    ai[q] = fma(a.x, x.y, fma(a.y, x.x, ai[q]));
+                }
+            }
+        }
+    }
+    if (!row_ok) return;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        if (c0 + q >= nrhs) break;
+        double2 *o = out + (int64_t)(c0 + q) * outN + it.out0 + i;
+        double2 v = accumulate ? *o : make_double2(0.0, 0.0);
+        v.x += alpha * (double)ar[q];
+        v.y += alpha * (double)ai[q];
+        *o = v;
+    }
+}
+
+template <typename R>
+static void launch_body_matvec(Ctx &c, const BodyMatItem *items, int nitems, const double2 *in, int64_t inN,
+                               int nrhs, double2 *out, int64_t outN, double alpha, bool accumulate) {
+    if (nitems == 0) return;
+    const int nr = nrhs >= 16 ? 16 : nrhs >= 8 ? 8 : nrhs >= 4 ? 4 : nrhs >= 2 ? 2 : 1;
+    const dim3 grid(nitems, ceil_div(nrhs, nr));
+    const int acc = accumulate ? 1 : 0;
+    switch (nr) {
+    case 16:
+        hipLaunchKernelGGL((body_matvec_kernel<R, 16>), grid, dim3(256), 0, c.stream, items, in, inN, nrhs, out, outN,
+                           alpha, acc);
+        break;
+    case 8:
+        hipLaunchKernelGGL((body_matvec_kernel<R, 8>), grid, dim3(256), 0, c.stream, items, in, inN, nrhs, out, outN,
+                           alpha, acc);
+        break;
+    case 4:
+        hipLaunchKernelGGL((body_matvec_kernel<R, 4>), grid, dim3(256), 0, c.stream, items, in, inN, nrhs, out, outN,
+                           alpha, acc);
+        break;
+    case 2:
+        hipLaunchKernelGGL((body_matvec_kernel<R, 2>), grid, dim3(256), 0, c.stream, items, in, inN, nrhs, out, outN,
+                           alpha, acc);
+        break;
+    default:
+        hipLaunchKernelGGL((body_matvec_kernel<R, 1>), grid, dim3(256), 0, c.stream, items, in, inN, nrhs, out, outN,
+                           alpha, acc);
+    }
+    AXS_HIP(hipGetLastError());
+}
+
+// work items for one product per body: blocks A32/A64 of m_b x K_b rows, in
+// 256-row slices
+static BodyMatItem *upload_items(Ctx &c, const std::vector<BodyMatItem> &bodies, int &count) {
+    std::vector<BodyMatItem> v;
+    for (const BodyMatItem &b : bodies)
+        for (int r0 = 0; r0 < b.m; r0 += 256) {
+            BodyMatItem t = b;
+            t.row0 = r0;
+            v.push_back(t);
+        }
+    count = (int)v.size();
+    if (v.empty()) return nullptr;
+    BodyMatItem *d = (BodyMatItem *)c.dalloc(v.size() * sizeof(BodyMatItem));
+    AXS_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(BodyMatItem), hipMemcpyHostToDevice));
+    return d;
+}
+
 void point_operator(Ctx &c, const void *sigma, void *y, int nrhs, int prec) {
     const PointSkel &P = *c.pop;
     const int64_t Ns = c.N, tot = Ns * nrhs;
@@ -1439,42 +1604,17 @@ void point_operator(Ctx &c, const void *sigma, void *y, int nrhs, int prec) {
     double2 *w = (double2 *)c.scratch(WS_XR, tot * sizeof(double2));
     interbody_reduce_to_c128(c, w, nrhs, prec);
     if (y != sigma) AXS_HIP(hipMemcpyAsync(y, sigma, tot * sizeof(double2), hipMemcpyDeviceToDevice, c.stream));
-    rocblas_handle h = blas_of(c);
-    double2 *yy = (double2 *)y;
-    if (prec == AXS_FP64) {
-        const rocblas_double_complex one = {1.0, 0.0};
-        for (const PointRun &r : P.runs)
-            AXS_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, r.k, r.nb, r.k,
-                                                   &one, zc(P.S64[r.shape]), r.k, 0, zc(w + r.s0), r.k,
-                                                   (rocblas_stride)Ns, &one, zc(yy + r.s0), r.k, (rocblas_stride)Ns,
-                                                   nrhs));
-    } else {
-        float2 *w32 = (float2 *)c.scratch(WS_XI, 2 * tot * sizeof(float2));
-        float2 *t32 = w32 + tot;
-        hipLaunchKernelGGL(to_c64_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, w, tot, w32);
-        AXS_HIP(hipGetLastError());
-        const rocblas_float_complex one = {1.0f, 0.0f}, zero = {0.0f, 0.0f};
-        for (const PointRun &r : P.runs)
-            AXS_BLAS(rocblas_cgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, r.k, r.nb, r.k,
-                                                   &one, cc(P.S32[r.shape]), r.k, 0, cc(w32 + r.s0), r.k,
-                                                   (rocblas_stride)Ns, &zero, cc(t32 + r.s0), r.k, (rocblas_stride)Ns,
-                                                   nrhs));
-        hipLaunchKernelGGL(add_c64_kernel, dim3(ceil_div(tot, 256)), dim3(256), 0, c.stream, yy, t32, tot);
-        AXS_HIP(hipGetLastError());
-    }
+    if (prec == AXS_FP64)
+        launch_body_matvec<double>(c, P.sp_items, P.n_sp, w, Ns, nrhs, (double2 *)y, Ns, 1.0, true);
+    else
+        launch_body_matvec<float>(c, P.sp_items, P.n_sp, w, Ns, nrhs, (double2 *)y, Ns, 1.0, true);
 }
 
 // out = alpha X^T y per body (full [nrhs][N] -> skeleton [nrhs][Ns])
 static void point_restrict(Ctx &c, const void *y, void *out, int nrhs, double alpha) {
     const PointSkel &P = *c.skel->pts;
-    const int64_t N = c.N, Ns = c.skel->Ns;
-    rocblas_handle h = blas_of(c);
-    const rocblas_double_complex a = {alpha, 0.0}, zero = {0.0, 0.0};
-    for (const PointRun &r : P.runs)
-        AXS_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_none, r.k, r.nb, r.n, &a,
-                                               zc(P.XT[r.shape]), r.k, 0, zc((const double2 *)y + r.o0), r.n,
-                                               (rocblas_stride)N, &zero, zc((double2 *)out + r.s0), r.k,
-                                               (rocblas_stride)Ns, nrhs));
+    launch_body_matvec<double>(c, P.rs_items, P.n_rs, (const double2 *)y, c.N, nrhs, (double2 *)out, c.skel->Ns,
+                               alpha, false);
 }
 
 // out = add + X w per body (skeleton -> full)
@@ -1488,10 +1628,9 @@ static void point_prolong(Ctx &c, const void *w, const void *add, void *out, int
     rocblas_handle h = blas_of(c);
     const rocblas_double_complex one = {1.0, 0.0};
     for (const PointRun &r : P.runs)
-        AXS_BLAS(rocblas_zgemm_strided_batched(h, rocblas_operation_transpose, rocblas_operation_none, r.n, r.nb, r.k,
-                                               &one, zc(P.XT[r.shape]), r.k, 0, zc((const double2 *)w + r.s0), r.k,
-                                               (rocblas_stride)Ns, &one, zc((double2 *)out + r.o0), r.n,
-                                               (rocblas_stride)N, nrhs));
+        run_gemm(h, rocblas_zgemm_strided_batched, rocblas_operation_transpose, r.n, r.k, r.nb, nrhs, &one,
+                 zc(P.XT[r.shape]), r.k, zc((const double2 *)w + r.s0), r.k, Ns, &one, zc((double2 *)out + r.o0), r.n,
+                 N);
 }
 
 }  // namespace axs

@@ -210,18 +210,20 @@ def test_point_skeleton_counts_bracket_the_papers():
             ctx.close()
 
 
-def test_point_skeleton_batched_solve_on_mixed_bodies():
+@pytest.mark.parametrize("nrhs", [16, 5])
+def test_point_skeleton_batched_solve_on_mixed_bodies(nrhs):
     """Point skeletons of the 8 mixed bodies (three shapes in runs of one to
-    three bodies; kappa = 2 pi, discretised for 4 pi) with 16 right-hand sides:
-    the batched point-order sum over the skeleton nodes and the batched S_p
-    products inside the mixed solve; every lifted density close to the full
-    FP64 solution and with a certified full-system residual, at eps = 1e-10:
-    both within 5e-9 (4.3e-10 and 4.0e-10 seen; 13,862 of 59,130 unknowns
-    stay, against 42,444 with ring skeletons at 1e-8)."""
+    three bodies; kappa = 2 pi, discretised for 4 pi) with 16 right-hand sides
+    (the MFMA order over the skeleton nodes, the per-body products in one
+    group of 16 rhs) and with 5 (the point order; groups of 4, the second one
+    partly filled): every lifted density close to the full FP64 solution and
+    with a certified full-system residual, at eps = 1e-10: both within 5e-9
+    (4.3e-10 and 4.0e-10 seen with 16 rhs; 13,862 of 59,130 unknowns stay,
+    against 42,444 with ring skeletons at 1e-8)."""
     from paper_1406_0236_amd import SOLVE_FP64, SOLVE_MIXED
     from workloads import configs
-    wl = configs.mixed_bodies(n_dirs=16, disc_kappa=4 * np.pi)
-    print(f"[gpu] point skeleton batched {wl.name} N={wl.N}", flush=True)
+    wl = configs.mixed_bodies(n_dirs=nrhs, disc_kappa=4 * np.pi)
+    print(f"[gpu] point skeleton batched {wl.name} N={wl.N} rhs={nrhs}", flush=True)
     ctx = _ctx(wl)
     try:
         ns = ctx.skeletonize_points(1e-10, 2.0, 0, 3)
@@ -233,9 +235,9 @@ def test_point_skeleton_batched_solve_on_mixed_bodies():
         assert all(i["converged"] for i in info_f)
         sol, info = ctx.solve_skeleton(vd, mode=SOLVE_MIXED, tol=1e-11, max_iters=100, certify=True)
         x, xf = sol.cpu().numpy(), full.cpu().numpy()
-        errs = [_rel(x[c], xf[c]) for c in range(16)]
+        errs = [_rel(x[c], xf[c]) for c in range(nrhs)]
         res = [i["rel_residual"] for i in info]
-        print(f"16 rhs: worst error vs full solution {max(errs):.2e}, worst full-system residual {max(res):.2e}, "
+        print(f"{nrhs} rhs: worst error vs full solution {max(errs):.2e}, worst full-system residual {max(res):.2e}, "
               f"inner iterations {info[0]['inner_iterations']}", flush=True)
         assert max(errs) < 5e-9 and max(res) < 5e-9
     finally:
