@@ -17,7 +17,9 @@ carries
     (and, in `skeleton.points`, through point skeletons from the randomized ID);
   - `c5`: the largest workload (64 mixed bodies in a 24^3 box, kappa = 4 pi,
     N = 1,351,890, 16 plane waves): one mixed and one FP64 batched solve to
-    1e-7, iterations and explicit FP64 residuals;
+    1e-7, iterations and explicit FP64 residuals, and in
+    `c5.skeleton_points` the same 16 rhs through point skeletons at eps 1e-10
+    (one randomized ID per body shape);
   - `warm_start`: the learned warm start on the 8 mixed bodies (network trained
     on 4,096 of the method's own solves, k in [1.5 pi, 2.5 pi]), 512 held-out
     (k, direction) pairs solved from three initial guesses: zero, the
@@ -125,6 +127,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--small", action="store_true", help="two-sphere workload (quick check)")
     ap.add_argument("--no-c5", action="store_true", help="leave out the 64-body leg")
+    ap.add_argument("--no-c5-points", dest="c5_points", action="store_false",
+                    help="leave out the 64-body leg's point-skeleton solve")
     ap.add_argument("--no-warm-start", action="store_true", help="leave out the learned warm-start leg")
     ap.add_argument("--learned", action="store_true",
                     help="learned warm start on the 8 mixed bodies: 64 wavenumbers x 64 directions of "
@@ -412,6 +416,7 @@ def c5_leg(args):
     b_ = ctx.apply_precond(v, FP64)
     bn = torch.linalg.norm(b_, dim=1)
     res = {}
+    ref = None
     for mode, name in ((SOLVE_MIXED, "mixed"), (SOLVE_FP64, "fp64")):
         torch.cuda.synchronize()
         t0 = time.time()
@@ -424,12 +429,20 @@ def c5_leg(args):
                      "max_rel_residual": max(i["rel_residual"] for i in info),
                      "max_explicit_rel_residual": expl, "converged": all(i["converged"] for i in info)}
         log(f"c5 {name}: {dt:.1f} s, {res[name]}")
+        if name == "mixed":
+            ref = sol
         del sol
+    # the same 16 rhs through point skeletons of Sec. 5 (one ID per body shape)
+    points = point_skeleton_leg(ctx, v, args.tol, 1e-10, ref) if args.c5_points else None
+    del ref
     ctx.close()
-    return {"workload": wl.name, "bodies": len(wl.bodies), "N": wl.N, "kappa": wl.kappa, "nrhs": r,
-            "tol": args.tol, "precompute_s": t_pre, "interbody_pairs": wl.pairs, **res,
-            "speedup_mixed_vs_fp64": res["fp64"]["s"] / res["mixed"]["s"],
-            "initial_guess": "zero (the learned warm start is trained for the 8-body geometry only)"}
+    out = {"workload": wl.name, "bodies": len(wl.bodies), "N": wl.N, "kappa": wl.kappa, "nrhs": r,
+           "tol": args.tol, "precompute_s": t_pre, "interbody_pairs": wl.pairs, **res,
+           "speedup_mixed_vs_fp64": res["fp64"]["s"] / res["mixed"]["s"],
+           "initial_guess": "zero (the learned warm start is trained for the 8-body geometry only)"}
+    if points is not None:
+        out["skeleton_points"] = points
+    return out
 
 
 def warm_start_leg(n_k=64, n_d=64, held_k=8, held_d=64, epochs=200, log_fn=None):

@@ -310,11 +310,13 @@ axs_status axs_skeletonize(axs_ctx *ctx, double eps, double proxy_factor, int64_
  * chosen by QR with randomized column pivoting of the sketch (blocks of 64
  * pivots, each block orthonormalised by CholeskyQR2 and projected out of the
  * rest twice); the rank k is the first pivot with |R_kk| < eps
- * |R_00|; ell starts at 256 and grows, by the decay of |R_jj| seen, until
- * k <= ell - 16.  Then U_p = V_p = X
+ * |R_00|; ell starts at 256 for the first shape and at 1.25 k + 64 of the
+ * shape before for each later one, and grows, by the decay of |R_jj| seen,
+ * until k <= ell - 16.  Then U_p = V_p = X
  * (N_G N_F x k), S_p = X^T A_pp^{-1} X is dense k x k (FP64 and FP32 copies),
- * B~ is the point-order inter-body sum over the skeleton nodes, and
- * axs_solve_skeleton solves through it.
+ * B~ is the inter-body sum over the skeleton nodes (the point order, or the
+ * MFMA orders from 16 rhs), S_p and X^T are applied per body in one launch
+ * over all bodies, and axs_solve_skeleton solves through it.
  *  eps, proxy_factor : as for axs_skeletonize; every shape needs a proxy
  *                 radius of at least 1.05 x its bounding radius (AXS_EINVAL).
  *  n_proxy      : polar proxy points per sphere, 0 for 40 + ceil(1.25 kappa R_p).

@@ -1172,8 +1172,9 @@ static int64_t next_sketch_width(const std::vector<double> &diag, double eps, in
     return std::max(lo, std::min(hi, want));
 }
 
-// point ID of one shape: ascending skeleton nodes and X^T (device, k x n)
-static void point_id(Ctx &c, const Shape &s, double R_p, double eps, int npx, uint64_t seed,
+// point ID of one shape: ascending skeleton nodes and X^T (device, k x n); the
+// sketch starts max(256, ell0) rows wide and grows as next_sketch_width says
+static void point_id(Ctx &c, const Shape &s, double R_p, double eps, int npx, uint64_t seed, int ell0,
                      std::vector<int> &nodes, double2 *&XT, int &ell_used) {
     rocblas_handle h = blas_of(c);
     const int NG = s.NG, M = s.M, NF = s.NF, nm = 2 * M + 1;
@@ -1195,7 +1196,7 @@ static void point_id(Ctx &c, const Shape &s, double R_p, double eps, int npx, ui
     double2 *Es = upload(c, dft_matrix(M, NF, -1.0, 1.0, true));    // (2M+1) x NF: e^{-i m theta_l}
     const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
     const int64_t cap = std::min<int64_t>(n, Cpm);
-    int ell = (int)std::min<int64_t>(256, cap);
+    int ell = (int)std::min<int64_t>(std::max(256, ell0), cap);
     double2 *Rm = nullptr;
     std::vector<int> perm;
     int k = 0;
@@ -1328,11 +1329,16 @@ void skeletonize_points(Ctx &c, double eps, double factor, int n_proxy, uint64_t
     P.S64.assign(nsh, nullptr);
     P.S32.assign(nsh, nullptr);
     try {
+        // the first shape's sketch starts 256 wide; each later one at the width
+        // the rank of the one before would have asked for (shapes of one
+        // scene have similar ranks), which saves the narrower attempts
+        int ell0 = 256;
         for (size_t k = 0; k < nsh; ++k) {
             const Shape &s = c.shapes[k];
             const int npx = n_proxy > 0 ? n_proxy : 40 + (int)std::ceil(1.25 * s.kappa * Rp[k]);
-            point_id(c, s, Rp[k], eps, npx, seed, P.nodes[k], P.XT[k], P.ell[k]);
+            point_id(c, s, Rp[k], eps, npx, seed, ell0, P.nodes[k], P.XT[k], P.ell[k]);
             P.k[k] = (int)P.nodes[k].size();
+            ell0 = (int)(1.25 * P.k[k]) + 64;
             P.n[k] = s.NG * s.NF;
             point_sp(c, s, P.k[k], P.XT[k], P.S64[k], P.S32[k]);
             sk->rank.push_back(P.k[k]);
