@@ -166,6 +166,9 @@ def main():
     ap.add_argument("--skeleton", action="store_true",
                     help="the 27-sphere benchmark through the ring skeletonization of Sec. 5: ID time, "
                          "ranks, compressed mixed and FP64 solves, full-system residual of the lifted density")
+    ap.add_argument("--many-points", action="store_true",
+                    help="the 64-body workload (16 plane waves) through point skeletons only: ID at eps "
+                         "1e-10, one warm-up and one timed mixed solve, full-system residual")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="launch only what the hardware-counter passes measure: a 512 MiB device copy "
                          "(calibration), then two FP32 and one FP64 inter-body sums on the 27 spheres, "
@@ -202,6 +205,8 @@ def main():
         return shard(args)
     if args.skeleton:
         return skeleton(args)
+    if args.many_points:
+        return many_points(args)
 
     t_start = time.time()
     wl = configs.two_spheres() if args.small else configs.sphere_lattice()
@@ -934,6 +939,27 @@ def point_skeleton_leg(ctx, v, tol, eps=1e-8, ref=None):
         out["rel_diff_vs_uncompressed"] = float(torch.linalg.norm(sol - ref) / torch.linalg.norm(ref))
     log(f"point skeleton solve: {out}")
     return out
+
+
+def many_points(args, eps=1e-10):
+    """The 64-body workload's 16 plane waves through point skeletons only (one
+    randomized ID per body shape): the leg `c5.skeleton_points` of the default
+    line, on its own (for kernel traces)."""
+    import torch
+    from paper_1406_0236_amd import Context
+    from workloads import configs
+    wl = configs.mixed_many()
+    log(f"workload {wl.name}: N={wl.N}, rhs={len(wl.dirs)}")
+    ctx = Context(0).add_workload(wl)
+    ctx.precompute_scattering()
+    v = ctx.incident_plane_waves(wl.dirs)
+    torch.cuda.synchronize()
+    pts = point_skeleton_leg(ctx, v, args.tol, eps)
+    ctx.close()
+    print(json.dumps({"metric": "s to 1e-7 residual of the compressed system (Sec. 5 point skeletons), 16 rhs",
+                      "value": pts["mixed_s"], "unit": "s", "higher_is_better": False,
+                      "config": {"workload": wl.name, "N": wl.N, "nrhs": len(wl.dirs), "tol": args.tol},
+                      "skeleton_points": pts}), flush=True)
 
 
 def skeleton(args, eps=1e-8):
