@@ -983,52 +983,62 @@ __global__ void cadd_kernel(double2 *__restrict__ y, const double2 *__restrict__
 // QR with randomized column pivoting of A (ell x n, leading dimension ell),
 // blocks of 64 pivots, until |R_kk| < eps |R_00|; returns k and the column
 // order perm (perm[q] = original column at position q).  Rm (ell x n, leading
-// dimension ell) then holds R_11 and R_12 in its rows 0..k-1.  Per block: a
-// Gaussian sketch of the trailing columns (80 rows, one GEMM) chooses the
-// pivots (device-side pivoted Gram-Schmidt on the sketch); the chosen panel
-// is orthonormalised by CholeskyQR2 (Gram matrix, Cholesky, triangular solve,
-// twice) and the trailing columns are projected against it twice (block
-// classical Gram-Schmidt with reorthogonalisation): every step a GEMM.
+// dimension ell) then holds R_11 and R_12 in its rows 0..k-1.  Blocked as in
+// HQRRP, left-looking:
+//   - one Gaussian sketch Y = Omega A (80 rows) of the whole matrix; each
+//     block's 64 pivots are chosen on a copy of Y's trailing columns by
+//     device-side pivoted Gram-Schmidt; after the block Y is downdated,
+//     Y_t <- Y_t - (Y_p R_11^{-1}) R_12, so that it stays the sketch of the
+//     trailing columns projected against every chosen column;
+//   - the trailing columns of A are never updated: the chosen panel is
+//     projected against the Q of the earlier blocks (first pass with the
+//     R entries already known, a second pass that recomputes them), then
+//     orthonormalised by CholeskyQR2 (Gram matrix, Cholesky, triangular
+//     solve, twice); its rows of R_12 are Q_b^H A_t, one GEMM;
+// so each block costs one GEMM over the trailing columns instead of the four
+// of a right-looking update with reorthogonalisation.
 static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int64_t n, double eps, uint64_t seed,
                  std::vector<int> &perm, std::vector<double> &diag) {
-    constexpr int BMAX = 64, P = 16;
+    constexpr int BMAX = 64, P = 16, YR = BMAX + P;
     const int kmax = (int)std::min<int64_t>(ell, n);
     perm.resize(n);
     std::iota(perm.begin(), perm.end(), 0);
     diag.clear();
-    double2 *Om = (double2 *)c.dalloc((size_t)(BMAX + P) * ell * sizeof(double2));
-    double2 *G = (double2 *)c.dalloc((size_t)(BMAX + P) * n * sizeof(double2));
+    double2 *Om = (double2 *)c.dalloc((size_t)YR * ell * sizeof(double2));
+    double2 *Y = (double2 *)c.dalloc((size_t)YR * n * sizeof(double2));
+    double2 *G = (double2 *)c.dalloc((size_t)YR * n * sizeof(double2));
     double *nrm = (double *)c.dalloc(n * sizeof(double));
     int *dpiv = (int *)c.dalloc((BMAX + 2) * sizeof(int));
     int *dinfo = dpiv + BMAX;
     double *dnu2 = (double *)c.dalloc(BMAX * sizeof(double));
     double2 *tmp = (double2 *)c.dalloc((size_t)ell * 2 * BMAX * sizeof(double2));
+    double2 *rawA = (double2 *)c.dalloc((size_t)ell * BMAX * sizeof(double2));   // the panel before projection
+    double2 *rawR = (double2 *)c.dalloc((size_t)ell * BMAX * sizeof(double2));   // its R rows 0..j0-1
     int2 *mv = (int2 *)c.dalloc(2 * BMAX * sizeof(int2));
     double2 *W = (double2 *)c.dalloc(4 * BMAX * BMAX * sizeof(double2));
     double2 *R1 = W + BMAX * BMAX, *R2 = R1 + BMAX * BMAX, *Rp = R2 + BMAX * BMAX;
-    double2 *S = (double2 *)c.dalloc((size_t)BMAX * n * sizeof(double2));
+    double2 *S = (double2 *)c.dalloc((size_t)ell * BMAX * sizeof(double2));
     const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0}, mone = {-1.0, 0.0};
+    // Y = Omega A
+    hipLaunchKernelGGL(gauss_fill_kernel, dim3(ceil_div((int64_t)YR * ell, 256)), dim3(256), 0, c.stream, Om, YR,
+                       (int64_t)ell, seed + 0x5851F42D4C957F2DULL, (int64_t)1, (int64_t)YR, 0);
+    AXS_HIP(hipGetLastError());
+    AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, YR, (rocblas_int)n, ell, &one, zc(Om),
+                           YR, zc(A), ell, &zero, zc(Y), YR));
     std::vector<double2> hd(BMAX);
     double d0 = 0.0;
-    int k = -1, blk = 0;
-    for (int j0 = 0; j0 < kmax && k < 0; ++blk) {
+    int k = -1;
+    for (int j0 = 0; j0 < kmax && k < 0;) {
         int b = std::min(BMAX, kmax - j0);
-        const int rows = b + P;
         const int64_t nrem = n - j0;
-        double2 *Atr = A + (int64_t)j0 * ell;
-        // Gaussian sketch of the trailing columns: G = Om A[:, j0:n]
-        hipLaunchKernelGGL(gauss_fill_kernel, dim3(ceil_div((int64_t)rows * ell, 256)), dim3(256), 0, c.stream,
-                           Om, rows, (int64_t)ell, seed + 0x5851F42D4C957F2DULL * (uint64_t)(blk + 1), (int64_t)1,
-                           (int64_t)rows, 0);
-        AXS_HIP(hipGetLastError());
-        AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, rows, (rocblas_int)nrem, ell, &one,
-                               zc(Om), rows, zc(Atr), ell, &zero, zc(G), rows));
-        // b pivots by pivoted Gram-Schmidt over the columns of G, chosen on the device
+        // b pivots by pivoted Gram-Schmidt over a copy of the trailing sketch, chosen on the device
+        AXS_HIP(hipMemcpyAsync(G, Y + (int64_t)j0 * YR, (size_t)YR * nrem * sizeof(double2),
+                               hipMemcpyDeviceToDevice, c.stream));
         const unsigned gblk = (unsigned)ceil_div(nrem, (int64_t)4);
-        hipLaunchKernelGGL(gcol_norms_kernel, dim3(gblk), dim3(256), 0, c.stream, G, rows, nrem, nrm);
+        hipLaunchKernelGGL(gcol_norms_kernel, dim3(gblk), dim3(256), 0, c.stream, G, YR, nrem, nrm);
         hipLaunchKernelGGL(gcol_argmax_kernel, dim3(1), dim3(1024), 0, c.stream, nrm, nrem, dpiv, dnu2, 0);
         for (int t = 0; t < b; ++t) {
-            hipLaunchKernelGGL(gcol_step_kernel, dim3(gblk), dim3(256), 0, c.stream, G, rows, nrem, dpiv, dnu2, t,
+            hipLaunchKernelGGL(gcol_step_kernel, dim3(gblk), dim3(256), 0, c.stream, G, YR, nrem, dpiv, dnu2, t,
                                nrm);
             if (t + 1 < b)
                 hipLaunchKernelGGL(gcol_argmax_kernel, dim3(1), dim3(1024), 0, c.stream, nrm, nrem, dpiv, dnu2,
@@ -1045,8 +1055,8 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
                 seen[loc[t]] = 1;
             }
         }
-        // move the chosen columns to positions j0 .. j0 + b - 1 (all ell rows)
-        std::vector<int> dst_of(b, -1);
+        // move the chosen columns to positions j0 .. j0 + b - 1 (A and Rm: all
+        // ell rows; Y: its YR rows)
         std::vector<int2> moves;
         std::vector<char> taken(b, 0);
         for (int t = 0; t < b; ++t)
@@ -1070,17 +1080,37 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
                 for (int ph = 0; ph < 2; ++ph)
                     hipLaunchKernelGGL(move_cols_kernel, dim3(ceil_div((int64_t)ell * cnt, 256)), dim3(256), 0,
                                        c.stream, M, (int64_t)ell, ell, mv, cnt, tmp, ph);
+            for (int ph = 0; ph < 2; ++ph)
+                hipLaunchKernelGGL(move_cols_kernel, dim3(ceil_div((int64_t)YR * cnt, 256)), dim3(256), 0, c.stream,
+                                   Y, (int64_t)YR, YR, mv, cnt, tmp, ph);
             AXS_HIP(hipGetLastError());
             AXS_HIP(hipStreamSynchronize(c.stream));   // moves is pageable host memory
         }
-        // CholeskyQR2 of the panel Pn = A[:, j0:j0+b]: Pn = Q Rp, Q in place of Pn.
-        // A Cholesky that finds less rank than b columns shortens the panel to
-        // that rank (the rest stay in the trailing matrix) and starts again from
-        // a copy of the panel.
-        double2 *Pn = Atr;
-        AXS_HIP(hipMemcpy2DAsync(tmp, ell * sizeof(double2), Pn, ell * sizeof(double2), ell * sizeof(double2), b,
+        // the panel Pn = A[:, j0:j0+b], kept raw (with its R rows 0..j0-1) so
+        // that a panel shortened by the Cholesky can give its other columns
+        // back to the trailing matrix unprojected
+        double2 *Pn = A + (int64_t)j0 * ell;
+        double2 *Rcol = Rm + (int64_t)j0 * ell;     // rows 0..j0-1 of the panel's columns
+        AXS_HIP(hipMemcpy2DAsync(rawA, ell * sizeof(double2), Pn, ell * sizeof(double2), ell * sizeof(double2), b,
                                  hipMemcpyDeviceToDevice, c.stream));
+        if (j0 > 0)
+            AXS_HIP(hipMemcpy2DAsync(rawR, ell * sizeof(double2), Rcol, ell * sizeof(double2),
+                                     (size_t)j0 * sizeof(double2), b, hipMemcpyDeviceToDevice, c.stream));
         for (int pass = 0; pass < 2;) {
+            if (pass == 0 && j0 > 0) {
+                // project against Q = A[:, 0:j0]: first with the known R rows
+                // (Q^H of the raw columns), then recomputed (reorthogonalisation)
+                AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, ell, b, j0, &mone, zc(A),
+                                       ell, zc(Rcol), ell, &one, zc(Pn), ell));
+                AXS_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, j0, b, ell,
+                                       &one, zc(A), ell, zc(Pn), ell, &zero, zc(S), j0));
+                AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, ell, b, j0, &mone, zc(A),
+                                       ell, zc(S), j0, &one, zc(Pn), ell));
+                hipLaunchKernelGGL(cadd_kernel, dim3(ceil_div((int64_t)j0 * b, 256)), dim3(256), 0, c.stream, Rcol,
+                                   S, j0, (int64_t)b, (int64_t)ell, (int64_t)j0);
+                AXS_HIP(hipGetLastError());
+            }
+            // CholeskyQR2 of the projected panel: Pn = Q Rp, Q in place of Pn
             double2 *Rk = pass == 0 ? R1 : R2;
             AXS_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, b, b, ell, &one,
                                    zc(Pn), ell, zc(Pn), ell, &zero, zc(W), b));
@@ -1095,9 +1125,13 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
                     k = j0;
                     break;
                 }
-                b = info;
-                AXS_HIP(hipMemcpy2DAsync(Pn, ell * sizeof(double2), tmp, ell * sizeof(double2),
+                // give every panel column back raw, then retry with the first info
+                AXS_HIP(hipMemcpy2DAsync(Pn, ell * sizeof(double2), rawA, ell * sizeof(double2),
                                          ell * sizeof(double2), b, hipMemcpyDeviceToDevice, c.stream));
+                if (j0 > 0)
+                    AXS_HIP(hipMemcpy2DAsync(Rcol, ell * sizeof(double2), rawR, ell * sizeof(double2),
+                                             (size_t)j0 * sizeof(double2), b, hipMemcpyDeviceToDevice, c.stream));
+                b = info;
                 pass = 0;
                 continue;
             }
@@ -1111,25 +1145,18 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
                                &zero, zc(Rp), b));
         AXS_HIP(hipMemcpy2DAsync(Rm + j0 + (int64_t)j0 * ell, ell * sizeof(double2), Rp, b * sizeof(double2),
                                  b * sizeof(double2), b, hipMemcpyDeviceToDevice, c.stream));
-        // project the trailing columns against Q twice; R12 rows = Q^H A (both passes)
+        // rows j0..j0+b-1 of R_12 = Q_b^H A_t, and the sketch downdate
         const int64_t nt = nrem - b;
         if (nt > 0) {
-            double2 *Ct = Atr + (int64_t)b * ell;
-            double2 *R12 = Rm + j0 + (int64_t)(j0 + b) * ell;
-            for (int pass = 0; pass < 2; ++pass) {
-                AXS_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, b,
-                                       (rocblas_int)nt, ell, &one, zc(Pn), ell, zc(Ct), ell, &zero, zc(S), b));
-                AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, ell, (rocblas_int)nt, b,
-                                       &mone, zc(Pn), ell, zc(S), b, &one, zc(Ct), ell));
-                if (pass == 0) {
-                    AXS_HIP(hipMemcpy2DAsync(R12, ell * sizeof(double2), S, b * sizeof(double2), b * sizeof(double2),
-                                             nt, hipMemcpyDeviceToDevice, c.stream));
-                } else {
-                    hipLaunchKernelGGL(cadd_kernel, dim3(ceil_div((int64_t)b * nt, 256)), dim3(256), 0, c.stream, R12,
-                                       S, b, nt, (int64_t)ell, (int64_t)b);
-                    AXS_HIP(hipGetLastError());
-                }
-            }
+            const int64_t jt = j0 + b;
+            AXS_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, b,
+                                   (rocblas_int)nt, ell, &one, zc(Pn), ell, zc(A + jt * ell), ell, &zero,
+                                   zc(Rm + j0 + jt * ell), ell));
+            double2 *Yp = Y + (int64_t)j0 * YR;
+            AXS_BLAS(rocblas_ztrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                                   rocblas_diagonal_non_unit, YR, b, &one, zc(Rp), b, zc(Yp), YR));
+            AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, YR, (rocblas_int)nt, b, &mone,
+                                   zc(Yp), YR, zc(Rm + j0 + jt * ell), ell, &one, zc(Y + jt * YR), YR));
         }
         hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(BMAX), 0, c.stream, Rm, (int64_t)ell, j0, b, W);
         AXS_HIP(hipGetLastError());
@@ -1148,8 +1175,8 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
         j0 += b;
     }
     if (k < 0) k = kmax;
-    for (void *q : {(void *)Om, (void *)G, (void *)nrm, (void *)dpiv, (void *)dnu2, (void *)tmp, (void *)mv, (void *)W,
-                    (void *)S})
+    for (void *q : {(void *)Om, (void *)Y, (void *)G, (void *)nrm, (void *)dpiv, (void *)dnu2, (void *)tmp,
+                    (void *)rawA, (void *)rawR, (void *)mv, (void *)W, (void *)S})
         c.dfree(q);
     return k;
 }
