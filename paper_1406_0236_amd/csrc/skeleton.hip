@@ -838,31 +838,63 @@ __device__ __forceinline__ double wave_sum64(double v) {
     return v;
 }
 
-__global__ void gcol_norms_kernel(const double2 *__restrict__ G, int rows, int64_t n, double *__restrict__ nrm) {
-    const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (col >= n) return;   // the same for the whole wavefront
-    const double2 *g = G + col * rows;
-    double a = 0.0;
-    for (int r = lane; r < rows; r += 64) a = fma(g[r].x, g[r].x, fma(g[r].y, g[r].y, a));
-    a = wave_sum64(a);
-    if (lane == 0) nrm[col] = a;
+// the best remaining column of a block of 4 wavefronts (one column each, lane
+// 0 holding its squared norm a, -1 for a chosen or absent column): part_v /
+// part_i[blockIdx.x]; NaN never wins, ties go to the smaller column
+__device__ __forceinline__ void gcol_block_best(double a, int64_t col, double *__restrict__ part_v,
+                                                int *__restrict__ part_i) {
+    __shared__ double sv[4];
+    __shared__ int si[4];
+    if ((threadIdx.x & 63) == 0) {
+        sv[threadIdx.x >> 6] = a;
+        si[threadIdx.x >> 6] = a >= 0.0 ? (int)col : -1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bv = -1.0;
+        int bi = -1;
+        for (int w = 0; w < 4; ++w)   // columns rise with w: the first maximum stays
+            if (si[w] >= 0 && sv[w] > bv) {
+                bv = sv[w];
+                bi = si[w];
+            }
+        part_v[blockIdx.x] = bv;
+        part_i[blockIdx.x] = bi;
+    }
 }
 
-// the largest squared norm among the unchosen columns (ties to the smaller
-// index; NaN never wins): piv[t], nu2[t], and the column is marked chosen.
-// piv[t] = -1 if every remaining norm is NaN.
-__global__ void gcol_argmax_kernel(double *__restrict__ nrm, int64_t n, int *__restrict__ piv,
-                                   double *__restrict__ nu2, int t) {
+__global__ __launch_bounds__(256) void gcol_norms_kernel(const double2 *__restrict__ G, int rows, int64_t n,
+                                                         double *__restrict__ nrm, double *__restrict__ part_v,
+                                                         int *__restrict__ part_i) {
+    const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double a = -1.0;
+    if (col < n) {   // the same for the whole wavefront
+        const double2 *g = G + col * rows;
+        double acc = 0.0;
+        for (int r = lane; r < rows; r += 64) acc = fma(g[r].x, g[r].x, fma(g[r].y, g[r].y, acc));
+        a = wave_sum64(acc);
+        if (lane == 0) nrm[col] = a;
+    }
+    gcol_block_best(a, col, part_v, part_i);
+}
+
+// the best of the blocks' candidates (ties to the smaller column): piv[t],
+// nu2[t], and the column is marked chosen; piv[t] = -1 if none is left
+__global__ __launch_bounds__(1024) void gcol_argmax_kernel(const double *__restrict__ part_v,
+                                                           const int *__restrict__ part_i, int nparts,
+                                                           double *__restrict__ nrm, int *__restrict__ piv,
+                                                           double *__restrict__ nu2, int t) {
     __shared__ double sv[1024];
     __shared__ int si[1024];
     double bv = -1.0;
     int bi = -1;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) {
-        const double v = nrm[i];
-        if (v > bv) {   // indices rise within a thread: the first maximum stays
+    for (int q = threadIdx.x; q < nparts; q += 1024) {   // blocks rise within a thread
+        const int i = part_i[q];
+        const double v = part_v[q];
+        if (i >= 0 && v > bv) {
             bv = v;
-            bi = (int)i;
+            bi = i;
         }
     }
     sv[threadIdx.x] = bv;
@@ -888,38 +920,44 @@ __global__ void gcol_argmax_kernel(double *__restrict__ nrm, int64_t n, int *__r
     }
 }
 
-// one Gram-Schmidt step against the pivot column piv[t] (two projections),
-// then the new squared norms; chosen columns (nrm < 0) are left alone
-__global__ void gcol_step_kernel(double2 *__restrict__ G, int rows, int64_t n, const int *__restrict__ piv,
-                                 const double *__restrict__ nu2, int t, double *__restrict__ nrm) {
+// one Gram-Schmidt step against the pivot column piv[t]: one projection, the
+// squared norm recomputed from the updated column in the same pass (not
+// downdated), and each block's best remaining column for the next argmax.
+// Chosen columns (nrm < 0) are left alone.
+__global__ __launch_bounds__(256) void gcol_step_kernel(double2 *__restrict__ G, int rows, int64_t n,
+                                                        const int *__restrict__ piv, const double *__restrict__ nu2,
+                                                        int t, double *__restrict__ nrm, double *__restrict__ part_v,
+                                                        int *__restrict__ part_i) {
     const int64_t col = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (col >= n) return;
     const int p = piv[t];
     const double s = nu2[t];
-    if (p < 0 || nrm[col] < 0.0) return;   // uniform across the wavefront
-    double2 *g = G + col * rows;
-    const double2 *u = G + (int64_t)p * rows;
-    if (s > 0.0) {
-        for (int pass = 0; pass < 2; ++pass) {
-            double dr = 0.0, di = 0.0;   // <g, u> = sum g conj(u)
+    double a = -1.0;
+    if (col < n && p >= 0 && nrm[col] >= 0.0) {   // uniform across the wavefront
+        double2 *g = G + col * rows;
+        const double2 *u = G + (int64_t)p * rows;
+        double dr = 0.0, di = 0.0;   // <g, u> = sum g conj(u)
+        if (s > 0.0) {
             for (int r = lane; r < rows; r += 64) {
                 dr = fma(g[r].x, u[r].x, fma(g[r].y, u[r].y, dr));
                 di = fma(g[r].y, u[r].x, fma(-g[r].x, u[r].y, di));
             }
             dr = wave_sum64(dr) / s;
             di = wave_sum64(di) / s;
-            for (int r = lane; r < rows; r += 64) {
-                const double2 w = u[r];
-                g[r].x -= dr * w.x - di * w.y;
-                g[r].y -= dr * w.y + di * w.x;
-            }
         }
+        double acc = 0.0;
+        for (int r = lane; r < rows; r += 64) {
+            const double2 w = u[r];
+            double2 v = g[r];
+            v.x -= dr * w.x - di * w.y;
+            v.y -= dr * w.y + di * w.x;
+            g[r] = v;
+            acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+        }
+        a = wave_sum64(acc);
+        if (lane == 0) nrm[col] = a;
     }
-    double a = 0.0;
-    for (int r = lane; r < rows; r += 64) a = fma(g[r].x, g[r].x, fma(g[r].y, g[r].y, a));
-    a = wave_sum64(a);
-    if (lane == 0) nrm[col] = a;
+    gcol_block_best(a, col, part_v, part_i);
 }
 
 // Cholesky factor of a small Hermitian positive definite W (b x b, column-major,
@@ -1008,6 +1046,10 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
     double2 *Y = (double2 *)c.dalloc((size_t)YR * n * sizeof(double2));
     double2 *G = (double2 *)c.dalloc((size_t)YR * n * sizeof(double2));
     double *nrm = (double *)c.dalloc(n * sizeof(double));
+    const int64_t maxblk = ceil_div(n, (int64_t)4);
+    AXS_REQUIRE(maxblk <= INT32_MAX && n <= INT32_MAX, AXS_EINVAL, "too many nodes in one shape");
+    double *part_v = (double *)c.dalloc(maxblk * sizeof(double));
+    int *part_i = (int *)c.dalloc(maxblk * sizeof(int));
     int *dpiv = (int *)c.dalloc((BMAX + 2) * sizeof(int));
     int *dinfo = dpiv + BMAX;
     double *dnu2 = (double *)c.dalloc(BMAX * sizeof(double));
@@ -1035,14 +1077,15 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
         AXS_HIP(hipMemcpyAsync(G, Y + (int64_t)j0 * YR, (size_t)YR * nrem * sizeof(double2),
                                hipMemcpyDeviceToDevice, c.stream));
         const unsigned gblk = (unsigned)ceil_div(nrem, (int64_t)4);
-        hipLaunchKernelGGL(gcol_norms_kernel, dim3(gblk), dim3(256), 0, c.stream, G, YR, nrem, nrm);
-        hipLaunchKernelGGL(gcol_argmax_kernel, dim3(1), dim3(1024), 0, c.stream, nrm, nrem, dpiv, dnu2, 0);
-        for (int t = 0; t < b; ++t) {
+        hipLaunchKernelGGL(gcol_norms_kernel, dim3(gblk), dim3(256), 0, c.stream, G, YR, nrem, nrm, part_v,
+                           part_i);
+        hipLaunchKernelGGL(gcol_argmax_kernel, dim3(1), dim3(1024), 0, c.stream, part_v, part_i, (int)gblk, nrm, dpiv,
+                           dnu2, 0);
+        for (int t = 0; t + 1 < b; ++t) {
             hipLaunchKernelGGL(gcol_step_kernel, dim3(gblk), dim3(256), 0, c.stream, G, YR, nrem, dpiv, dnu2, t,
-                               nrm);
-            if (t + 1 < b)
-                hipLaunchKernelGGL(gcol_argmax_kernel, dim3(1), dim3(1024), 0, c.stream, nrm, nrem, dpiv, dnu2,
-                                   t + 1);
+                               nrm, part_v, part_i);
+            hipLaunchKernelGGL(gcol_argmax_kernel, dim3(1), dim3(1024), 0, c.stream, part_v, part_i, (int)gblk, nrm,
+                               dpiv, dnu2, t + 1);
         }
         AXS_HIP(hipGetLastError());
         std::vector<int> loc(b);
@@ -1175,7 +1218,8 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
         j0 += b;
     }
     if (k < 0) k = kmax;
-    for (void *q : {(void *)Om, (void *)Y, (void *)G, (void *)nrm, (void *)dpiv, (void *)dnu2, (void *)tmp,
+    for (void *q : {(void *)Om, (void *)Y, (void *)G, (void *)nrm, (void *)part_v, (void *)part_i, (void *)dpiv,
+                    (void *)dnu2, (void *)tmp,
                     (void *)rawA, (void *)rawR, (void *)mv, (void *)W, (void *)S})
         c.dfree(q);
     return k;
