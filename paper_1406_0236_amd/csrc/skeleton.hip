@@ -923,6 +923,7 @@ __global__ __launch_bounds__(1024) void gcol_argmax_kernel(const double *__restr
 // one Gram-Schmidt step against the pivot column piv[t]: one projection, the
 // squared norm recomputed from the updated column in the same pass (not
 // downdated), and each block's best remaining column for the next argmax.
+// A column (rows <= 128) is read once into registers, two entries per lane.
 // Chosen columns (nrm < 0) are left alone.
 __global__ __launch_bounds__(256) void gcol_step_kernel(double2 *__restrict__ G, int rows, int64_t n,
                                                         const int *__restrict__ piv, const double *__restrict__ nu2,
@@ -936,25 +937,24 @@ __global__ __launch_bounds__(256) void gcol_step_kernel(double2 *__restrict__ G,
     if (col < n && p >= 0 && nrm[col] >= 0.0) {   // uniform across the wavefront
         double2 *g = G + col * rows;
         const double2 *u = G + (int64_t)p * rows;
-        double dr = 0.0, di = 0.0;   // <g, u> = sum g conj(u)
+        const bool h0 = lane < rows, h1 = lane + 64 < rows;
+        const double2 z = make_double2(0.0, 0.0);
+        double2 g0 = h0 ? g[lane] : z, g1 = h1 ? g[lane + 64] : z;
+        const double2 u0 = h0 ? u[lane] : z, u1 = h1 ? u[lane + 64] : z;
         if (s > 0.0) {
-            for (int r = lane; r < rows; r += 64) {
-                dr = fma(g[r].x, u[r].x, fma(g[r].y, u[r].y, dr));
-                di = fma(g[r].y, u[r].x, fma(-g[r].x, u[r].y, di));
-            }
+            // <g, u> = sum g conj(u)
+            double dr = fma(g0.x, u0.x, fma(g0.y, u0.y, fma(g1.x, u1.x, g1.y * u1.y)));
+            double di = fma(g0.y, u0.x, fma(-g0.x, u0.y, fma(g1.y, u1.x, -g1.x * u1.y)));
             dr = wave_sum64(dr) / s;
             di = wave_sum64(di) / s;
+            g0.x -= dr * u0.x - di * u0.y;
+            g0.y -= dr * u0.y + di * u0.x;
+            g1.x -= dr * u1.x - di * u1.y;
+            g1.y -= dr * u1.y + di * u1.x;
+            if (h0) g[lane] = g0;
+            if (h1) g[lane + 64] = g1;
         }
-        double acc = 0.0;
-        for (int r = lane; r < rows; r += 64) {
-            const double2 w = u[r];
-            double2 v = g[r];
-            v.x -= dr * w.x - di * w.y;
-            v.y -= dr * w.y + di * w.x;
-            g[r] = v;
-            acc = fma(v.x, v.x, fma(v.y, v.y, acc));
-        }
-        a = wave_sum64(acc);
+        a = wave_sum64(fma(g0.x, g0.x, fma(g0.y, g0.y, fma(g1.x, g1.x, g1.y * g1.y))));
         if (lane == 0) nrm[col] = a;
     }
     gcol_block_best(a, col, part_v, part_i);
@@ -1018,6 +1018,55 @@ __global__ void cadd_kernel(double2 *__restrict__ y, const double2 *__restrict__
     y[r + q * ldy].y += x[r + q * ldx].y;
 }
 
+// C = s_c C + s_w sum_q W_q (m x n; C with leading dimension ldc, the W_q
+// packed m x n one after another); s_c, s_w real
+__global__ void sum_slices_kernel(double2 *__restrict__ C, int64_t ldc, const double2 *__restrict__ W, int m,
+                                  int n, int nsl, double s_c, double s_w) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)m * n) return;
+    const int r = (int)(t % m);
+    const int64_t q = t / m;
+    double2 a = make_double2(0.0, 0.0);
+    for (int sl = 0; sl < nsl; ++sl) {   // fixed order: reproducible
+        const double2 w = W[(int64_t)sl * m * n + t];
+        a.x += w.x;
+        a.y += w.y;
+    }
+    double2 *c = C + r + q * ldc;
+    const double2 c0 = s_c != 0.0 ? *c : make_double2(0.0, 0.0);
+    *c = make_double2(s_c * c0.x + s_w * a.x, s_c * c0.y + s_w * a.y);
+}
+
+// C = s_w op(A) B + s_c C (op: none or conjugate transpose; s_w, s_c real)
+// with the inner dimension K split into slices: a strided batch of GEMMs of
+// the slices into W (at most wcap complex entries), then one reduction.  The
+// products here have small outputs (64 x 64 Gram matrices, j0 x 64 and
+// ell x 64 projections) and long inner dimensions, which one GEMM runs on a
+// few workgroups, each down the whole of K.
+static void gemm_splitk(Ctx &c, rocblas_handle h, rocblas_operation opA, int m, int n, int K, double s_w,
+                        const double2 *A, int lda, const double2 *B, int ldb, double s_c, double2 *C, int ldc,
+                        double2 *W, int64_t wcap) {
+    const int64_t tiles = ceil_div((int64_t)m, (int64_t)64) * ceil_div((int64_t)n, (int64_t)64);
+    int nsl = (int)std::min<int64_t>(std::max<int64_t>(1, 512 / tiles), K / 64);
+    nsl = (int)std::min<int64_t>(nsl, wcap / ((int64_t)m * n));
+    const rocblas_double_complex w = {s_w, 0.0}, cc0 = {s_c, 0.0}, one = {1.0, 0.0}, zero = {0.0, 0.0};
+    if (nsl < 2) {
+        AXS_BLAS(rocblas_zgemm(h, opA, rocblas_operation_none, m, n, K, &w, zc(A), lda, zc(B), ldb, &cc0, zc(C), ldc));
+        return;
+    }
+    const int sl = (K + nsl - 1) / nsl;
+    const int full = K / sl, rem = K - full * sl;
+    const rocblas_stride sa = opA == rocblas_operation_none ? (rocblas_stride)sl * lda : (rocblas_stride)sl;
+    AXS_BLAS(rocblas_zgemm_strided_batched(h, opA, rocblas_operation_none, m, n, sl, &one, zc(A), lda, sa, zc(B), ldb,
+                                           (rocblas_stride)sl, &zero, zc(W), m, (rocblas_stride)m * n, full));
+    if (rem > 0)
+        AXS_BLAS(rocblas_zgemm(h, opA, rocblas_operation_none, m, n, rem, &one, zc(A + full * sa), lda,
+                               zc(B + (int64_t)full * sl), ldb, &zero, zc(W + (int64_t)full * m * n), m));
+    hipLaunchKernelGGL(sum_slices_kernel, dim3(ceil_div((int64_t)m * n, 256)), dim3(256), 0, c.stream, C,
+                       (int64_t)ldc, W, m, n, full + (rem > 0 ? 1 : 0), s_c, s_w);
+    AXS_HIP(hipGetLastError());
+}
+
 // QR with randomized column pivoting of A (ell x n, leading dimension ell),
 // blocks of 64 pivots, until |R_kk| < eps |R_00|; returns k and the column
 // order perm (perm[q] = original column at position q).  Rm (ell x n, leading
@@ -1038,6 +1087,7 @@ __global__ void cadd_kernel(double2 *__restrict__ y, const double2 *__restrict__
 static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int64_t n, double eps, uint64_t seed,
                  std::vector<int> &perm, std::vector<double> &diag) {
     constexpr int BMAX = 64, P = 16, YR = BMAX + P;
+    static_assert(YR <= 128, "gcol_step_kernel holds a sketch column in two entries per lane");
     const int kmax = (int)std::min<int64_t>(ell, n);
     perm.resize(n);
     std::iota(perm.begin(), perm.end(), 0);
@@ -1060,6 +1110,8 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
     double2 *W = (double2 *)c.dalloc(4 * BMAX * BMAX * sizeof(double2));
     double2 *R1 = W + BMAX * BMAX, *R2 = R1 + BMAX * BMAX, *Rp = R2 + BMAX * BMAX;
     double2 *S = (double2 *)c.dalloc((size_t)ell * BMAX * sizeof(double2));
+    const int64_t wkcap = (int64_t)ell * BMAX * 8;   // split-K partial products
+    double2 *Wk = (double2 *)c.dalloc((size_t)wkcap * sizeof(double2));
     const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0}, mone = {-1.0, 0.0};
     // Y = Omega A
     hipLaunchKernelGGL(gauss_fill_kernel, dim3(ceil_div((int64_t)YR * ell, 256)), dim3(256), 0, c.stream, Om, YR,
@@ -1143,20 +1195,19 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
             if (pass == 0 && j0 > 0) {
                 // project against Q = A[:, 0:j0]: first with the known R rows
                 // (Q^H of the raw columns), then recomputed (reorthogonalisation)
-                AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, ell, b, j0, &mone, zc(A),
-                                       ell, zc(Rcol), ell, &one, zc(Pn), ell));
-                AXS_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, j0, b, ell,
-                                       &one, zc(A), ell, zc(Pn), ell, &zero, zc(S), j0));
-                AXS_BLAS(rocblas_zgemm(h, rocblas_operation_none, rocblas_operation_none, ell, b, j0, &mone, zc(A),
-                                       ell, zc(S), j0, &one, zc(Pn), ell));
+                gemm_splitk(c, h, rocblas_operation_none, ell, b, j0, -1.0, A, ell, Rcol, ell, 1.0, Pn, ell, Wk,
+                            wkcap);
+                gemm_splitk(c, h, rocblas_operation_conjugate_transpose, j0, b, ell, 1.0, A, ell, Pn, ell, 0.0, S,
+                            j0, Wk, wkcap);
+                gemm_splitk(c, h, rocblas_operation_none, ell, b, j0, -1.0, A, ell, S, j0, 1.0, Pn, ell, Wk, wkcap);
                 hipLaunchKernelGGL(cadd_kernel, dim3(ceil_div((int64_t)j0 * b, 256)), dim3(256), 0, c.stream, Rcol,
                                    S, j0, (int64_t)b, (int64_t)ell, (int64_t)j0);
                 AXS_HIP(hipGetLastError());
             }
             // CholeskyQR2 of the projected panel: Pn = Q Rp, Q in place of Pn
             double2 *Rk = pass == 0 ? R1 : R2;
-            AXS_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, b, b, ell, &one,
-                                   zc(Pn), ell, zc(Pn), ell, &zero, zc(W), b));
+            gemm_splitk(c, h, rocblas_operation_conjugate_transpose, b, b, ell, 1.0, Pn, ell, Pn, ell, 0.0, W, b, Wk,
+                        wkcap);
             hipLaunchKernelGGL(chol_small_kernel, dim3(1), dim3(64), 0, c.stream, W, b, Rk, dinfo);
             AXS_HIP(hipGetLastError());
             int info = 0;
@@ -1220,7 +1271,7 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
     if (k < 0) k = kmax;
     for (void *q : {(void *)Om, (void *)Y, (void *)G, (void *)nrm, (void *)part_v, (void *)part_i, (void *)dpiv,
                     (void *)dnu2, (void *)tmp,
-                    (void *)rawA, (void *)rawR, (void *)mv, (void *)W, (void *)S})
+                    (void *)rawA, (void *)rawR, (void *)mv, (void *)W, (void *)S, (void *)Wk})
         c.dfree(q);
     return k;
 }
