@@ -200,7 +200,7 @@ def test_fullsize_point_id_interpolates_unseen_fields(lattice):
     fields it never saw, computed here from their definitions: point sources
     outside its proxy sphere (incoming; the ID must reproduce u from u(I)) and
     a random density's field at far targets (outgoing; A_far X^T sigma on the
-    skeleton nodes).  Both to 5e-8 (2.1e-9 and 2.6e-9 seen)."""
+    skeleton nodes).  Both to 5e-8 (1.9e-9 and 2.3e-9 seen)."""
     wl, S, ctx = lattice
     ctx.skeletonize_points(1e-10, 2.0, 0, 1)
     nodes = ctx.skeleton_nodes(0)

@@ -218,7 +218,7 @@ def test_point_skeleton_batched_solve_on_mixed_bodies(nrhs):
     group of 16 rhs) and with 5 (the point order; groups of 4, the second one
     partly filled): every lifted density close to the full FP64 solution and
     with a certified full-system residual, at eps = 1e-10: both within 5e-9
-    (4.3e-10 and 4.0e-10 seen with 16 rhs; 13,862 of 59,130 unknowns stay,
+    (3.1e-10 and 3.2e-10 seen with 16 rhs; 13,970 of 59,130 unknowns stay,
     against 42,444 with ring skeletons at 1e-8)."""
     from paper_1406_0236_amd import SOLVE_FP64, SOLVE_MIXED
     from workloads import configs
