@@ -6,9 +6,11 @@
 //     s~ + S B~ s~ = -v~,   S_p = V_p^* A_pp^{-1} U_p,   v~_p = V_p^* A_pp^{-1} v_p,
 // and lifts the result back with s_p = -A_pp^{-1} (v_p + U_p sum_q A~_pq s~_q).
 //
-// For bodies of revolution the skeletons here are whole rings (contour nodes
-// with all their azimuthal nodes): U_p = X (x) I and V_p^* = X^T (x) I with one
-// NG x k matrix X per shape acting on the contour index.  Then
+// Two versions.  Point skeletons (single nodes from a randomized ID, as the
+// paper prints it) are in the second half of this file.  Ring skeletons keep
+// whole rings (contour nodes with all their azimuthal nodes): U_p = X (x) I
+// and V_p^* = X^T (x) I with one NG x k matrix X per shape acting on the
+// contour index.  Then
 //   - B~ is the inter-body sum over the skeleton rings: the ring-order kernels
 //     run on it unchanged;
 //   - S_p is block diagonal in the Fourier modes, S~_m = X^T S_m X (k x k):
@@ -650,18 +652,22 @@ void skel_prolong(Ctx &c, const void *w, const void *add, void *out, int nrhs) {
 // so A[s, (i, l)] = sum_m e^{-i m theta_l} W_m[s, i],  W_m = Psi_m conj(H_|m|)^T:
 // 2M+1 GEMMs of ell x C' x NG and one DFT GEMM per contour node.  The columns
 // of A (= nodes) are chosen by QR with randomized column pivoting in blocks
-// of 64 (as in Martinsson, Quintana-Orti, Heavner and van de Geijn's HQRRP:
-// per block, pivoted Gram-Schmidt on the device on an 80-row Gaussian sketch
-// of the trailing columns), each block orthonormalised by CholeskyQR2 and the
-// trailing columns projected against it twice, so that the dense work is
-// GEMMs; the rank k is the first pivot with |R_kk| < eps |R_00|, and
-// X(J, :) = (R_11^{-1} R_12)^* as in the ring version.  The sketch width ell
-// starts at 256 and grows (by the decay of |R_jj| seen so far) until
-// k <= ell - 16.  Then
+// of 64 (as in Martinsson, Quintana-Orti, Heavner and van de Geijn's HQRRP),
+// left-looking: one 80-row Gaussian sketch of A, downdated after each block,
+// chooses the pivots (pivoted Gram-Schmidt on the device); each panel is
+// projected against the earlier blocks and orthonormalised by CholeskyQR2,
+// and its rows of R_12 are one GEMM over the trailing columns, which are never
+// updated (see hqrrp); the rank k is the first pivot with |R_kk| < eps
+// |R_00|, and X(J, :) = (R_11^{-1} R_12)^* as in the ring version.  The sketch
+// width ell starts at 256 (for later shapes at 1.25 k + 64 of the shape
+// before) and grows (by the decay of |R_jj| seen so far) until k <= ell - 16.
+// Then
 //   S_p = X^T A_pp^{-1} X  (k x k, dense) from per-mode products with S_m,
-//   B~ the point-order inter-body sum over the skeleton nodes,
+//   B~ the inter-body sum over the skeleton nodes (point order; MFMA orders
+//   from 16 rhs),
 // and the compressed system runs in a child context whose operator is
-// s~ + S B~ s~ (S_p applied by one batched GEMM per run of bodies of a shape).
+// s~ + S B~ s~ (S_p applied per body by body_matvec_kernel, all bodies in one
+// launch).
 #define AXS_BLAS(call)                                                                                      \
     do {                                                                                                    \
         rocblas_status st_ = (call);                                                                        \
