@@ -693,8 +693,6 @@ void destroy_blas(Ctx &c) {
 
 static inline rocblas_double_complex *zc(double2 *p) { return (rocblas_double_complex *)p; }
 static inline const rocblas_double_complex *zc(const double2 *p) { return (const rocblas_double_complex *)p; }
-static inline rocblas_float_complex *cc(float2 *p) { return (rocblas_float_complex *)p; }
-static inline const rocblas_float_complex *cc(const float2 *p) { return (const rocblas_float_complex *)p; }
 
 // the counter-based generator of the sketch: SplitMix64 (Steele, Lea and
 // Flood) of seed * 0x632BE59BD9B4E019 + counter, top 53 bits centred in their
@@ -776,14 +774,6 @@ __global__ void assemble_xt_kernel(const double2 *__restrict__ A, int64_t ld, co
 __global__ void to_c64_kernel(const double2 *__restrict__ a, int64_t n, float2 *__restrict__ b) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) b[t] = make_float2((float)a[t].x, (float)a[t].y);
-}
-
-__global__ void add_c64_kernel(double2 *__restrict__ y, const float2 *__restrict__ a, int64_t n) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) {
-        y[t].x += (double)a[t].x;
-        y[t].y += (double)a[t].y;
-    }
 }
 
 // node arrays of the skeleton: rows of the parent's [7][N] FP64 arrays
