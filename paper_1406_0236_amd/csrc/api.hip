@@ -172,6 +172,7 @@ void apply_precond(Ctx &c, const void *x, void *y, int nrhs, int prec, double be
 static void precompute_all(Ctx &c) {
     AXS_REQUIRE(!c.bodies.empty(), AXS_ESTATE, "no bodies");
     for (auto &s : c.shapes) precompute_shape(c, s);
+    invert_shapes(c);
     finish_precompute(c);
 }
 

@@ -292,7 +292,8 @@ struct Skeleton {
 // launches (defined in the .hip files)
 // ---------------------------------------------------------------------------
 // setup.hip
-void precompute_shape(Ctx &c, Shape &s);
+void precompute_shape(Ctx &c, Shape &s);   // A~_m of one shape
+void invert_shapes(Ctx &c);                 // S_m = A~_m^{-1} of every shape
 void gauss_legendre_rule(int n, std::vector<double> &x, std::vector<double> &w);
 // k^G_m w (m = 0..M) for arbitrary (target ring, source ring) pairs: host arrays
 // pts[7][P] = (r_t, r_s, r_s - r_t, z_s - z_t, n_r, n_z of the source, weight);

@@ -385,16 +385,22 @@ __global__ void add_half_identity_kernel(double2 *A, int M, int NG) {
     A[((int64_t)m * NG + i) * NG + i].x += 0.5;
 }
 
-// Gauss-Jordan inverse with partial pivoting (ties -> lowest row), one block per matrix.
+// Gauss-Jordan inverse with partial pivoting (ties -> lowest row), one block
+// per matrix; the matrices of every shape (all modes) in one launch.
+struct GJItem {
+    const double2 *A;   // NG x NG, row-major
+    double2 *work;      // NG x 2 NG
+    double2 *S;         // NG x NG, row-major: A^{-1}
+    int NG, pad;
+};
 template <int BS>
-__global__ __launch_bounds__(BS) void gauss_jordan_kernel(const double2 *__restrict__ A, int NG,
-                                                          double2 *__restrict__ work,
-                                                          double2 *__restrict__ S) {
-    const int m = blockIdx.x;
+__global__ __launch_bounds__(BS) void gauss_jordan_kernel(const GJItem *__restrict__ items) {
+    const GJItem it = items[blockIdx.x];
+    const int NG = it.NG;
     const int W = 2 * NG;
-    const double2 *a = A + (int64_t)m * NG * NG;
-    double2 *g = work + (int64_t)m * NG * W;
-    double2 *s = S + (int64_t)m * NG * NG;
+    const double2 *a = it.A;
+    double2 *g = it.work;
+    double2 *s = it.S;
     __shared__ double rmax[BS];
     __shared__ int ridx[BS];
     __shared__ double2 piv_inv;
@@ -706,17 +712,52 @@ void precompute_shape(Ctx &c, Shape &s) {
     hipLaunchKernelGGL(add_half_identity_kernel, dim3(ceil_div((M + 1) * NG, 256)), dim3(256), 0, c.stream, A,
                        M, NG);
     AXS_HIP(hipGetLastError());
-    // inverses
-    double2 *S = (double2 *)c.dalloc(nmat * sizeof(double2));
-    double2 *work = (double2 *)c.scratch(WS_TMP, (size_t)(M + 1) * NG * 2 * NG * sizeof(double2));
-    hipLaunchKernelGGL(gauss_jordan_kernel<256>, dim3(M + 1), dim3(256), NG * sizeof(double2), c.stream, A, NG,
-                       work, S);
-    AXS_HIP(hipGetLastError());
-    s.S64 = (double *)S;
-    AXS_HIP(hipStreamSynchronize(c.stream));
+    AXS_HIP(hipStreamSynchronize(c.stream));   // the inverses follow for all shapes at once
     for (void *ptr : {(void *)d_sn, (void *)d_lden, (void *)d_gu, (void *)d_gw, (void *)d_r, (void *)d_z,
                       (void *)d_nr, (void *)d_nz, (void *)d_aw})
         c.dfree(ptr);
+}
+
+// S_m = A~_m^{-1} for every shape and mode: one Gauss-Jordan launch over all
+// the matrices (per shape only M + 1 workgroups would run), in groups whose
+// work arrays (NG x 2 NG per matrix) stay within 4 GiB
+void invert_shapes(Ctx &c) {
+    constexpr size_t WORK_CAP = (size_t)4 << 30;
+    size_t k = 0;
+    while (k < c.shapes.size()) {
+        size_t k1 = k, bytes = 0;
+        int maxNG = 0;
+        while (k1 < c.shapes.size()) {
+            const Shape &s = c.shapes[k1];
+            const size_t b = (size_t)(s.M + 1) * s.NG * 2 * s.NG * sizeof(double2);
+            if (k1 > k && bytes + b > WORK_CAP) break;
+            bytes += b;
+            maxNG = std::max(maxNG, s.NG);
+            ++k1;
+        }
+        double2 *work = (double2 *)c.dalloc(bytes);
+        std::vector<GJItem> items;
+        size_t off = 0;
+        for (size_t q = k; q < k1; ++q) {
+            Shape &s = c.shapes[q];
+            const int64_t nn = (int64_t)s.NG * s.NG;
+            double2 *S = (double2 *)c.dalloc((size_t)(s.M + 1) * nn * sizeof(double2));
+            s.S64 = (double *)S;
+            for (int m = 0; m <= s.M; ++m) {
+                items.push_back(GJItem{(const double2 *)s.A64 + m * nn, work + off, S + m * nn, s.NG, 0});
+                off += (size_t)2 * nn;
+            }
+        }
+        GJItem *d_items = (GJItem *)c.dalloc(items.size() * sizeof(GJItem));
+        AXS_HIP(hipMemcpy(d_items, items.data(), items.size() * sizeof(GJItem), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(gauss_jordan_kernel<256>, dim3((unsigned)items.size()), dim3(256),
+                           maxNG * sizeof(double2), c.stream, d_items);
+        AXS_HIP(hipGetLastError());
+        AXS_HIP(hipStreamSynchronize(c.stream));
+        c.dfree(d_items);
+        c.dfree(work);
+        k = k1;
+    }
 }
 
 void modal_values(Ctx &c, double kappa, double gam_re, double gam_im, int M, int Nt,
