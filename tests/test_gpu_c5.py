@@ -161,7 +161,7 @@ def test_c5_point_skeleton_solve_certified(many):
     """The same 16 plane waves through point skeletons (Sec. 5; one randomized
     ID per body shape, 23 shapes; proxy radii limited by the neighbours at
     gaps of 0.5) at eps 1e-10: fewer than a fifth of the unknowns stay
-    (234,206 of 1,351,890 seen), and the lifted densities' residual in the full
+    (233,797 of 1,351,890 seen), and the lifted densities' residual in the full
     system -- the FP64 operator on every row, whose rows the sampled-row test
     above pins to the reference -- is below 1e-7 for every rhs (3.0e-8 seen).
     After the certified mixed solve, the lifted densities also agree with its
