@@ -48,7 +48,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
 # source they were taken on (source_fingerprint: code, not comments).
 TRAFFIC_BYTES = 115.16e6
-TRAFFIC_SOURCE_SHA = "b694b1ce76a9af15"
+TRAFFIC_SOURCE_SHA = "6c5270ae362bd37b"
 
 
 def source_fingerprint(path):

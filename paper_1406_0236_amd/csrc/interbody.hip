@@ -516,8 +516,20 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
                     beta[k] = fma(-kap, al[k], fma(nzj, pzp, -nrj * rj) * c1);
                 }
                 if constexpr (FOLD) {
+                    // entry 0 is azimuth 0 (cos 1, sin 0), which has no mirror: one pair
+                    {
+                        const R cl = src[0];
+                        R qv[6];
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) qv[i] = src[2 + i];
+#pragma unroll
+                        for (int k = 0; k < TPT; ++k) {
+                            const R ra = fma(Ax[k], cl, al[k]);
+                            ring_term1<R>(ra, fma(kap, ra, beta[k]), n0, s_tab, qv, ar[k][0], ai[k][0]);
+                        }
+                    }
 #pragma unroll 1
-                    for (int l = 0; l < ne; ++l) {
+                    for (int l = 1; l < ne; ++l) {
                         const R *s = src + l * ST;
                         const R cl = s[0], sl = s[1];
                         R qv[6], mv[6];
