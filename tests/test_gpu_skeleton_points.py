@@ -210,12 +210,13 @@ def test_point_skeleton_counts_bracket_the_papers():
             ctx.close()
 
 
-@pytest.mark.parametrize("nrhs", [16, 5])
+@pytest.mark.parametrize("nrhs", [16, 9, 5, 2])
 def test_point_skeleton_batched_solve_on_mixed_bodies(nrhs):
     """Point skeletons of the 8 mixed bodies (three shapes in runs of one to
     three bodies; kappa = 2 pi, discretised for 4 pi) with 16 right-hand sides
     (the MFMA order over the skeleton nodes, the per-body products in one
-    group of 16 rhs) and with 5 (the point order; groups of 4, the second one
+    group of 16 rhs) and with 9, 5 and 2 (the point order; the per-body
+    products in groups of 8, 4 and 2 rhs, the second group of 9 and of 5
     partly filled): every lifted density close to the full FP64 solution and
     with a certified full-system residual, at eps = 1e-10: both within 5e-9
     (3.1e-10 and 3.2e-10 seen with 16 rhs; 13,970 of 59,130 unknowns stay,
