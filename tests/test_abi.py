@@ -111,3 +111,19 @@ def test_package_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dp, f)).read()
                 assert "oracle" not in re.sub(r"#.*|//.*", "", text), f
+
+
+def test_traffic_figure_belongs_to_the_current_kernel_source():
+    """bench.py reports the FP32 inter-body kernel's measured HBM bytes only
+    for the kernel source they were taken on; the profile that holds them
+    names the same fingerprint, so a change of the kernel's code shows here
+    until its counter passes are taken again."""
+    import bench
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sha = bench.source_fingerprint(os.path.join(root, "paper_1406_0236_amd", "csrc", "interbody.hip"))
+    assert sha == bench.TRAFFIC_SOURCE_SHA
+    with open(os.path.join(root, "profiles", "interbody_sphere_lattice_27_k4pi_pmc.md")) as f:
+        text = f.read()
+    assert f"`{sha}`" in text
+    mb = float(re.search(r"\*\*([0-9.]+) MB\*\*", text).group(1))
+    assert abs(mb * 1e6 - bench.TRAFFIC_BYTES) < 0.1e6
