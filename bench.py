@@ -48,7 +48,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # (profiles/interbody_sphere_lattice_27_k4pi_pmc.md); valid only for the kernel
 # source they were taken on (source_fingerprint: code, not comments).
 TRAFFIC_BYTES = 115.16e6
-TRAFFIC_SOURCE_SHA = "6c5270ae362bd37b"
+TRAFFIC_SOURCE_SHA = "c2b78089b674c037"
 
 
 def source_fingerprint(path):

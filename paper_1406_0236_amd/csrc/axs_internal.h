@@ -180,7 +180,7 @@ struct Ctx {
     int64_t nblk = 0;
     int mf16_gexp = 0;
     bool mf16_ok = false;
-    double2 *sctab = nullptr;            // [256]: (cos, sin)(2 pi k / 256) for the FP64 sin/cos
+    double2 *sctab = nullptr;            // [1024]: (cos, sin)(2 pi k / 1024) for the FP64 sin/cos
     // every body's diameter is under 127 wavelengths, so the phase less the
     // per-(wavefront, source body) whole revolutions floor(min (|p| - r_b) k/2pi)
     // stays inside the hardware sin/cos input range (ring and MFMA orders rely on it)

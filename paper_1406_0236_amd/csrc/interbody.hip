@@ -15,7 +15,7 @@
 //   - FP32 path: the phase in revolutions, less whole revolutions per
 //     (wavefront, source body), fed to the hardware sin/cos (which take
 //     revolutions and reduce up to 256 of them), 1/R from v_rsq;
-//   - FP64 path: the same structure with sin/cos from a 256-entry LDS table
+//   - FP64 path: the same structure with sin/cos from a 1024-entry LDS table
 //     and short polynomials, and a Newton-refined hardware 1/sqrt.
 // Two source orders ("variants") compute the same sum:
 //   - points: each staged source carries x, y, z, n and q (with one
@@ -48,27 +48,33 @@ __device__ __forceinline__ void sincos_rev_near(float ph, float &s, float &c) {
     c = __builtin_amdgcn_cosf(ph);
 }
 
-// sin and cos of 2 pi t in FP64 for |t| < 2^40 revolutions, with a 256-entry
-// table of (cos, sin)(2 pi j / 256) held in LDS:
-//   y = t + 1.5 * 2^44 (one add; the sum has an ulp of 1/256) rounds t to the
-//   nearest multiple j / 256, and the low word of y is j, which indexes the
-//   table; y - 1.5 * 2^44 is j / 256 exactly, and so is r = t - j / 256, in
-//   [-1/512, 1/512];
-//   with x = 2 pi r: sin x to x^5 and cos x to x^6 (truncation below 1e-17)
-//   as polynomials in r (Taylor coefficients times powers of 2 pi);
+// sin and cos of 2 pi t in FP64 for |t| < 2^40 revolutions, with a 1024-entry
+// table of (cos, sin)(2 pi j / 1024) held in LDS:
+//   y = t + 1.5 * 2^42 (one add; the sum has an ulp of 1/1024) rounds t to the
+//   nearest multiple j / 1024, and the low word of y is j, which indexes the
+//   table; y - 1.5 * 2^42 is j / 1024 exactly, and so is r = t - j / 1024, in
+//   [-1/2048, 1/2048];
+//   with x = 2 pi r, |x| <= h = pi / 1024: cos x to x^4 (Taylor; the first
+//   dropped term below 1.2e-18) and sin x to x^3, with the x^5 term of its
+//   Taylor series economised into x and x^3 by the Chebyshev polynomial T5 on
+//   [-h, h] (x^5 ~ (5/4) h^2 x^3 - (5/16) h^4 x, error h^5 / 16 there), so the
+//   truncation stays below h^5 / 1920 + h^7 / 5040 = 1.5e-16; both as
+//   polynomials in r (coefficients times powers of 2 pi);
 //   then the angle sum with the table entry.
-constexpr double SC_MAGIC = 26388279066624.0;   // 1.5 * 2^44
+constexpr int SC_N = 1024;
+constexpr double SC_MAGIC = 6597069766656.0;   // 1.5 * 2^42
 constexpr double SC_A = 6.283185307179586476925287;
-constexpr double SC_S1 = SC_A, SC_S3 = -SC_A * SC_A * SC_A / 6.0, SC_S5 = SC_A * SC_A * SC_A * SC_A * SC_A / 120.0;
-constexpr double SC_C2 = -SC_A * SC_A / 2.0, SC_C4 = SC_A * SC_A * SC_A * SC_A / 24.0,
-                 SC_C6 = -SC_A * SC_A * SC_A * SC_A * SC_A * SC_A / 720.0;
+constexpr double SC_H = SC_A / (2 * SC_N);
+constexpr double SC_S1 = SC_A * (1.0 - SC_H * SC_H * SC_H * SC_H / 384.0),
+                 SC_S3 = SC_A * SC_A * SC_A * (-1.0 / 6.0 + SC_H * SC_H / 96.0);
+constexpr double SC_C2 = -SC_A * SC_A / 2.0, SC_C4 = SC_A * SC_A * SC_A * SC_A / 24.0;
 __device__ __forceinline__ void sincos_rev_tab(double t, const double2 *tab, double &s, double &c) {
     const double y = t + SC_MAGIC;
     const double r = t - (y - SC_MAGIC);          // exact
     const double r2 = r * r;
-    const double sx = r * fma(r2, fma(r2, SC_S5, SC_S3), SC_S1);
-    const double cx = fma(r2, fma(r2, fma(r2, SC_C6, SC_C4), SC_C2), 1.0);
-    const double2 e = tab[__double2loint(y) & 255];   // (cos, sin)(2 pi j / 256)
+    const double sx = r * fma(r2, SC_S3, SC_S1);
+    const double cx = fma(r2, fma(r2, SC_C4, SC_C2), 1.0);
+    const double2 e = tab[__double2loint(y) & (SC_N - 1)];   // (cos, sin)(2 pi j / 1024)
     s = fma(e.y, cx, e.x * sx);
     c = fma(e.x, cx, -e.y * sx);
 }
@@ -81,8 +87,8 @@ __device__ __forceinline__ void sincos_any(double t, const double2 *tab, double 
 // phase in revolutions).  FP32: the hardware sin/cos of R' - n0, n0 the whole
 // revolutions of the (wavefront, source body), which keeps the argument in
 // their input range.  FP64: as sincos_rev_tab, with the product r2 u rounded
-// to the table's 1/256 steps inside one FMA, y = r2 u + 1.5 * 2^44, and the
-// remainder r = r2 u - J, J = y - 1.5 * 2^44, formed by a second FMA, so the
+// to the table's 1/1024 steps inside one FMA, y = r2 u + 1.5 * 2^42, and the
+// remainder r = r2 u - J, J = y - 1.5 * 2^42, formed by a second FMA, so the
 // remainder carries the product's full precision (R' < 2^40 revolutions).
 __device__ __forceinline__ void sincos_phase(float r2, float u, float n0, const double2 *, float &s, float &c) {
     sincos_rev_near(fma(r2, u, -n0), s, c);
@@ -91,9 +97,9 @@ __device__ __forceinline__ void sincos_phase(double r2, double u, double, const 
     const double y = fma(r2, u, SC_MAGIC);
     const double r = fma(r2, u, -(y - SC_MAGIC));
     const double rr = r * r;
-    const double sx = r * fma(rr, fma(rr, SC_S5, SC_S3), SC_S1);
-    const double cx = fma(rr, fma(rr, fma(rr, SC_C6, SC_C4), SC_C2), 1.0);
-    const double2 e = tab[__double2loint(y) & 255];   // (cos, sin)(2 pi j / 256)
+    const double sx = r * fma(rr, SC_S3, SC_S1);
+    const double cx = fma(rr, fma(rr, SC_C4, SC_C2), 1.0);
+    const double2 e = tab[__double2loint(y) & (SC_N - 1)];   // (cos, sin)(2 pi j / 1024)
     s = fma(e.y, cx, e.x * sx);
     c = fma(e.x, cx, -e.y * sx);
 }
@@ -101,7 +107,7 @@ __device__ __forceinline__ void sincos_phase(double r2, double u, double, const 
 template <typename R, int BS>
 __device__ __forceinline__ void load_sctab(double2 *dst, const double2 *__restrict__ src) {
     if constexpr (sizeof(R) == 8)
-        for (int i = threadIdx.x; i < 256; i += BS) dst[i] = src[i];
+        for (int i = threadIdx.x; i < SC_N; i += BS) dst[i] = src[i];
 }
 
 // floor(max(min over the wavefront of v, 0)), the same in every lane; in FP32
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(BS) void interbody_kernel(
     constexpr bool FOLD = NR == 1 && !LAP;
     constexpr int ST = SrcStride<R, NR, FOLD>::value;
     __shared__ __align__(16) R tile[BS * ST];
-    __shared__ double2 s_tab[sizeof(R) == 8 ? 256 : 1];
+    __shared__ double2 s_tab[sizeof(R) == 8 ? SC_N : 1];
     load_sctab<R, BS>(s_tab, sctab);
 
     const IBWork w = work[blockIdx.x];
@@ -403,7 +409,7 @@ __global__ __launch_bounds__(BS) void interbody_ring_kernel(
     constexpr int ST = RingStride<R, NR, FOLD>::value;
     constexpr int QB = FOLD ? 8 : 2 + 2 * NR;   // offset of the mirror's densities in an entry
     __shared__ __align__(16) R tile[BS * ST];
-    __shared__ double2 s_tab[sizeof(R) == 8 ? 256 : 1];
+    __shared__ double2 s_tab[sizeof(R) == 8 ? SC_N : 1];
     load_sctab<R, BS>(s_tab, sctab);
 
     const IBWork w = work[blockIdx.x];
@@ -685,7 +691,7 @@ __global__ __launch_bounds__(256) void interbody_mfma_kernel(
     __shared__ V s_sr[CH], s_sn[CH];
     // densities: NR < 16 as [src][c](re, im); NR = 16 as planes re[src][c], im[src][c]
     __shared__ R s_q[CH * 2 * NR];
-    __shared__ double2 s_tab[sizeof(R) == 8 ? 256 : 1];
+    __shared__ double2 s_tab[sizeof(R) == 8 ? SC_N : 1];
     load_sctab<R, 256>(s_tab, sctab);
 
     const IBWork w = work[blockIdx.x];
@@ -1352,11 +1358,11 @@ void build_ring_tables(Ctx &c) {
     up(fr, c.frame64, c.frame32);
     up(csv, c.cs64, c.cs32);
 
-    // (cos, sin)(2 pi k / 256) for the FP64 sin/cos of the inter-body kernels
-    std::vector<double> tab(512);
-    for (int k = 0; k < 256; ++k) {
-        tab[2 * k] = std::cos(2.0 * M_PI * k / 256.0);
-        tab[2 * k + 1] = std::sin(2.0 * M_PI * k / 256.0);
+    // (cos, sin)(2 pi k / 1024) for the FP64 sin/cos of the inter-body kernels
+    std::vector<double> tab(2 * SC_N);
+    for (int k = 0; k < SC_N; ++k) {
+        tab[2 * k] = std::cos(2.0 * M_PI * k / SC_N);
+        tab[2 * k + 1] = std::sin(2.0 * M_PI * k / SC_N);
     }
     c.sctab = (double2 *)c.dalloc(tab.size() * sizeof(double));
     AXS_HIP(hipMemcpy(c.sctab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
