@@ -1041,9 +1041,9 @@ __global__ void sum_slices_kernel(double2 *__restrict__ C, int64_t ldc, const do
 // few workgroups, each down the whole of K.
 static void gemm_splitk(Ctx &c, rocblas_handle h, rocblas_operation opA, int m, int n, int K, double s_w,
                         const double2 *A, int lda, const double2 *B, int ldb, double s_c, double2 *C, int ldc,
-                        double2 *W, int64_t wcap) {
+                        double2 *W, int64_t wcap, int64_t want = 512) {
     const int64_t tiles = ceil_div((int64_t)m, (int64_t)64) * ceil_div((int64_t)n, (int64_t)64);
-    int nsl = (int)std::min<int64_t>(std::max<int64_t>(1, 512 / tiles), K / 64);
+    int nsl = (int)std::min<int64_t>(std::max<int64_t>(1, want / tiles), K / 64);
     nsl = (int)std::min<int64_t>(nsl, wcap / ((int64_t)m * n));
     const rocblas_double_complex w = {s_w, 0.0}, cc0 = {s_c, 0.0}, one = {1.0, 0.0}, zero = {0.0, 0.0};
     if (nsl < 2) {
@@ -1106,7 +1106,9 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
     double2 *W = (double2 *)c.dalloc(4 * BMAX * BMAX * sizeof(double2));
     double2 *R1 = W + BMAX * BMAX, *R2 = R1 + BMAX * BMAX, *Rp = R2 + BMAX * BMAX;
     double2 *S = (double2 *)c.dalloc((size_t)ell * BMAX * sizeof(double2));
-    const int64_t wkcap = (int64_t)ell * BMAX * 8;   // split-K partial products
+    // split-K partial products: 8 slices of the ell x 64 panel products, 4 of
+    // the 64-row R_12 block
+    const int64_t wkcap = std::max<int64_t>((int64_t)ell * 8, n * 4) * BMAX;
     double2 *Wk = (double2 *)c.dalloc((size_t)wkcap * sizeof(double2));
     const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0}, mone = {-1.0, 0.0};
     // Y = Omega A
@@ -1239,9 +1241,10 @@ static int hqrrp(Ctx &c, rocblas_handle h, double2 *A, double2 *Rm, int ell, int
         const int64_t nt = nrem - b;
         if (nt > 0) {
             const int64_t jt = j0 + b;
-            AXS_BLAS(rocblas_zgemm(h, rocblas_operation_conjugate_transpose, rocblas_operation_none, b,
-                                   (rocblas_int)nt, ell, &one, zc(Pn), ell, zc(A + jt * ell), ell, &zero,
-                                   zc(Rm + j0 + jt * ell), ell));
+            // one row of 64 x 64 tiles down an inner dimension of ell: split along
+            // it so that each CU holds several tiles
+            gemm_splitk(c, h, rocblas_operation_conjugate_transpose, b, (int)nt, ell, 1.0, Pn, ell, A + jt * ell, ell,
+                        0.0, Rm + j0 + jt * ell, ell, Wk, wkcap, 1024);
             double2 *Yp = Y + (int64_t)j0 * YR;
             AXS_BLAS(rocblas_ztrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
                                    rocblas_diagonal_non_unit, YR, b, &one, zc(Rp), b, zc(Yp), YR));
