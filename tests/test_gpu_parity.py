@@ -835,9 +835,11 @@ def test_target_body_range_is_one_gpus_share(mixed):
     multiply-accumulate; 5 rhs, ring order).  With the launch shape pinned the
     rows equal the full sum's bit for bit; with the default shape (splits
     chosen for the share) within rounding; the rows against the reference; the
-    solves refuse while the range is set; (0, 0) restores every row."""
+    solves refuse while the range is set, the compressed one included (its
+    certificate applies the full operator); (0, 0) restores every row."""
     from paper_1406_0236_amd import FP32, FP64, SOLVE_MIXED, AxsError
     wl, S, ctx = mixed
+    ctx.skeletonize(1e-8)   # so that the compressed solve fails on the range, not on a missing skeleton
     lo = sum(b.n_nodes for b in wl.bodies[:2])
     hi = sum(b.n_nodes for b in wl.bodies[:5])
     for prec, nrhs, seed in ((FP64, 3, 71), (FP32, 16, 72), (FP32, 5, 73)):
@@ -854,6 +856,9 @@ def test_target_body_range_is_one_gpus_share(mixed):
                 ctx.apply_matvec(x, prec)
             with pytest.raises(AxsError, match="target-body range"):
                 ctx.solve(ctx.incident_plane_waves(wl.dirs[:1]), mode=SOLVE_MIXED, tol=1e-7)
+            with pytest.raises(AxsError, match="target-body range"):
+                ctx.solve_skeleton(ctx.incident_plane_waves(wl.dirs[:1]), mode=SOLVE_MIXED, tol=1e-7,
+                                   certify=True)
         finally:
             ctx.set_target_bodies(0, 0)
         assert np.array_equal(pinned[:, lo:hi], full[:, lo:hi]), (prec, nrhs)
