@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -127,3 +128,12 @@ def test_traffic_figure_belongs_to_the_current_kernel_source():
     assert f"`{sha}`" in text
     mb = float(re.search(r"\*\*([0-9.]+) MB\*\*", text).group(1))
     assert abs(mb * 1e6 - bench.TRAFFIC_BYTES) < 0.1e6
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: --gpus 2 exits with status 2 and says so,
+    before it imports torch or touches a device."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2, (r.returncode, r.stderr)
+    assert "one GPU only" in r.stderr and r.stdout == ""
