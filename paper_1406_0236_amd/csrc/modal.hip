@@ -18,7 +18,6 @@ template <> struct CT<double> { using T = double2; };
 
 constexpr int DFT_GI = 16;     // contour nodes per DFT block
 constexpr int DFT_BS = 256;
-constexpr int MAX_NF = 1023;
 
 __device__ __forceinline__ int64_t xelem(const BodyDev &b, int nrhs, int k, int c, int i) {
     const int m = k <= b.M ? k : k - b.NF;
